@@ -1,0 +1,180 @@
+/*
+ * fhe_mi355x.h -- C ABI of the MI355X (gfx950) library for homomorphic
+ * multiplication in non-RNS CKKS / BGV (HEAAN-style parameterization).
+ *
+ * Representation (Section 4.1 "The Radix Representation", Section 5.1
+ * "Representation Overview"): a polynomial of Z_Q[X]/(X^N+1) with Q = 2^logq is
+ * stored limb-major as uint32[L][N], L = ceil(logq / 32).  Entry [i][j] is the
+ * 32-bit limb i (limb 0 least significant) of coefficient j.  Bits at positions
+ * >= logq must be zero on input and are zero on output.  A ciphertext is two such
+ * polynomials (c0, c1).  A batch of cnum ciphertexts with equal parameters (the
+ * CipherTensor of Section 6.1) is uint32[cnum][L][N] per component, contiguous.
+ *
+ * Ring products (Section 5.1, pipeline summary) lift limbs onto 30-bit
+ * NTT-friendly primes q = 1 (mod 2^17), run negacyclic NTTs (Eq. negacyclic_ntt,
+ * Eq. negacyclic_intt), multiply pointwise (Eq. ntt_mul), and rebuild limbs by
+ * Garner's mixed-radix conversion (Eq. garner_mrc).  All arithmetic is exact.
+ *
+ * Conventions where the paper is silent (the same readings as the CPU oracle):
+ *   - Q_l = 2^logq and the special modulus P = 2^logP; "mod Q_l" keeps logq bits.
+ *   - Relinearization multiplies the representative of d2 in [0, Q_l).
+ *   - CKKS divisions by 2^k round half up: floor((x + 2^(k-1)) / 2^k).
+ *   - BGV divisions by 2^k are t-corrected:
+ *       floor(x / 2^k) + [[ (x mod 2^k) * (2^-k mod t) ]]_t, centered in (-t/2, t/2].
+ *   - Relinearization rounding, then the addition, then the rescale rounding.
+ *
+ * Pointers: "device" pointers are HIP device memory owned by the caller, which must
+ * keep them alive until the work queued on `stream` has completed; "host" pointers
+ * are read before the call returns.  `stream` is a hipStream_t (NULL = default
+ * stream).  Work is queued asynchronously; argument errors are reported
+ * synchronously; a HIP launch or runtime error is returned as FHE_E_DEVICE and kept
+ * as the context's sticky error until fhe_ctx_reset_error.  Inputs must be
+ * canonical; the library does not check the values of device data.
+ *
+ * Thread safety: a context may be used from several host threads, but calls that
+ * share a context serialize on an internal lock; scratch memory is held per
+ * (context, stream), so work on different streams does not alias.
+ */
+#ifndef FHE_MI355X_H
+#define FHE_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status codes */
+#define FHE_OK 0
+#define FHE_E_INVAL (-1)  /* null pointer or argument out of its documented range  */
+#define FHE_E_SHAPE (-2)  /* operands of different N, logq, scheme or t            */
+#define FHE_E_RANGE (-3)  /* beyond the context limits or the key's level          */
+#define FHE_E_NOMEM (-4)  /* device or host allocation failed                      */
+#define FHE_E_DEVICE (-5) /* HIP runtime or launch error (sticky, see above)       */
+#define FHE_E_STATE (-6)  /* object in the wrong state (e.g. destroyed, mismatched) */
+
+#define FHE_CKKS 0
+#define FHE_BGV 1
+
+/* Supported ring degrees: 2^10 <= N <= 2^16 (the prime table has q = 1 mod 2^17). */
+#define FHE_LOGN_MIN 10
+#define FHE_LOGN_MAX 16
+
+typedef struct fhe_ctx fhe_ctx;
+typedef struct fhe_evk fhe_evk;
+
+/* Text for a status code (static storage). */
+const char* fhe_strerror(int status);
+
+/* Create a context on HIP device `device` able to hold ciphertexts with
+ * logq <= logQ_max and keys with logP <= logP_max.  Builds on the device the
+ * tables of Section 5.2 (twiddles psi^j and their inverses, n^-1, the limb
+ * weights 2^(32i) mod q_j, the Garner constants q_i^-1 mod q_j and
+ * M_i = prod_(k<i) q_k), for as many primes as the largest relinearization
+ * product at these limits needs.  *out receives the context (library-owned;
+ * release with fhe_ctx_destroy).  Errors: FHE_E_INVAL (bad limits or null out),
+ * FHE_E_RANGE (limits need more primes than the table holds), FHE_E_NOMEM,
+ * FHE_E_DEVICE. */
+int fhe_ctx_create(int device, int logQ_max, int logP_max, fhe_ctx** out);
+
+/* Destroy a context and every table and scratch buffer it owns (waits for the
+ * device first).  Keys created on it must be destroyed before.  NULL is a no-op. */
+void fhe_ctx_destroy(fhe_ctx* ctx);
+
+/* Return and clear the sticky device error of the context. */
+int fhe_ctx_reset_error(fhe_ctx* ctx);
+
+/* Number of primes in the context's table. */
+int fhe_prime_count(const fhe_ctx* ctx, int* count);
+
+/* Prime `idx` of the table and its primitive 2^17-th root of unity psi (host
+ * outputs).  The transform of size N uses psi^(2^16 / N) (Section 2.3: q = 1 mod
+ * 2N, psi a primitive 2N-th root).  Primes are the largest q < 2^30 with
+ * q = 1 (mod 2^17), in decreasing order; psi = g^((q-1)/2^17) for the smallest
+ * g >= 2 giving an element of order 2^17. */
+int fhe_prime_info(const fhe_ctx* ctx, int idx, uint32_t* q, uint32_t* psi);
+
+/* Number of primes K the library uses for the exact product of two polynomials
+ * of degree < N with coefficients in [0, 2^bits_a) and [0, 2^bits_b), summed over
+ * `terms` products: the smallest K with prod_(i<K) q_i > 2^(e+1), where
+ * e = bits_a + bits_b + logN + ceil(log2(terms)).  (Host output.) */
+int fhe_primes_needed(const fhe_ctx* ctx, int logN, int bits_a, int bits_b, int terms, int* K);
+
+/* Limb -> RNS projection (Section 5.1 "Limb-to-RNS Conversion"): for each of
+ * `count` polynomials, res[c][p][j] = A_j mod q_p for primes p < nprimes, where A_j
+ * is coefficient j of limbs[c] (uint32[count][L][N], device) and res is
+ * uint32[count][nprimes][N] (device).  Errors: FHE_E_INVAL, FHE_E_RANGE. */
+int fhe_lift(fhe_ctx* ctx, int logN, int L, int nprimes, const uint32_t* limbs,
+             uint32_t* res, int count, void* stream);
+
+/* Standalone negacyclic NTT over primes 0..nprimes-1, in place on
+ * data = uint32[count][nprimes][N] (device), values in [0, q_p).
+ * inverse = 0: Eq. negacyclic_ntt, output in bit-reversed order: position r holds
+ *              abar_i with r = bitrev_(logN)(i).
+ * inverse = 1: Eq. negacyclic_intt, input in that bit-reversed order, natural-order
+ *              output.
+ * Errors: FHE_E_INVAL, FHE_E_RANGE (logN outside [10, 16], too many primes). */
+int fhe_ntt(fhe_ctx* ctx, int logN, int nprimes, int inverse, uint32_t* data, int count,
+            void* stream);
+
+/* Ring multiply (Section 2.3, Eq. schoolbook then Eq. reduction, mod Q = 2^logq):
+ * c[i] = a[i] * b[i] in Z_(2^logq)[X]/(X^N+1) for i < cnum.  a, b, c are device
+ * uint32[cnum][L][N]; c may alias a or b.  Errors: FHE_E_INVAL, FHE_E_RANGE,
+ * FHE_E_NOMEM, FHE_E_DEVICE. */
+int fhe_ring_mul(fhe_ctx* ctx, int logN, int logq, const uint32_t* a, const uint32_t* b,
+                 uint32_t* c, int cnum, void* stream);
+
+/* Upload a relinearization key (b', a') (Section 6.2 "Cryptographic Key
+ * Management": relinearization keys) given at modulus P * 2^logQ_key:
+ * b_host, a_host are host uint32[L_PQ][N], L_PQ = ceil((logP + logQ_key) / 32).
+ * The library keeps the limbs on the device and, per ciphertext level logq used
+ * with it, the NTT form of the key reduced mod P * 2^logq (built on first use or by
+ * fhe_evk_prepare).  *out is library-owned; release with fhe_evk_destroy.
+ * scheme is FHE_CKKS or FHE_BGV; t (odd, 3 <= t < 2^31) is read for BGV only.
+ * Errors: FHE_E_INVAL, FHE_E_RANGE (logQ_key > logQ_max or logP > logP_max),
+ * FHE_E_NOMEM, FHE_E_DEVICE. */
+int fhe_evk_create(fhe_ctx* ctx, int scheme, uint32_t t, int logN, int logQ_key, int logP,
+                   const uint32_t* b_host, const uint32_t* a_host, fhe_evk** out);
+
+/* Build (if not yet built) the resident NTT form of the key for level logq. */
+int fhe_evk_prepare(fhe_evk* evk, int logq, void* stream);
+
+/* Release a key and its device memory (waits for the device).  NULL is a no-op. */
+void fhe_evk_destroy(fhe_evk* evk);
+
+/* Homomorphic multiplication with relinearization (the HE-mult of Section 6.2,
+ * "multiplication followed by relinearization"; Karatsuba-equivalent tensor of
+ * Section 5.4): for each i < cnum,
+ *   d0 = x0 y0, d1 = x0 y1 + x1 y0, d2 = x1 y1            (mod Q_l = 2^logq)
+ *   k0 = d2 b', k1 = d2 a'                                (mod P Q_l)
+ *   out0 = [d0 + R(k0)]_(Q_l), out1 = [d1 + R(k1)]_(Q_l)
+ * with R the CKKS or BGV division by P of the header notes.  x0, x1, y0, y1,
+ * out0, out1 are device uint32[cnum][L][N]; outputs must not alias inputs.
+ * Metadata (logp adds, BGV gamma multiplies) is the caller's.
+ * Errors: FHE_E_INVAL, FHE_E_SHAPE (logN differs from the key's),
+ * FHE_E_RANGE (logq > key level), FHE_E_NOMEM, FHE_E_DEVICE. */
+int fhe_mul_relin(fhe_ctx* ctx, fhe_evk* evk, int logN, int logq, const uint32_t* x0,
+                  const uint32_t* x1, const uint32_t* y0, const uint32_t* y1, uint32_t* out0,
+                  uint32_t* out1, int cnum, void* stream);
+
+/* Rescale by `bits` (rescaleBy of Section 6.2; arbitrary bit counts as in Section
+ * 3.2): out = [R(in)]_(2^(logq - bits)) per component, R the CKKS or BGV division
+ * by 2^bits.  in0/in1 device uint32[cnum][L][N], out0/out1 device
+ * uint32[cnum][L'][N] with L' = ceil((logq - bits) / 32); in place is allowed.
+ * 1 <= bits < logq.  Errors: FHE_E_INVAL, FHE_E_DEVICE. */
+int fhe_rescale(fhe_ctx* ctx, int scheme, uint32_t t, int logN, int logq, int bits,
+                const uint32_t* in0, const uint32_t* in1, uint32_t* out0, uint32_t* out1,
+                int cnum, void* stream);
+
+/* fhe_mul_relin followed by fhe_rescale(bits), fused; bit-identical to the two
+ * calls.  out0/out1 are uint32[cnum][L'][N], L' = ceil((logq - bits) / 32). */
+int fhe_mul_relin_rescale(fhe_ctx* ctx, fhe_evk* evk, int logN, int logq, int bits,
+                          const uint32_t* x0, const uint32_t* x1, const uint32_t* y0,
+                          const uint32_t* y1, uint32_t* out0, uint32_t* out1, int cnum,
+                          void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FHE_MI355X_H */

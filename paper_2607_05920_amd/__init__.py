@@ -1,0 +1,267 @@
+"""MI355X (gfx950) homomorphic multiplication for non-RNS CKKS/BGV.
+
+Thin ctypes binding over the C ABI of ``libfhe_mi355x.so`` (declared in
+``include/fhe_mi355x.h``).  Every step of the computation runs in the library's
+HIP kernels; this module only marshals arguments: torch CUDA tensors for device
+buffers (int32 tensors holding the uint32 limb bits) and the current torch stream.
+Importing the module does not need a GPU; calling a compute function without the
+built library raises ``LibraryMissing``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfhe_mi355x.so")
+
+CKKS = 0
+BGV = 1
+
+STATUS = {
+    0: "ok", -1: "invalid argument", -2: "shape mismatch", -3: "out of range",
+    -4: "out of memory", -5: "device error", -6: "bad state",
+}
+
+# Every exported symbol and its ctypes signature (restype, argtypes).
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_U = ctypes.c_uint32
+EXPORTS = {
+    "fhe_strerror": (ctypes.c_char_p, [_I]),
+    "fhe_ctx_create": (_I, [_I, _I, _I, ctypes.POINTER(_P)]),
+    "fhe_ctx_destroy": (None, [_P]),
+    "fhe_ctx_reset_error": (_I, [_P]),
+    "fhe_prime_count": (_I, [_P, ctypes.POINTER(_I)]),
+    "fhe_prime_info": (_I, [_P, _I, ctypes.POINTER(_U), ctypes.POINTER(_U)]),
+    "fhe_primes_needed": (_I, [_P, _I, _I, _I, _I, ctypes.POINTER(_I)]),
+    "fhe_lift": (_I, [_P, _I, _I, _I, _P, _P, _I, _P]),
+    "fhe_ntt": (_I, [_P, _I, _I, _I, _P, _I, _P]),
+    "fhe_ring_mul": (_I, [_P, _I, _I, _P, _P, _P, _I, _P]),
+    "fhe_evk_create": (_I, [_P, _I, _U, _I, _I, _I, _P, _P, ctypes.POINTER(_P)]),
+    "fhe_evk_prepare": (_I, [_P, _I, _P]),
+    "fhe_evk_destroy": (None, [_P]),
+    "fhe_mul_relin": (_I, [_P, _P, _I, _I, _P, _P, _P, _P, _P, _P, _I, _P]),
+    "fhe_rescale": (_I, [_P, _I, _U, _I, _I, _I, _P, _P, _P, _P, _I, _P]),
+    "fhe_mul_relin_rescale": (_I, [_P, _P, _I, _I, _I, _P, _P, _P, _P, _P, _P, _I, _P]),
+}
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+class FheError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        super().__init__(f"{fn} failed: {STATUS.get(status, status)} ({status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library (no GPU needed to load it)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise LibraryMissing(f"{path} is not built; run paper_2607_05920_amd/build.py")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(fn: str, status: int):
+    if status != 0:
+        raise FheError(fn, status)
+
+
+def _ptr(t) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("device buffers must be torch CUDA tensors")
+    if t.dtype not in (torch.int32, torch.uint32):
+        raise TypeError("limb buffers must be 32-bit integer tensors")
+    if not t.is_contiguous():
+        raise ValueError("buffers must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def nlimbs(bits: int) -> int:
+    return (bits + 31) // 32
+
+
+def _need(t, words: int, name: str):
+    if t.numel() < words:
+        raise ValueError(f"{name}: {t.numel()} words, {words} needed")
+
+
+class Context:
+    """A library context on one device: prime, twiddle and Garner tables."""
+
+    def __init__(self, logQ_max: int, logP_max: int, device: int = 0):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check("fhe_ctx_create", lib.fhe_ctx_create(device, logQ_max, logP_max, ctypes.byref(h)))
+        self._h = h
+        self.logQ_max, self.logP_max, self.device = logQ_max, logP_max, device
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load_library().fhe_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def prime_count(self) -> int:
+        n = ctypes.c_int()
+        _check("fhe_prime_count", load_library().fhe_prime_count(self._h, ctypes.byref(n)))
+        return n.value
+
+    def prime_info(self, idx: int):
+        q, psi = ctypes.c_uint32(), ctypes.c_uint32()
+        _check("fhe_prime_info", load_library().fhe_prime_info(self._h, idx, ctypes.byref(q), ctypes.byref(psi)))
+        return q.value, psi.value
+
+    def primes_needed(self, logN: int, bits_a: int, bits_b: int, terms: int = 1) -> int:
+        k = ctypes.c_int()
+        _check("fhe_primes_needed",
+               load_library().fhe_primes_needed(self._h, logN, bits_a, bits_b, terms, ctypes.byref(k)))
+        return k.value
+
+    def reset_error(self) -> int:
+        return load_library().fhe_ctx_reset_error(self._h)
+
+    # -------------------------------------------------------------- compute
+    def lift(self, logN: int, L: int, nprimes: int, limbs, res, count: int = 1, stream=None):
+        N = 1 << logN
+        _need(limbs, count * L * N, "limbs")
+        _need(res, count * nprimes * N, "res")
+        _check("fhe_lift", load_library().fhe_lift(self._h, logN, L, nprimes, _ptr(limbs), _ptr(res), count,
+                                                   _stream(stream)))
+
+    def ntt(self, logN: int, nprimes: int, data, count: int = 1, inverse: bool = False, stream=None):
+        _need(data, count * nprimes << logN, "data")
+        _check("fhe_ntt", load_library().fhe_ntt(self._h, logN, nprimes, int(inverse), _ptr(data), count,
+                                                 _stream(stream)))
+
+    def ring_mul(self, logN: int, logq: int, a, b, out, cnum: int = 1, stream=None):
+        w = cnum * nlimbs(logq) << logN
+        for t, n in ((a, "a"), (b, "b"), (out, "out")):
+            _need(t, w, n)
+        _check("fhe_ring_mul", load_library().fhe_ring_mul(self._h, logN, logq, _ptr(a), _ptr(b), _ptr(out), cnum,
+                                                           _stream(stream)))
+
+    def rescale(self, scheme: int, t: int, logN: int, logq: int, bits: int, in0, in1, out0, out1,
+                cnum: int = 1, stream=None):
+        _need(in0, cnum * nlimbs(logq) << logN, "in0")
+        _need(in1, cnum * nlimbs(logq) << logN, "in1")
+        _need(out0, cnum * nlimbs(logq - bits) << logN, "out0")
+        _need(out1, cnum * nlimbs(logq - bits) << logN, "out1")
+        _check("fhe_rescale", load_library().fhe_rescale(self._h, scheme, t, logN, logq, bits, _ptr(in0), _ptr(in1),
+                                                         _ptr(out0), _ptr(out1), cnum, _stream(stream)))
+
+    def mul_relin(self, evk: "EvalKey", logq: int, x0, x1, y0, y1, out0, out1, cnum: int = 1, stream=None):
+        w = cnum * nlimbs(logq) << evk.logN
+        for t, n in ((x0, "x0"), (x1, "x1"), (y0, "y0"), (y1, "y1"), (out0, "out0"), (out1, "out1")):
+            _need(t, w, n)
+        _check("fhe_mul_relin", load_library().fhe_mul_relin(
+            self._h, evk.handle, evk.logN, logq, _ptr(x0), _ptr(x1), _ptr(y0), _ptr(y1), _ptr(out0), _ptr(out1),
+            cnum, _stream(stream)))
+
+    def mul_relin_rescale(self, evk: "EvalKey", logq: int, bits: int, x0, x1, y0, y1, out0, out1, cnum: int = 1,
+                          stream=None):
+        w = cnum * nlimbs(logq) << evk.logN
+        for t, n in ((x0, "x0"), (x1, "x1"), (y0, "y0"), (y1, "y1")):
+            _need(t, w, n)
+        wo = cnum * nlimbs(logq - bits) << evk.logN
+        _need(out0, wo, "out0")
+        _need(out1, wo, "out1")
+        _check("fhe_mul_relin_rescale", load_library().fhe_mul_relin_rescale(
+            self._h, evk.handle, evk.logN, logq, bits, _ptr(x0), _ptr(x1), _ptr(y0), _ptr(y1), _ptr(out0),
+            _ptr(out1), cnum, _stream(stream)))
+
+
+class EvalKey:
+    """Relinearization key (b', a') at modulus P 2^logQ; host limb arrays uint32[L][N]."""
+
+    def __init__(self, ctx: Context, scheme: int, t: int, logN: int, logQ: int, logP: int, b_limbs, a_limbs):
+        import numpy as np
+        lib = load_library()
+        L = nlimbs(logP + logQ)
+        b = np.ascontiguousarray(b_limbs, dtype=np.uint32)
+        a = np.ascontiguousarray(a_limbs, dtype=np.uint32)
+        if b.shape != (L, 1 << logN) or a.shape != (L, 1 << logN):
+            raise ValueError(f"key limbs must be uint32[{L}][{1 << logN}]")
+        h = ctypes.c_void_p()
+        _check("fhe_evk_create", lib.fhe_evk_create(ctx.handle, scheme, t, logN, logQ, logP,
+                                                    b.ctypes.data_as(ctypes.c_void_p),
+                                                    a.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)))
+        self._h = h
+        self.ctx, self.scheme, self.t = ctx, scheme, t
+        self.logN, self.logQ, self.logP = logN, logQ, logP
+
+    @property
+    def handle(self):
+        return self._h
+
+    def prepare(self, logq: int, stream=None):
+        _check("fhe_evk_prepare", load_library().fhe_evk_prepare(self._h, logq, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load_library().fhe_evk_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def to_device(arr, device: int = 0):
+    """numpy uint32 array -> contiguous torch int32 CUDA tensor with the same bits."""
+    import numpy as np
+    import torch
+    a = np.ascontiguousarray(arr, dtype=np.uint32)
+    return torch.from_numpy(a.view(np.int32)).to(f"cuda:{device}")
+
+
+def to_host(t):
+    """torch int32 CUDA tensor -> numpy uint32 array with the same bits."""
+    import numpy as np
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+@dataclass
+class Ciphertext:
+    """Device ciphertext batch: c0, c1 of shape [cnum][L][N] plus metadata."""
+    c0: object
+    c1: object
+    logN: int
+    logq: int
+    logp: int = 0
+    scheme: int = CKKS
+    t: int = 0
+    gamma: int = 1

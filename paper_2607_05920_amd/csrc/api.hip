@@ -1,0 +1,873 @@
+// Host layer of the C ABI: contexts, precomputed tables (Section 5.2), keys,
+// scratch memory and the launch sequences of the HE-mult pipeline.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "fhe_internal.h"
+#include "fhe_mi355x.h"
+
+using namespace fhe;
+
+namespace {
+
+// ---------------------------------------------------------------- host number theory
+
+uint64_t mulmod64(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((unsigned __int128)a * b % m); }
+
+uint64_t powmod(uint64_t b, uint64_t e, uint64_t m) {
+  uint64_t r = 1 % m;
+  b %= m;
+  while (e) {
+    if (e & 1) r = mulmod64(r, b, m);
+    b = mulmod64(b, b, m);
+    e >>= 1;
+  }
+  return r;
+}
+
+uint64_t invmod(uint64_t a, uint64_t m) {  // m prime
+  return powmod(a % m, m - 2, m);
+}
+
+bool is_prime32(uint32_t n) {
+  if (n < 2) return false;
+  for (uint32_t p : {2u, 3u, 5u, 7u, 11u, 13u}) {
+    if (n % p == 0) return n == p;
+  }
+  uint32_t d = n - 1;
+  int s = 0;
+  while ((d & 1) == 0) {
+    d >>= 1;
+    ++s;
+  }
+  for (uint32_t a : {2u, 3u, 5u, 7u}) {  // deterministic below 3.2e9
+    uint64_t x = powmod(a, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool comp = true;
+    for (int r = 1; r < s; ++r) {
+      x = mulmod64(x, x, n);
+      if (x == n - 1) {
+        comp = false;
+        break;
+      }
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+
+uint32_t bitrev(uint32_t x, int bits) {
+  uint32_t r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1u) << (bits - 1 - i);
+  return r;
+}
+
+uint2 shoup_pair(uint32_t w, uint32_t q) {
+  return make_uint2(w, (uint32_t)(((uint64_t)w << 32) / q));
+}
+
+// Unsigned big integer as little-endian 32-bit words.
+struct Big {
+  std::vector<uint32_t> w{1};
+  void mul_small(uint32_t m) {
+    uint64_t c = 0;
+    for (auto& x : w) {
+      uint64_t t = (uint64_t)x * m + c;
+      x = (uint32_t)t;
+      c = t >> 32;
+    }
+    if (c) w.push_back((uint32_t)c);
+  }
+  int bitlen() const {
+    int n = (int)w.size();
+    while (n > 0 && w[n - 1] == 0) --n;
+    if (n == 0) return 0;
+    return 32 * (n - 1) + (32 - __builtin_clz(w[n - 1]));
+  }
+  uint32_t bits_at(int pos, int nb) const {  // nb <= 32
+    uint64_t v = 0;
+    int wi = pos >> 5, sh = pos & 31;
+    if (wi < (int)w.size()) v = w[wi];
+    if (wi + 1 < (int)w.size()) v |= (uint64_t)w[wi + 1] << 32;
+    return (uint32_t)((v >> sh) & ((nb == 32) ? 0xFFFFFFFFull : ((1ull << nb) - 1)));
+  }
+};
+
+template <typename T>
+hipError_t upload(T** dptr, const std::vector<T>& h) {
+  hipError_t e = hipMalloc((void**)dptr, h.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+int ceil_log2(int x) {
+  int r = 0;
+  while ((1 << r) < x) ++r;
+  return r;
+}
+
+int status_of(hipError_t e) {
+  if (e == hipSuccess) return FHE_OK;
+  if (e == hipErrorOutOfMemory) return FHE_E_NOMEM;
+  return FHE_E_DEVICE;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- objects
+
+struct Workspace {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+struct fhe_ctx {
+  int device = 0;
+  int logQ_max = 0, logP_max = 0;
+  int K = 0;     // primes in the table
+  int Kpad = 0;  // K + padding read by blocked kernels
+  std::vector<uint32_t> q, psi;
+  std::vector<int> mbits;  // mbits[k] = bit length of M_k = prod_(i<k) q_i, k <= K
+  // device tables
+  PrimeC* pc = nullptr;
+  uint2* tw = nullptr;
+  uint2* itw = nullptr;
+  uint2* nscale[kLogNMax + 1] = {};  // N^-1 per prime
+  uint2* gscale[kLogNMax + 1] = {};  // N^-1 2^32 I_k per prime (Garner-bound transforms)
+  uint32_t* liftT = nullptr;
+  int TS = 0, Lmax = 0;
+  uint32_t* Gt = nullptr;
+  int GS = 0;
+  uint32_t* Ct = nullptr;
+  int CS = 0, Dmax = 0;
+  int* kstart = nullptr;
+  std::vector<uint32_t> Ik;  // host copy of I_k
+  std::map<int, uint32_t*> ow;       // per offset exponent e
+  std::map<uint32_t, uint32_t*> pw;  // per BGV t: 2^(32 l) mod t
+  std::map<std::pair<void*, int>, Workspace> ws;  // (stream, slot)
+  std::recursive_mutex mu;
+  int sticky = FHE_OK;
+};
+
+struct fhe_evk {
+  fhe_ctx* ctx = nullptr;
+  int scheme = 0;
+  uint32_t t = 0;
+  int logN = 0, logQ = 0, logP = 0;
+  std::vector<uint32_t> hb, ha;  // host limbs [L_PQ][N]
+  std::map<int, uint32_t*> ntt;  // per logq: [2][K_r][N]
+};
+
+namespace {
+
+int set_sticky(fhe_ctx* c, hipError_t e) {
+  int st = status_of(e);
+  if (st != FHE_OK && c->sticky == FHE_OK) c->sticky = st;
+  return st;
+}
+
+// Smallest K with M_K > 2^(e+1), i.e. bitlen(M_K) >= e + 2 (M_K is odd).
+int primes_for_e(const fhe_ctx* c, int e) {
+  for (int k = 0; k <= c->K; ++k)
+    if (c->mbits[k] >= e + 2) return k;
+  return -1;
+}
+
+uint32_t* offsets(fhe_ctx* c, int e, hipError_t* err) {
+  auto it = c->ow.find(e);
+  if (it != c->ow.end()) return it->second;
+  std::vector<uint32_t> h(c->Kpad, 0);
+  for (int k = 0; k < c->K; ++k) h[k] = (uint32_t)mulmod64(powmod(2, e, c->q[k]), c->Ik[k], c->q[k]);
+  uint32_t* d = nullptr;
+  *err = upload(&d, h);
+  if (*err != hipSuccess) return nullptr;
+  c->ow[e] = d;
+  return d;
+}
+
+uint32_t* pow_table(fhe_ctx* c, uint32_t t, hipError_t* err) {
+  auto it = c->pw.find(t);
+  if (it != c->pw.end()) return it->second;
+  std::vector<uint32_t> h(512);
+  uint64_t x = 1 % t;
+  const uint64_t w32 = ((uint64_t)1 << 32) % t;
+  for (auto& v : h) {
+    v = (uint32_t)x;
+    x = x * w32 % t;
+  }
+  uint32_t* d = nullptr;
+  *err = upload(&d, h);
+  if (*err != hipSuccess) return nullptr;
+  c->pw[t] = d;
+  return d;
+}
+
+// Scratch memory of a (context, stream, slot), grown on demand.
+void* scratch(fhe_ctx* c, void* stream, int slot, size_t bytes, hipError_t* err) {
+  Workspace& w = c->ws[std::make_pair(stream, slot)];
+  if (w.bytes < bytes) {
+    if (w.ptr) {
+      hipStreamSynchronize((hipStream_t)stream);
+      hipFree(w.ptr);
+      w.ptr = nullptr;
+      w.bytes = 0;
+    }
+    *err = hipMalloc(&w.ptr, bytes);
+    if (*err != hipSuccess) return nullptr;
+    w.bytes = bytes;
+  }
+  *err = hipSuccess;
+  return w.ptr;
+}
+
+int check_logN(int logN) { return (logN >= FHE_LOGN_MIN && logN <= FHE_LOGN_MAX) ? FHE_OK : FHE_E_RANGE; }
+
+NttArgs ntt_args(fhe_ctx* c, uint32_t* data, int logN, int K, int per_group, long long gstride,
+                 bool inverse, const uint2* scale) {
+  NttArgs a;
+  a.data = data;
+  a.logN = logN;
+  a.K = K;
+  a.per_group = per_group;
+  a.group_stride = gstride;
+  a.tw = inverse ? c->itw : c->tw;
+  a.pc = c->pc;
+  a.scale = scale;
+  return a;
+}
+
+LiftArgs lift_args(fhe_ctx* c, const uint32_t* limbs, uint32_t* res, long long in_stride,
+                   long long out_stride, int N, int L, int K) {
+  LiftArgs a;
+  a.limbs = limbs;
+  a.res = res;
+  a.in_stride = in_stride;
+  a.out_stride = out_stride;
+  a.N = N;
+  a.L = L;
+  a.K = K;
+  a.T = c->liftT;
+  a.TS = c->TS;
+  a.pc = c->pc;
+  return a;
+}
+
+GarnerArgs garner_args(fhe_ctx* c, const uint32_t* res, int per_group, long long gstride,
+                       long long pstride, uint32_t* out, long long ostride, int N, int K,
+                       int outbits, const uint32_t* ow) {
+  GarnerArgs a;
+  a.res = res;
+  a.per_group = per_group;
+  a.gstride = gstride;
+  a.pstride = pstride;
+  a.out = out;
+  a.ostride = ostride;
+  a.N = N;
+  a.K = K;
+  a.outbits = outbits;
+  a.Lout = (outbits + 31) / 32;
+  a.pc = c->pc;
+  a.Gt = c->Gt;
+  a.GS = c->GS;
+  a.Ow = ow;
+  a.Ct = c->Ct;
+  a.CS = c->CS;
+  a.kstart = c->kstart;
+  return a;
+}
+
+// Build the relinearization key's NTT form for level logq.
+int evk_prepare_locked(fhe_evk* k, int logq, hipStream_t stream) {
+  fhe_ctx* c = k->ctx;
+  if (k->ntt.count(logq)) return FHE_OK;
+  if (logq < 1 || logq > k->logQ) return FHE_E_RANGE;
+  const int N = 1 << k->logN;
+  const int bits = k->logP + logq;
+  const int Lk = (bits + 31) / 32;
+  const int Lfull = (k->logP + k->logQ + 31) / 32;
+  const int Kr = primes_for_e(c, k->logN + 2 * logq + k->logP);
+  if (Kr < 0) return FHE_E_RANGE;
+  // key limbs reduced mod P 2^logq
+  std::vector<uint32_t> h((size_t)2 * Lk * N);
+  for (int part = 0; part < 2; ++part) {
+    const std::vector<uint32_t>& src = part ? k->ha : k->hb;
+    for (int l = 0; l < Lk; ++l) {
+      uint32_t mask = 0xFFFFFFFFu;
+      if (l == Lk - 1 && (bits & 31)) mask = (1u << (bits & 31)) - 1u;
+      for (int j = 0; j < N; ++j)
+        h[((size_t)part * Lk + l) * N + j] = (l < Lfull ? src[(size_t)l * N + j] : 0u) & mask;
+    }
+  }
+  uint32_t* limbs = nullptr;
+  uint32_t* out = nullptr;
+  hipError_t e = hipMalloc(&limbs, h.size() * 4);
+  if (e != hipSuccess) return set_sticky(c, e);
+  e = hipMalloc(&out, (size_t)2 * Kr * N * 4);
+  if (e != hipSuccess) {
+    hipFree(limbs);
+    return set_sticky(c, e);
+  }
+  e = hipMemcpyAsync(limbs, h.data(), h.size() * 4, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = launch_lift(lift_args(c, limbs, out, (long long)Lk * N, (long long)Kr * N, N, Lk, Kr), 2, stream);
+  if (e == hipSuccess)
+    e = launch_ntt(ntt_args(c, out, k->logN, Kr, 2 * Kr, 0, false, nullptr), 2 * Kr, false, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  hipFree(limbs);
+  if (e != hipSuccess) {
+    hipFree(out);
+    return set_sticky(c, e);
+  }
+  k->ntt[logq] = out;
+  return FHE_OK;
+}
+
+// The HE-mult pipeline; writes out0/out1 ([cnum][L][N]) = [d + R(k)]_(2^logq).
+int mul_relin_locked(fhe_ctx* c, fhe_evk* k, int logN, int logq, const uint32_t* x0,
+                     const uint32_t* x1, const uint32_t* y0, const uint32_t* y1, uint32_t* out0,
+                     uint32_t* out1, long long ostride, int cnum, hipStream_t st) {
+  const int N = 1 << logN;
+  const int L = (logq + 31) / 32;
+  const int logP = k->logP;
+  const int LK = (logP + logq + 31) / 32;
+  const int et = 2 * logq + logN + 1;
+  const int er = logN + 2 * logq + logP;
+  const int Kt = primes_for_e(c, et);
+  const int Kr = primes_for_e(c, er);
+  if (Kt < 0 || Kr < 0) return FHE_E_RANGE;
+  int rc = evk_prepare_locked(k, logq, st);
+  if (rc != FHE_OK) return rc;
+  hipError_t e = hipSuccess;
+  const uint32_t* owt = offsets(c, et, &e);
+  if (!owt) return set_sticky(c, e);
+  const uint32_t* owr = offsets(c, er, &e);
+  if (!owr) return set_sticky(c, e);
+  const long long NN = N;
+  // scratch layout (words)
+  const long long szRt = (long long)cnum * 4 * Kt * NN;  // tensor residues
+  const long long szDl = (long long)cnum * 3 * L * NN;   // d0, d1, d2 limbs
+  const long long szRr = (long long)cnum * Kr * NN;      // d2 residues
+  const long long szK = (long long)cnum * 2 * Kr * NN;   // k0, k1 residues
+  const long long szKl = (long long)cnum * 2 * LK * NN;  // k0, k1 limbs
+  const long long words = szRt + szDl + szRr + szK + szKl;
+  uint32_t* ws = (uint32_t*)scratch(c, st, 0, (size_t)words * 4, &e);
+  if (!ws) return set_sticky(c, e);
+  uint32_t* Rt = ws;
+  uint32_t* Dl = Rt + szRt;
+  uint32_t* Rr = Dl + szDl;
+  uint32_t* Rk = Rr + szRr;
+  uint32_t* Kl = Rk + szK;
+  const long long polyw = (long long)L * NN;
+  const long long cstride = polyw;  // inputs are [cnum][L][N]
+  // 1. lift the four inputs: Rt[c][i][Kt][N], i = x0, x1, y0, y1
+  const uint32_t* ins[4] = {x0, x1, y0, y1};
+  for (int i = 0; i < 4 && e == hipSuccess; ++i)
+    e = launch_lift(lift_args(c, ins[i], Rt + (long long)i * Kt * NN, cstride, 4LL * Kt * NN, N, L, Kt),
+                    cnum, st);
+  // 2. forward NTT of all 4 cnum Kt transforms
+  if (e == hipSuccess)
+    e = launch_ntt(ntt_args(c, Rt, logN, Kt, 4 * Kt, 4LL * Kt * NN, false, nullptr), cnum * 4 * Kt, false, st);
+  // 3. tensor products into slots 0..2
+  if (e == hipSuccess) {
+    PointwiseArgs pa{};
+    pa.a = Rt;
+    pa.group_stride = 4LL * Kt * NN;
+    pa.N = N;
+    pa.K = Kt;
+    pa.pc = c->pc;
+    e = launch_tensor_pointwise(pa, cnum, st);
+  }
+  // 4. inverse NTT of slots 0..2 (factor N^-1 2^32 I_k)
+  if (e == hipSuccess)
+    e = launch_ntt(ntt_args(c, Rt, logN, Kt, 3 * Kt, 4LL * Kt * NN, true, c->gscale[logN]), cnum * 3 * Kt,
+                   true, st);
+  // 5. Garner -> d0, d1, d2 mod 2^logq: Dl[c][i][L][N]
+  if (e == hipSuccess)
+    e = launch_garner(garner_args(c, Rt, 3, 4LL * Kt * NN, (long long)Kt * NN, Dl, polyw, N, Kt, logq, owt),
+                      cnum * 3, st);
+  // 6. lift d2 onto Kr primes
+  if (e == hipSuccess)
+    e = launch_lift(lift_args(c, Dl + 2 * polyw, Rr, 3 * polyw, (long long)Kr * NN, N, L, Kr), cnum, st);
+  // 7. forward NTT of d2
+  if (e == hipSuccess)
+    e = launch_ntt(ntt_args(c, Rr, logN, Kr, Kr, (long long)Kr * NN, false, nullptr), cnum * Kr, false, st);
+  // 8. products with the resident key: Rk[c][0..1][Kr][N]
+  if (e == hipSuccess) {
+    PointwiseArgs pa{};
+    pa.a = Rr;
+    pa.b = k->ntt[logq];
+    pa.out = Rk;
+    pa.group_stride = (long long)Kr * NN;
+    pa.out_stride = 2LL * Kr * NN;
+    pa.N = N;
+    pa.K = Kr;
+    pa.pc = c->pc;
+    e = launch_relin_pointwise(pa, cnum, st);
+  }
+  // 9. inverse NTT
+  if (e == hipSuccess)
+    e = launch_ntt(ntt_args(c, Rk, logN, Kr, 2 * Kr, 2LL * Kr * NN, true, c->gscale[logN]), cnum * 2 * Kr,
+                   true, st);
+  // 10. Garner -> k0, k1 mod 2^(logP + logq)
+  if (e == hipSuccess)
+    e = launch_garner(garner_args(c, Rk, 2, 2LL * Kr * NN, (long long)Kr * NN, Kl, (long long)LK * NN, N, Kr,
+                                  logP + logq, owr),
+                      cnum * 2, st);
+  // 11. c_i = [d_i + R(k_i)]_(2^logq)
+  if (e == hipSuccess) {
+    ComposeArgs ca{};
+    ca.k = Kl;
+    ca.kstride = (long long)LK * NN;
+    ca.d = Dl;
+    ca.dstride = polyw;
+    ca.out0 = out0;
+    ca.out1 = out1;
+    ca.ostride = ostride;
+    ca.N = N;
+    ca.L = L;
+    ca.LK = LK;
+    ca.logq = logq;
+    ca.logP = logP;
+    ca.scheme = k->scheme;
+    if (k->scheme == FHE_BGV) {
+      ca.t = k->t;
+      ca.invP = (uint32_t)invmod(powmod(2, logP, k->t), k->t);
+      ca.pw = pow_table(c, k->t, &e);
+    }
+    if (e == hipSuccess) e = launch_compose(ca, cnum, st);
+  }
+  return set_sticky(c, e);
+}
+
+int rescale_locked(fhe_ctx* c, int scheme, uint32_t t, int logN, int logq, int bits,
+                   const uint32_t* in0, const uint32_t* in1, long long istride, uint32_t* out0,
+                   uint32_t* out1, long long ostride, int cnum, hipStream_t st) {
+  RescaleArgs ra{};
+  ra.in0 = in0;
+  ra.in1 = in1;
+  ra.out0 = out0;
+  ra.out1 = out1;
+  ra.istride = istride;
+  ra.ostride = ostride;
+  ra.N = 1 << logN;
+  ra.logq = logq;
+  ra.bits = bits;
+  ra.scheme = scheme;
+  hipError_t e = hipSuccess;
+  if (scheme == FHE_BGV) {
+    ra.t = t;
+    ra.invB = (uint32_t)invmod(powmod(2, bits, t), t);
+    ra.pw = pow_table(c, t, &e);
+    if (!ra.pw) return set_sticky(c, e);
+  }
+  e = launch_rescale(ra, cnum, st);
+  return set_sticky(c, e);
+}
+
+bool valid_t(int scheme, uint32_t t) {
+  if (scheme == FHE_CKKS) return true;
+  return scheme == FHE_BGV && t >= 3 && (t & 1) && t < (1u << 24);
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+
+extern "C" {
+
+const char* fhe_strerror(int status) {
+  switch (status) {
+    case FHE_OK: return "ok";
+    case FHE_E_INVAL: return "invalid argument";
+    case FHE_E_SHAPE: return "operand shape or parameter mismatch";
+    case FHE_E_RANGE: return "beyond context limits or key level";
+    case FHE_E_NOMEM: return "out of memory";
+    case FHE_E_DEVICE: return "HIP device error";
+    case FHE_E_STATE: return "object in the wrong state";
+    default: return "unknown status";
+  }
+}
+
+int fhe_ctx_create(int device, int logQ_max, int logP_max, fhe_ctx** out) {
+  if (!out || logQ_max < 1 || logP_max < 1 || logQ_max > 8192 || logP_max > 8192) return FHE_E_INVAL;
+  *out = nullptr;
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) return FHE_E_DEVICE;
+  fhe_ctx* c = new (std::nothrow) fhe_ctx();
+  if (!c) return FHE_E_NOMEM;
+  c->device = device;
+  c->logQ_max = logQ_max;
+  c->logP_max = logP_max;
+  // primes q = 1 mod 2^17 below 2^30, largest first, until the largest relinearization
+  // product (logN 16, logq = logQ_max, logP = logP_max) is covered.
+  const int e_max = kLogNMax + 2 * logQ_max + logP_max;
+  Big M;
+  c->mbits.push_back(M.bitlen());
+  for (uint32_t cand = (1u << 30) - (1u << 17) + 1; cand > (1u << 29); cand -= (1u << 17)) {
+    if (c->mbits.back() >= e_max + 2) break;
+    if (!is_prime32(cand)) continue;
+    c->q.push_back(cand);
+    M.mul_small(cand);
+    c->mbits.push_back(M.bitlen());
+  }
+  if (c->mbits.back() < e_max + 2) {
+    delete c;
+    return FHE_E_RANGE;
+  }
+  const int K = (int)c->q.size();
+  c->K = K;
+  c->Kpad = K + kGarnerBlock + kLiftPrimes;
+  const int Kpad = c->Kpad;
+  // psi: g^((q-1)/2^17) for the smallest g with order exactly 2^17
+  for (int k = 0; k < K; ++k) {
+    const uint32_t q = c->q[k];
+    for (uint32_t g = 2;; ++g) {
+      uint64_t r = powmod(g, (q - 1) >> 17, q);
+      if (powmod(r, 1u << 16, q) == q - 1) {
+        c->psi.push_back((uint32_t)r);
+        break;
+      }
+    }
+  }
+  // per-prime constants
+  std::vector<PrimeC> pc(Kpad);
+  for (int k = 0; k < Kpad; ++k) {
+    const uint32_t q = k < K ? c->q[k] : c->q[0];
+    uint32_t inv = 1;  // q^-1 mod 2^32 by Newton iteration
+    for (int it = 0; it < 5; ++it) inv *= 2u - q * inv;
+    pc[k].q = q;
+    pc[k].qneg = (uint32_t)(0u - inv);
+    pc[k].c32 = (uint32_t)((1ull << 32) % q);
+    pc[k].two_q = 2 * q;
+  }
+  // I_k = [M_k^-1]_(q_k); mk[j][k] = [M_j]_(q_k)
+  c->Ik.assign(K, 1);
+  std::vector<uint32_t> Mmod(K, 1);  // running [M_j]_(q_k) for the current j
+  c->GS = Kpad;
+  std::vector<uint32_t> Gt((size_t)K * c->GS, 0);
+  for (int j = 0; j < K; ++j) {
+    for (int k = j + 1; k < K; ++k) {
+      // Mmod[k] currently holds [M_j]_(q_k)
+      Gt[(size_t)j * c->GS + k] = Mmod[k];
+    }
+    for (int k = 0; k < K; ++k) Mmod[k] = (uint32_t)mulmod64(Mmod[k], c->q[j], c->q[k]);
+  }
+  {
+    // I_k from [M_k]_(q_k): recompute M_k mod q_k
+    for (int k = 0; k < K; ++k) {
+      uint64_t m = 1;
+      for (int i = 0; i < k; ++i) m = mulmod64(m, c->q[i], c->q[k]);
+      c->Ik[k] = (uint32_t)invmod(m, c->q[k]);
+    }
+    for (int j = 0; j < K; ++j)
+      for (int k = j + 1; k < K; ++k) {
+        uint64_t v = mulmod64(Gt[(size_t)j * c->GS + k], c->Ik[k], c->q[k]);
+        Gt[(size_t)j * c->GS + k] = (uint32_t)mulmod64(v, (1ull << 32) % c->q[k], c->q[k]);
+      }
+  }
+  // column digits of M_k (radix 2^26) and first contributing k per column
+  const int outbits_max = logP_max + logQ_max;
+  c->Dmax = (outbits_max + kHornerDigitBits - 1) / kHornerDigitBits;
+  c->CS = c->Dmax + kHornerBlock;
+  std::vector<uint32_t> Ct((size_t)Kpad * c->CS, 0);
+  {
+    Big Mk;
+    for (int k = 0; k < K; ++k) {
+      for (int m = 0; m < c->Dmax; ++m) Ct[(size_t)k * c->CS + m] = Mk.bits_at(kHornerDigitBits * m, kHornerDigitBits);
+      Mk.mul_small(c->q[k]);
+    }
+  }
+  std::vector<int> kstart(c->Dmax + kHornerBlock, K);
+  for (int m = 0; m < (int)kstart.size(); ++m)
+    for (int k = 0; k < K; ++k)
+      if (c->mbits[k] > kHornerDigitBits * m) {
+        kstart[m] = k;
+        break;
+      }
+  // lift constants 2^(28 i) 2^32 mod q_p (Montgomery form)
+  c->Lmax = (std::max(logQ_max, logP_max + logQ_max) + 31) / 32;
+  c->TS = 8 * ((c->Lmax + 6) / 7);
+  std::vector<uint32_t> T((size_t)Kpad * c->TS, 0);
+  for (int p = 0; p < K; ++p) {
+    const uint32_t q = c->q[p];
+    uint64_t v = (1ull << 32) % q;
+    const uint64_t step = (1ull << kLiftDigitBits) % q;
+    for (int i = 0; i < c->TS; ++i) {
+      T[(size_t)p * c->TS + i] = (uint32_t)v;
+      v = mulmod64(v, step, q);
+    }
+  }
+  // twiddles psi^bitrev(k) and psi^-bitrev(k), k < 2^16
+  std::vector<uint2> tw((size_t)K * kNMax), itw((size_t)K * kNMax);
+  {
+    std::vector<uint32_t> pw(kNMax), ipw(kNMax);
+    for (int p = 0; p < K; ++p) {
+      const uint32_t q = c->q[p];
+      const uint64_t ps = c->psi[p], ips = invmod(ps, q);
+      uint64_t a = 1, b = 1;
+      for (int i = 0; i < kNMax; ++i) {
+        pw[i] = (uint32_t)a;
+        ipw[i] = (uint32_t)b;
+        a = mulmod64(a, ps, q);
+        b = mulmod64(b, ips, q);
+      }
+      for (int i = 0; i < kNMax; ++i) {
+        const uint32_t br = bitrev((uint32_t)i, kLogNMax);
+        tw[(size_t)p * kNMax + i] = shoup_pair(pw[br], q);
+        itw[(size_t)p * kNMax + i] = shoup_pair(ipw[br], q);
+      }
+    }
+  }
+  // final inverse factors per logN
+  std::vector<std::vector<uint2>> ns(kLogNMax + 1), gs(kLogNMax + 1);
+  for (int lg = FHE_LOGN_MIN; lg <= kLogNMax; ++lg) {
+    ns[lg].assign(Kpad, make_uint2(0, 0));
+    gs[lg].assign(Kpad, make_uint2(0, 0));
+    for (int p = 0; p < K; ++p) {
+      const uint32_t q = c->q[p];
+      const uint64_t ni = invmod(1ull << lg, q);
+      ns[lg][p] = shoup_pair((uint32_t)ni, q);
+      const uint64_t g = mulmod64(mulmod64(ni, (1ull << 32) % q, q), c->Ik[p], q);
+      gs[lg][p] = shoup_pair((uint32_t)g, q);
+    }
+  }
+  // upload
+  if ((e = upload(&c->pc, pc)) == hipSuccess && (e = upload(&c->tw, tw)) == hipSuccess &&
+      (e = upload(&c->itw, itw)) == hipSuccess && (e = upload(&c->liftT, T)) == hipSuccess &&
+      (e = upload(&c->Gt, Gt)) == hipSuccess && (e = upload(&c->Ct, Ct)) == hipSuccess &&
+      (e = upload(&c->kstart, kstart)) == hipSuccess) {
+    for (int lg = FHE_LOGN_MIN; lg <= kLogNMax && e == hipSuccess; ++lg) {
+      e = upload(&c->nscale[lg], ns[lg]);
+      if (e == hipSuccess) e = upload(&c->gscale[lg], gs[lg]);
+    }
+  }
+  if (e != hipSuccess) {
+    fhe_ctx_destroy(c);
+    return status_of(e);
+  }
+  *out = c;
+  return FHE_OK;
+}
+
+void fhe_ctx_destroy(fhe_ctx* c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  hipDeviceSynchronize();
+  for (void* p : {(void*)c->pc, (void*)c->tw, (void*)c->itw, (void*)c->liftT, (void*)c->Gt, (void*)c->Ct,
+                  (void*)c->kstart})
+    if (p) hipFree(p);
+  for (int lg = 0; lg <= kLogNMax; ++lg) {
+    if (c->nscale[lg]) hipFree(c->nscale[lg]);
+    if (c->gscale[lg]) hipFree(c->gscale[lg]);
+  }
+  for (auto& kv : c->ow) hipFree(kv.second);
+  for (auto& kv : c->pw) hipFree(kv.second);
+  for (auto& kv : c->ws)
+    if (kv.second.ptr) hipFree(kv.second.ptr);
+  delete c;
+}
+
+int fhe_ctx_reset_error(fhe_ctx* c) {
+  if (!c) return FHE_E_INVAL;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  int s = c->sticky;
+  c->sticky = FHE_OK;
+  (void)hipGetLastError();
+  return s;
+}
+
+int fhe_prime_count(const fhe_ctx* c, int* count) {
+  if (!c || !count) return FHE_E_INVAL;
+  *count = c->K;
+  return FHE_OK;
+}
+
+int fhe_prime_info(const fhe_ctx* c, int idx, uint32_t* q, uint32_t* psi) {
+  if (!c || !q || !psi) return FHE_E_INVAL;
+  if (idx < 0 || idx >= c->K) return FHE_E_RANGE;
+  *q = c->q[idx];
+  *psi = c->psi[idx];
+  return FHE_OK;
+}
+
+int fhe_primes_needed(const fhe_ctx* c, int logN, int bits_a, int bits_b, int terms, int* K) {
+  if (!c || !K || bits_a < 1 || bits_b < 1 || terms < 1) return FHE_E_INVAL;
+  if (check_logN(logN) != FHE_OK) return FHE_E_RANGE;
+  const int k = primes_for_e(c, bits_a + bits_b + logN + ceil_log2(terms));
+  if (k < 0) return FHE_E_RANGE;
+  *K = k;
+  return FHE_OK;
+}
+
+int fhe_lift(fhe_ctx* c, int logN, int L, int nprimes, const uint32_t* limbs, uint32_t* res, int count,
+             void* stream) {
+  if (!c || !limbs || !res || count < 0 || L < 1 || nprimes < 1) return FHE_E_INVAL;
+  if (check_logN(logN) != FHE_OK || nprimes > c->K || L > c->Lmax) return FHE_E_RANGE;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (c->sticky != FHE_OK) return c->sticky;
+  hipSetDevice(c->device);
+  const int N = 1 << logN;
+  hipError_t e = launch_lift(lift_args(c, limbs, res, (long long)L * N, (long long)nprimes * N, N, L, nprimes),
+                             count, (hipStream_t)stream);
+  return set_sticky(c, e);
+}
+
+int fhe_ntt(fhe_ctx* c, int logN, int nprimes, int inverse, uint32_t* data, int count, void* stream) {
+  if (!c || !data || count < 0 || nprimes < 1 || (inverse != 0 && inverse != 1)) return FHE_E_INVAL;
+  if (check_logN(logN) != FHE_OK || nprimes > c->K) return FHE_E_RANGE;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (c->sticky != FHE_OK) return c->sticky;
+  hipSetDevice(c->device);
+  const long long N = 1LL << logN;
+  hipError_t e = launch_ntt(ntt_args(c, data, logN, nprimes, nprimes, (long long)nprimes * N, inverse != 0,
+                                     c->nscale[logN]),
+                            count * nprimes, inverse != 0, (hipStream_t)stream);
+  return set_sticky(c, e);
+}
+
+int fhe_ring_mul(fhe_ctx* c, int logN, int logq, const uint32_t* a, const uint32_t* b, uint32_t* out, int cnum,
+                 void* stream) {
+  if (!c || !a || !b || !out || cnum < 0 || logq < 1) return FHE_E_INVAL;
+  if (check_logN(logN) != FHE_OK || logq > c->logQ_max + c->logP_max) return FHE_E_RANGE;
+  if (cnum == 0) return FHE_OK;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (c->sticky != FHE_OK) return c->sticky;
+  hipSetDevice(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  const int N = 1 << logN;
+  const int L = (logq + 31) / 32;
+  const int eb = 2 * logq + logN;
+  const int K = primes_for_e(c, eb);
+  if (K < 0) return FHE_E_RANGE;
+  hipError_t e = hipSuccess;
+  const uint32_t* ow = offsets(c, eb, &e);
+  if (!ow) return set_sticky(c, e);
+  const long long KN = (long long)K * N;
+  uint32_t* R = (uint32_t*)scratch(c, stream, 0, (size_t)2 * cnum * KN * 4, &e);
+  if (!R) return set_sticky(c, e);
+  uint32_t* Ra = R;
+  uint32_t* Rb = R + (long long)cnum * KN;
+  e = launch_lift(lift_args(c, a, Ra, (long long)L * N, KN, N, L, K), cnum, st);
+  if (e == hipSuccess) e = launch_lift(lift_args(c, b, Rb, (long long)L * N, KN, N, L, K), cnum, st);
+  if (e == hipSuccess) e = launch_ntt(ntt_args(c, R, logN, K, K, KN, false, nullptr), 2 * cnum * K, false, st);
+  if (e == hipSuccess) {
+    PointwiseArgs pa{};
+    pa.a = Ra;
+    pa.b = Rb;
+    pa.group_stride = KN;
+    pa.N = N;
+    pa.K = K;
+    pa.pc = c->pc;
+    e = launch_ring_pointwise(pa, cnum, st);
+  }
+  if (e == hipSuccess) e = launch_ntt(ntt_args(c, Ra, logN, K, K, KN, true, c->gscale[logN]), cnum * K, true, st);
+  if (e == hipSuccess)
+    e = launch_garner(garner_args(c, Ra, 1, KN, 0, out, (long long)L * N, N, K, logq, ow), cnum, st);
+  return set_sticky(c, e);
+}
+
+int fhe_evk_create(fhe_ctx* c, int scheme, uint32_t t, int logN, int logQ_key, int logP, const uint32_t* b_host,
+                   const uint32_t* a_host, fhe_evk** out) {
+  if (!c || !b_host || !a_host || !out || logQ_key < 1 || logP < 1) return FHE_E_INVAL;
+  if (scheme != FHE_CKKS && scheme != FHE_BGV) return FHE_E_INVAL;
+  if (!valid_t(scheme, t)) return FHE_E_INVAL;
+  if (check_logN(logN) != FHE_OK || logQ_key > c->logQ_max || logP > c->logP_max) return FHE_E_RANGE;
+  *out = nullptr;
+  fhe_evk* k = new (std::nothrow) fhe_evk();
+  if (!k) return FHE_E_NOMEM;
+  k->ctx = c;
+  k->scheme = scheme;
+  k->t = scheme == FHE_BGV ? t : 0;
+  k->logN = logN;
+  k->logQ = logQ_key;
+  k->logP = logP;
+  const size_t n = (size_t)((logP + logQ_key + 31) / 32) << logN;
+  k->hb.assign(b_host, b_host + n);
+  k->ha.assign(a_host, a_host + n);
+  *out = k;
+  return FHE_OK;
+}
+
+int fhe_evk_prepare(fhe_evk* k, int logq, void* stream) {
+  if (!k || !k->ctx) return FHE_E_INVAL;
+  fhe_ctx* c = k->ctx;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (c->sticky != FHE_OK) return c->sticky;
+  hipSetDevice(c->device);
+  return evk_prepare_locked(k, logq, (hipStream_t)stream);
+}
+
+void fhe_evk_destroy(fhe_evk* k) {
+  if (!k) return;
+  if (k->ctx) {
+    hipSetDevice(k->ctx->device);
+    hipDeviceSynchronize();
+  }
+  for (auto& kv : k->ntt) hipFree(kv.second);
+  delete k;
+}
+
+int fhe_mul_relin(fhe_ctx* c, fhe_evk* k, int logN, int logq, const uint32_t* x0, const uint32_t* x1,
+                  const uint32_t* y0, const uint32_t* y1, uint32_t* out0, uint32_t* out1, int cnum, void* stream) {
+  if (!c || !k || !x0 || !x1 || !y0 || !y1 || !out0 || !out1 || cnum < 0 || logq < 1) return FHE_E_INVAL;
+  if (k->ctx != c) return FHE_E_STATE;
+  if (logN != k->logN) return FHE_E_SHAPE;
+  if (logq > k->logQ) return FHE_E_RANGE;
+  if (cnum == 0) return FHE_OK;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (c->sticky != FHE_OK) return c->sticky;
+  hipSetDevice(c->device);
+  const long long ostride = (long long)((logq + 31) / 32) << logN;
+  return mul_relin_locked(c, k, logN, logq, x0, x1, y0, y1, out0, out1, ostride, cnum, (hipStream_t)stream);
+}
+
+int fhe_rescale(fhe_ctx* c, int scheme, uint32_t t, int logN, int logq, int bits, const uint32_t* in0,
+                const uint32_t* in1, uint32_t* out0, uint32_t* out1, int cnum, void* stream) {
+  if (!c || !in0 || !in1 || !out0 || !out1 || cnum < 0 || logq < 2 || bits < 1 || bits >= logq) return FHE_E_INVAL;
+  if (scheme != FHE_CKKS && scheme != FHE_BGV) return FHE_E_INVAL;
+  if (!valid_t(scheme, t)) return FHE_E_INVAL;
+  if (check_logN(logN) != FHE_OK) return FHE_E_RANGE;
+  const int L = (logq + 31) / 32, Lo = (logq - bits + 31) / 32;
+  if (cnum > 1 && Lo != L && ((const void*)in0 == (void*)out0 || (const void*)in1 == (void*)out1))
+    return FHE_E_INVAL;  // in place needs equal strides
+  if (cnum == 0) return FHE_OK;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (c->sticky != FHE_OK) return c->sticky;
+  hipSetDevice(c->device);
+  return rescale_locked(c, scheme, t, logN, logq, bits, in0, in1, (long long)L << logN, out0, out1,
+                        (long long)Lo << logN, cnum, (hipStream_t)stream);
+}
+
+int fhe_mul_relin_rescale(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, const uint32_t* x0,
+                          const uint32_t* x1, const uint32_t* y0, const uint32_t* y1, uint32_t* out0,
+                          uint32_t* out1, int cnum, void* stream) {
+  if (!c || !k || !x0 || !x1 || !y0 || !y1 || !out0 || !out1 || cnum < 0 || logq < 2) return FHE_E_INVAL;
+  if (bits < 1 || bits >= logq) return FHE_E_INVAL;
+  if (k->ctx != c) return FHE_E_STATE;
+  if (logN != k->logN) return FHE_E_SHAPE;
+  if (logq > k->logQ) return FHE_E_RANGE;
+  if (cnum == 0) return FHE_OK;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (c->sticky != FHE_OK) return c->sticky;
+  hipSetDevice(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  const long long polyw = (long long)((logq + 31) / 32) << logN;
+  // relinearized ciphertexts go to a scratch area of their own, then rescale into out
+  hipError_t e = hipSuccess;
+  const size_t extra = (size_t)2 * cnum * polyw * 4;
+  uint32_t* tmp = (uint32_t*)scratch(c, stream, 1, extra, &e);
+  if (!tmp) return set_sticky(c, e);
+  int rc = mul_relin_locked(c, k, logN, logq, x0, x1, y0, y1, tmp, tmp + (long long)cnum * polyw, polyw, cnum, st);
+  if (rc != FHE_OK) return rc;
+  const long long ostride = (long long)((logq - bits + 31) / 32) << logN;
+  return rescale_locked(c, k->scheme, k->t, logN, logq, bits, tmp, tmp + (long long)cnum * polyw, polyw, out0,
+                        out1, ostride, cnum, st);
+}
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+// Internal interfaces between the host layer (api.hip) and the kernels
+// (kernels.hip).  Not part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "modarith.h"
+
+namespace fhe {
+
+constexpr int kLogNMax = 16;
+constexpr int kNMax = 1 << kLogNMax;
+constexpr int kLiftDigitBits = 28;    // lift input digits: 8 digits = 7 limbs
+constexpr int kHornerDigitBits = 26;  // Garner output radix
+constexpr int kGarnerBlock = 16;      // digits finalized per block (accumulators)
+constexpr int kHornerBlock = 16;      // output columns per block
+constexpr int kLiftPrimes = 16;       // primes per lift thread
+
+// Negacyclic NTT over a set of transforms.  Transform tr (blockIdx.y) lives at
+// data + (tr / per_group) * group_stride + (tr % per_group) * N and uses prime
+// (tr % per_group) % K.
+struct NttArgs {
+  uint32_t* data;
+  int logN;
+  int K;
+  int per_group;
+  long long group_stride;
+  const uint2* tw;     // [prime][kNMax] (w, floor(w 2^32 / q)), bit-reversed powers
+  const PrimeC* pc;
+  const uint2* scale;  // inverse only: per-prime final factor (w, w')
+};
+
+struct LiftArgs {
+  const uint32_t* limbs;  // poly z at limbs + z * in_stride, uint32[L][N]
+  uint32_t* res;          // poly z at res + z * out_stride, uint32[K][N]
+  long long in_stride, out_stride;
+  int N, L, K;
+  const uint32_t* T;  // [prime][TS]: 2^(28 i) 2^32 mod q
+  int TS;
+  const PrimeC* pc;
+};
+
+struct PointwiseArgs {
+  uint32_t* a;        // tensor: group c at a + c * group_stride, 4 x [K][N] (x0, x1, y0, y1)
+  const uint32_t* b;  // relin: key (B', A') [2][K][N]; ring: second operand
+  uint32_t* out;
+  long long group_stride, out_stride;
+  int N, K;
+  const PrimeC* pc;
+};
+
+struct GarnerArgs {
+  const uint32_t* res;  // poly z: res + (z / per_group) * gstride + (z % per_group) * pstride
+  int per_group;
+  long long gstride, pstride;
+  uint32_t* out;  // poly z: out + z * ostride, uint32[Lout][N]
+  long long ostride;
+  int N, K, outbits, Lout;
+  const PrimeC* pc;
+  const uint32_t* Gt;  // Gt[j * GS + k] = [M_j I_k 2^32]_(q_k)
+  int GS;
+  const uint32_t* Ow;  // [k] = [2^e I_k]_(q_k)
+  const uint32_t* Ct;  // Ct[k * CS + m] = radix-2^26 digit m of M_k
+  int CS;
+  const int* kstart;   // [m] = min k with M_k >= 2^(26 m)
+};
+
+struct ComposeArgs {
+  const uint32_t* k;  // poly z (= 2 c + i): k + z * kstride, uint32[LK][N]
+  long long kstride;
+  const uint32_t* d;  // d_i of ciphertext c at d + (3 c + i) * dstride, uint32[L][N]
+  long long dstride;
+  uint32_t* out0;
+  uint32_t* out1;
+  long long ostride;  // per ciphertext, uint32[L][N]
+  int N, L, LK, logq, logP, scheme;
+  uint32_t t, invP;  // BGV: t and 2^-logP mod t
+  const uint32_t* pw;  // BGV: pw[l] = 2^(32 l) mod t
+};
+
+struct RescaleArgs {
+  const uint32_t* in0;
+  const uint32_t* in1;
+  uint32_t* out0;
+  uint32_t* out1;
+  long long istride, ostride;
+  int N, logq, bits, scheme;
+  uint32_t t, invB;  // BGV: t and 2^-bits mod t
+  const uint32_t* pw;
+};
+
+hipError_t launch_ntt(const NttArgs& a, int ntransforms, bool inverse, hipStream_t s);
+hipError_t launch_lift(const LiftArgs& a, int npoly, hipStream_t s);
+hipError_t launch_tensor_pointwise(const PointwiseArgs& a, int cnum, hipStream_t s);
+hipError_t launch_relin_pointwise(const PointwiseArgs& a, int cnum, hipStream_t s);
+hipError_t launch_ring_pointwise(const PointwiseArgs& a, int cnum, hipStream_t s);
+hipError_t launch_garner(const GarnerArgs& a, int npoly, hipStream_t s);
+hipError_t launch_compose(const ComposeArgs& a, int cnum, hipStream_t s);
+hipError_t launch_rescale(const RescaleArgs& a, int cnum, hipStream_t s);
+
+}  // namespace fhe

@@ -1,0 +1,565 @@
+// gfx950 kernels for the non-RNS HE-mult pipeline:
+//   lift (limbs -> residues), negacyclic NTT / iNTT, pointwise products,
+//   Garner reconstruction (residues -> limbs), relinearization compose, rescale.
+#include "fhe_internal.h"
+
+namespace fhe {
+
+// ============================================================================ NTT
+//
+// Negacyclic transforms (Section 2.3, Eq. negacyclic_ntt / negacyclic_intt) with
+// the psi-twist merged into the twiddles (Section 5.1): the forward transform is
+// the Cooley-Tukey network whose stage with m groups uses psi^bitrev(m + i) for
+// group i and leaves the output in bit-reversed order; the inverse is the mirrored
+// Gentleman-Sande network with psi^-bitrev(h + i), then the factor N^-1.
+//
+// N = 2^logN is split as N = n1 * n2 (the two-pass / four-step scheme of Section
+// 5.3).  The n1-point stages run over columns {c + n2 u}; the n2-point stages run
+// over contiguous blocks.  Both passes use one kernel shape: a sub-transform of
+// n = 2^S points is held by T = n / 16 threads with 16 values each.  The first
+// register phase works on elements {u T + j} ("strided"), the other on
+// {16 j + u} ("contiguous"); one LDS exchange connects them.  Forward passes run
+// strided then contiguous; inverse passes the reverse.
+
+__device__ __forceinline__ void ct_bfly(uint32_t& X, uint32_t& Y, uint2 w, uint32_t q,
+                                        uint32_t two_q) {
+  // Lazy Cooley-Tukey butterfly: X, Y in [0, 4q) -> [0, 4q).
+  uint32_t x = csub(X, two_q);
+  uint32_t t = shoup_lazy(Y, w.x, w.y, q);
+  X = x + t;
+  Y = x - t + two_q;
+}
+
+__device__ __forceinline__ void gs_bfly(uint32_t& X, uint32_t& Y, uint2 w, uint32_t q,
+                                        uint32_t two_q) {
+  // Lazy Gentleman-Sande butterfly: X, Y in [0, 2q) -> [0, 2q).
+  uint32_t x = X, y = Y;
+  X = csub(x + y, two_q);
+  Y = shoup_lazy(x - y + two_q, w.x, w.y, q);
+}
+
+template <int S, bool INV, bool ROWS>
+__global__ __launch_bounds__(256) void ntt_pass_kernel(NttArgs a) {
+  constexpr int n = 1 << S;
+  constexpr int T = n / 16;
+  constexpr int NSUB = 256 / T;
+  // Row stride in LDS, chosen so that both access patterns are free of bank
+  // conflicts (element e sits at s * SS + e + e / 16).
+  constexpr int SS = ((n + n / 16 + 1 + 31) / 32) * 32 + (ROWS ? T : (NSUB >= 32 ? 1 : 2));
+  __shared__ uint32_t lds[NSUB * SS];
+
+  const int tid = threadIdx.x;
+  const int s = ROWS ? tid / T : tid % NSUB;
+  const int j = ROWS ? tid % T : tid / NSUB;
+
+  const int N = 1 << a.logN;
+  const int nsub_total = N / n;  // blocks (ROWS) or columns (COLS)
+  const int sg = blockIdx.x * NSUB + s;
+  const bool valid = sg < nsub_total;
+
+  const int tr = blockIdx.y;
+  const int grp = tr / a.per_group, r = tr % a.per_group;
+  const int p = r % a.K;
+  uint32_t* base = a.data + (long long)grp * a.group_stride + (long long)r * N;
+  const PrimeC pc = a.pc[p];
+  const uint32_t q = pc.q, two_q = pc.two_q;
+  const uint2* tw = a.tw + (long long)p * kNMax;
+
+  // ROWS: element e of block sg at sg * n + e.  COLS: element e of column sg at
+  // sg + (N / n) e.
+  const long long gstride = ROWS ? 1 : (long long)nsub_total;
+  uint32_t* gp = base + (ROWS ? (long long)sg * n : (long long)sg);
+  // Twiddle index of local stage m (groups) and local group i:
+  // COLS -> m + i; ROWS -> (N / n + sg) m + i.
+  const int tw_mul = ROWS ? (nsub_total + sg) : 1;
+
+  uint32_t x[16];
+  uint32_t* lrow = lds + s * SS;
+
+  if (!INV) {
+    if (valid) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) x[u] = gp[(long long)(u * T + j) * gstride];
+    }
+    // strided stages: m = 1, 2, 4, 8 groups, register distance 8 / m
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int m = 1 << st, h = 8 >> st;
+#pragma unroll
+      for (int g = 0; g < m; ++g) {
+        const uint2 w = tw[tw_mul * m + g];
+#pragma unroll
+        for (int u = 2 * h * g; u < 2 * h * g + h; ++u) ct_bfly(x[u], x[u + h], w, q, two_q);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = u * T + j;
+      lrow[e + (e >> 4)] = x[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = 16 * j + u;
+      x[u] = lrow[e + (e >> 4)];
+    }
+    // contiguous stages: half-distance t = T/2 .. 1, m = n / (2t) groups
+#pragma unroll
+    for (int t = T / 2; t >= 1; t >>= 1) {
+      const int m = n / (2 * t);
+#pragma unroll
+      for (int b0 = 0; b0 < 16; b0 += 2 * t) {
+        const uint2 w = tw[tw_mul * m + j * (8 / t) + b0 / (2 * t)];
+#pragma unroll
+        for (int u = b0; u < b0 + t; ++u) ct_bfly(x[u], x[u + t], w, q, two_q);
+      }
+    }
+    if (ROWS) {  // last forward pass: canonical output
+#pragma unroll
+      for (int u = 0; u < 16; ++u) x[u] = csub(csub(x[u], two_q), q);
+    }
+    if (valid) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) gp[(long long)(16 * j + u) * gstride] = x[u];
+    }
+  } else {
+    if (valid) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) x[u] = gp[(long long)(16 * j + u) * gstride];
+    }
+    // contiguous stages: t = 1 .. T/2, h = n / (2t) groups
+#pragma unroll
+    for (int t = 1; t < T; t <<= 1) {
+      const int h = n / (2 * t);
+#pragma unroll
+      for (int b0 = 0; b0 < 16; b0 += 2 * t) {
+        const uint2 w = tw[tw_mul * h + j * (8 / t) + b0 / (2 * t)];
+#pragma unroll
+        for (int u = b0; u < b0 + t; ++u) gs_bfly(x[u], x[u + t], w, q, two_q);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = 16 * j + u;
+      lrow[e + (e >> 4)] = x[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = u * T + j;
+      x[u] = lrow[e + (e >> 4)];
+    }
+    // strided stages: register distance hd = 1, 2, 4, 8; h = 8 / hd groups
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int hd = 1 << st, h = 8 >> st;
+#pragma unroll
+      for (int g = 0; g < h; ++g) {
+        const uint2 w = tw[tw_mul * h + g];
+#pragma unroll
+        for (int u = 2 * hd * g; u < 2 * hd * g + hd; ++u) gs_bfly(x[u], x[u + hd], w, q, two_q);
+      }
+    }
+    if (!ROWS) {  // last inverse pass: final factor, canonical output
+      const uint2 sc = a.scale[p];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) x[u] = csub(shoup_lazy(x[u], sc.x, sc.y, q), q);
+    }
+    if (valid) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) gp[(long long)(u * T + j) * gstride] = x[u];
+    }
+  }
+}
+
+template <int S, bool INV, bool ROWS>
+static hipError_t ntt_pass(const NttArgs& a, int ntr, hipStream_t st) {
+  constexpr int n = 1 << S;
+  constexpr int NSUB = 256 / (n / 16);
+  const int nsub_total = (1 << a.logN) / n;
+  dim3 grid((nsub_total + NSUB - 1) / NSUB, ntr);
+  hipLaunchKernelGGL((ntt_pass_kernel<S, INV, ROWS>), grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+template <bool INV, bool ROWS>
+static hipError_t ntt_pass_s(int S, const NttArgs& a, int ntr, hipStream_t st) {
+  switch (S) {
+    case 5: return ntt_pass<5, INV, ROWS>(a, ntr, st);
+    case 6: return ntt_pass<6, INV, ROWS>(a, ntr, st);
+    case 7: return ntt_pass<7, INV, ROWS>(a, ntr, st);
+    case 8: return ntt_pass<8, INV, ROWS>(a, ntr, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_ntt(const NttArgs& a, int ntr, bool inverse, hipStream_t st) {
+  if (ntr <= 0) return hipSuccess;
+  const int s_rows = a.logN / 2, s_cols = a.logN - s_rows;
+  hipError_t e;
+  if (!inverse) {
+    if ((e = ntt_pass_s<false, false>(s_cols, a, ntr, st)) != hipSuccess) return e;
+    return ntt_pass_s<false, true>(s_rows, a, ntr, st);
+  }
+  if ((e = ntt_pass_s<true, true>(s_rows, a, ntr, st)) != hipSuccess) return e;
+  return ntt_pass_s<true, false>(s_cols, a, ntr, st);
+}
+
+// ============================================================================ lift
+//
+// Limb -> RNS projection (Section 5.1, "Limb-to-RNS Conversion"): residue of
+// A = sum_i limb_i 2^(32 i) modulo each prime.  The limbs are re-cut into 28-bit
+// digits (8 digits per 7 limbs), so every digit-constant product is below 2^58 and
+// 40 of them fit a 64-bit accumulator between folds.  The constants are
+// 2^(28 i) 2^32 mod q, and the final Montgomery reduction removes the 2^32.
+
+template <int PB>
+__global__ __launch_bounds__(256) void lift_kernel(LiftArgs a) {
+  const int jc = blockIdx.y * 256 + threadIdx.x;  // coefficient
+  const int p0 = blockIdx.x * PB;
+  const int z = blockIdx.z;
+  if (jc >= a.N) return;
+  const uint32_t* src = a.limbs + (long long)z * a.in_stride + jc;
+  uint64_t acc[PB];
+#pragma unroll
+  for (int pp = 0; pp < PB; ++pp) acc[pp] = 0;
+  const int nchunk = (a.L + 6) / 7;
+  for (int ch = 0; ch < nchunk; ++ch) {
+    uint32_t w[8];
+#pragma unroll
+    for (int v = 0; v < 7; ++v) {
+      const int li = 7 * ch + v;
+      w[v] = li < a.L ? src[(long long)li * a.N] : 0u;
+    }
+    w[7] = 0;
+    uint32_t d[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int bit = 28 * u, wi = bit >> 5, sh = bit & 31;
+      uint32_t lo = w[wi] >> sh;
+      if (sh > 4) lo |= w[wi + 1] << (32 - sh);
+      d[u] = lo & 0x0FFFFFFFu;
+    }
+    const uint32_t* Tp = a.T + (long long)p0 * a.TS + 8 * ch;
+#pragma unroll
+    for (int pp = 0; pp < PB; ++pp) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[pp] = mad64(d[u], Tp[(long long)pp * a.TS + u], acc[pp]);
+    }
+    if (ch % 5 == 4) {
+#pragma unroll
+      for (int pp = 0; pp < PB; ++pp) acc[pp] = fold64(acc[pp], a.pc[p0 + pp].c32);
+    }
+  }
+  uint32_t* dst = a.res + (long long)z * a.out_stride + jc;
+#pragma unroll
+  for (int pp = 0; pp < PB; ++pp) {
+    const int p = p0 + pp;
+    if (p < a.K) dst[(long long)p * a.N] = reduce64_mont(acc[pp], a.pc[p]);
+  }
+}
+
+hipError_t launch_lift(const LiftArgs& a, int npoly, hipStream_t st) {
+  if (npoly <= 0) return hipSuccess;
+  dim3 grid((a.K + kLiftPrimes - 1) / kLiftPrimes, (a.N + 255) / 256, npoly);
+  hipLaunchKernelGGL((lift_kernel<kLiftPrimes>), grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// ============================================================================ pointwise
+//
+// Hadamard products in the NTT domain (Section 2.3, Eq. ntt_mul).  Montgomery
+// products carry a factor 2^-32, compensated in the inverse transform's final
+// factor.  Tensor: d0 = x0 y0, d1 = x0 y1 + x1 y0, d2 = x1 y1 (the Karatsuba
+// identity of Section 5.4 gives the same d1; with full-rate multiplies the direct
+// form issues fewer instructions).
+
+__global__ __launch_bounds__(256) void tensor_pointwise_kernel(PointwiseArgs a) {
+  const int jc = blockIdx.x * 256 + threadIdx.x;
+  const int p = blockIdx.y;
+  const int c = blockIdx.z;
+  if (jc >= a.N) return;
+  const long long KN = (long long)a.K * a.N;
+  uint32_t* g = a.a + (long long)c * a.group_stride + (long long)p * a.N + jc;
+  const PrimeC pc = a.pc[p];
+  const uint32_t x0 = g[0], x1 = g[KN], y0 = g[2 * KN], y1 = g[3 * KN];
+  const uint32_t d0 = mont_mul(x0, y0, pc.q, pc.qneg);
+  const uint32_t d2 = mont_mul(x1, y1, pc.q, pc.qneg);
+  const uint32_t d1 = add_mod(mont_mul(x0, y1, pc.q, pc.qneg), mont_mul(x1, y0, pc.q, pc.qneg), pc.q);
+  g[0] = d0;
+  g[KN] = d1;
+  g[2 * KN] = d2;
+}
+
+__global__ __launch_bounds__(256) void relin_pointwise_kernel(PointwiseArgs a) {
+  const int jc = blockIdx.x * 256 + threadIdx.x;
+  const int p = blockIdx.y;
+  const int c = blockIdx.z;
+  if (jc >= a.N) return;
+  const long long KN = (long long)a.K * a.N;
+  const long long off = (long long)p * a.N + jc;
+  const PrimeC pc = a.pc[p];
+  const uint32_t d = a.a[(long long)c * a.group_stride + off];
+  uint32_t* o = a.out + (long long)c * a.out_stride + off;
+  o[0] = mont_mul(d, a.b[off], pc.q, pc.qneg);
+  o[KN] = mont_mul(d, a.b[KN + off], pc.q, pc.qneg);
+}
+
+__global__ __launch_bounds__(256) void ring_pointwise_kernel(PointwiseArgs a) {
+  const int jc = blockIdx.x * 256 + threadIdx.x;
+  const int p = blockIdx.y;
+  const int c = blockIdx.z;
+  if (jc >= a.N) return;
+  const long long off = (long long)p * a.N + jc;
+  const PrimeC pc = a.pc[p];
+  uint32_t* x = a.a + (long long)c * a.group_stride + off;
+  const uint32_t y = a.b[(long long)c * a.group_stride + off];
+  *x = mont_mul(*x, y, pc.q, pc.qneg);
+}
+
+hipError_t launch_tensor_pointwise(const PointwiseArgs& a, int cnum, hipStream_t st) {
+  dim3 grid((a.N + 255) / 256, a.K, cnum);
+  hipLaunchKernelGGL(tensor_pointwise_kernel, grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_relin_pointwise(const PointwiseArgs& a, int cnum, hipStream_t st) {
+  dim3 grid((a.N + 255) / 256, a.K, cnum);
+  hipLaunchKernelGGL(relin_pointwise_kernel, grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_ring_pointwise(const PointwiseArgs& a, int cnum, hipStream_t st) {
+  dim3 grid((a.N + 255) / 256, a.K, cnum);
+  hipLaunchKernelGGL(ring_pointwise_kernel, grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// ============================================================================ Garner
+//
+// RNS -> limbs (Section 5.1, "RNS-to-Limb Reconstruction"; Section 2.5,
+// Eq. garner_mrc).  The integer recovered is Y = X + 2^e, where X is the signed
+// exact coefficient and 2^e exceeds |X|; Y lies in [0, M), so no sign test is
+// needed, and Y = X mod 2^outbits because e >= outbits.
+//
+// Mixed-radix digits: with M_k = prod_(i<k) q_i and I_k = [M_k^-1]_(q_k),
+//   v_k = [ x_k I_k + [2^e I_k] - sum_(j<k) v_j [M_j I_k] ]_(q_k),
+// the same digits as Garner's nested recurrence.  The factor I_k of x_k is
+// applied by the inverse NTT's final multiply.  The sum is a dot product of
+// 30-bit values: lazily accumulated in 64 bits (folded every 11 terms) against
+// constants in Montgomery form, reduced once per digit.
+//
+// One wave handles 64 coefficients (one per lane).  Digits are kept in LDS
+// ([k][lane]); digits are finalized in blocks of 16: the block's 16 sums first
+// take every earlier digit (one LDS read feeds 16 multiply-adds), then the block
+// is finished sequentially in registers.
+//
+// Limbs: Y = sum_k v_k M_k, taken mod 2^(26 D) as column sums over radix-2^26
+// digits of M_k (each product < 2^56, so a column of up to 255 terms fits 64 bits),
+// then carried and re-packed into 32-bit limbs.
+
+__global__ __launch_bounds__(64) void garner_kernel(GarnerArgs a) {
+  extern __shared__ uint32_t vd[];  // [K][64]
+  constexpr int B = kGarnerBlock;
+  constexpr int FOLD = 11;
+  const int lane = threadIdx.x;
+  const int jc = blockIdx.x * 64 + lane;
+  const int z = blockIdx.y;
+  const bool active = jc < a.N;
+  const int jcc = active ? jc : 0;
+  const uint32_t* in = a.res + (long long)(z / a.per_group) * a.gstride +
+                       (long long)(z % a.per_group) * a.pstride + jcc;
+  const int K = a.K;
+
+  for (int kb = 0; kb < K; kb += B) {
+    uint64_t acc[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) acc[u] = 0;
+    // earlier digits
+    for (int j0 = 0; j0 < kb; j0 += FOLD) {
+      const int jn = min(FOLD, kb - j0);
+      for (int jj = 0; jj < jn; ++jj) {
+        const int jd = j0 + jj;
+        const uint32_t v = vd[jd * 64 + lane];
+        const uint32_t* g = a.Gt + (long long)jd * a.GS + kb;
+#pragma unroll
+        for (int u = 0; u < B; ++u) acc[u] = mad64(v, g[u], acc[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u) acc[u] = fold64(acc[u], a.pc[kb + u].c32);
+    }
+    // digits of this block, in order
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int k = kb + u;
+      if (k < K) {
+        const PrimeC pk = a.pc[k];
+        const uint32_t sred = reduce64_mont(acc[u], pk);
+        const uint32_t xk = add_mod(in[(long long)k * a.N], a.Ow[k], pk.q);
+        const uint32_t v = sub_mod(xk, sred, pk.q);
+        vd[k * 64 + lane] = v;
+        const uint32_t* g = a.Gt + (long long)k * a.GS + kb;
+#pragma unroll
+        for (int w = u + 1; w < B; ++w) {
+          acc[w] = mad64(v, g[w], acc[w]);
+          // acc[w] holds at most a folded value plus (w - u) in-block products
+        }
+        if (u == FOLD - 1) {
+#pragma unroll
+          for (int w = FOLD; w < B; ++w) acc[w] = fold64(acc[w], a.pc[kb + w].c32);
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // Column sums over radix-2^26 digits of M_k, carried and packed into limbs.
+  const int D = (a.outbits + kHornerDigitBits - 1) / kHornerDigitBits;
+  uint32_t* out = a.out + (long long)z * a.ostride + jcc;
+  uint64_t carry = 0, bitbuf = 0;
+  int nbits = 0, li = 0;
+  const int topbits = a.outbits - 32 * (a.Lout - 1);
+  const uint32_t topmask = topbits >= 32 ? 0xFFFFFFFFu : ((1u << topbits) - 1u);
+  constexpr int BC = kHornerBlock;
+  for (int m0 = 0; m0 < D; m0 += BC) {
+    uint64_t col[BC];
+#pragma unroll
+    for (int m = 0; m < BC; ++m) col[m] = 0;
+    for (int k = a.kstart[m0]; k < K; ++k) {
+      const uint32_t v = vd[k * 64 + lane];
+      const uint32_t* cc = a.Ct + (long long)k * a.CS + m0;
+#pragma unroll
+      for (int m = 0; m < BC; ++m) col[m] = mad64(v, cc[m], col[m]);
+    }
+#pragma unroll
+    for (int m = 0; m < BC; ++m) {
+      if (m0 + m < D) {
+        const uint64_t t = col[m] + carry;
+        carry = t >> kHornerDigitBits;
+        bitbuf |= (t & ((1u << kHornerDigitBits) - 1u)) << nbits;
+        nbits += kHornerDigitBits;
+        if (nbits >= 32) {
+          if (li < a.Lout && active) {
+            uint32_t wv = (uint32_t)bitbuf;
+            if (li == a.Lout - 1) wv &= topmask;
+            out[(long long)li * a.N] = wv;
+          }
+          ++li;
+          bitbuf >>= 32;
+          nbits -= 32;
+        }
+      }
+    }
+  }
+  if (li < a.Lout && active) {
+    uint32_t wv = (uint32_t)bitbuf;
+    if (li == a.Lout - 1) wv &= topmask;
+    out[(long long)li * a.N] = wv;
+  }
+}
+
+hipError_t launch_garner(const GarnerArgs& a, int npoly, hipStream_t st) {
+  if (npoly <= 0) return hipSuccess;
+  dim3 grid((a.N + 63) / 64, npoly);
+  const size_t lds = (size_t)a.K * 64 * sizeof(uint32_t);
+  hipLaunchKernelGGL(garner_kernel, grid, dim3(64), lds, st, a);
+  return hipGetLastError();
+}
+
+// ============================================================================ compose / rescale
+//
+// Limb-serial finishing steps, one thread per coefficient.
+//   compose:  c_i = [d_i + R(k_i)]_(2^logq), R the rounding division by P = 2^logP
+//   rescale:  c'' = [R(c)]_(2^(logq - bits)), R the rounding division by 2^bits
+// CKKS rounds half up: floor(x / 2^s) + bit_(s-1)(x).  BGV adds the centered
+// [[ (x mod 2^s) 2^-s ]]_t instead (the t-corrected division).
+
+__device__ __forceinline__ int64_t round_correction(const uint32_t* x, long long stride, int nl,
+                                                    int sbits, int scheme, uint32_t t,
+                                                    uint32_t inv, const uint32_t* pw) {
+  // Correction added to floor(x / 2^sbits), x = sum_l x[l stride] 2^(32 l), nl limbs.
+  if (sbits <= 0) return 0;
+  if (scheme == 0) {
+    const int bi = sbits - 1;
+    if ((bi >> 5) >= nl) return 0;
+    return (x[(long long)(bi >> 5) * stride] >> (bi & 31)) & 1u;
+  }
+  // BGV: r = (x mod 2^sbits) mod t, then j = [[ r 2^-s ]]_t.
+  const int full = sbits >> 5, part = sbits & 31;
+  uint64_t acc = 0;
+  for (int l = 0; l < full && l < nl; ++l) acc += (uint64_t)x[(long long)l * stride] * pw[l];
+  if (part && full < nl) acc += (uint64_t)(x[(long long)full * stride] & ((1u << part) - 1u)) * pw[full];
+  const uint64_t rr = (acc % t) * inv % t;
+  return (2 * rr > t) ? (int64_t)rr - (int64_t)t : (int64_t)rr;
+}
+
+__global__ __launch_bounds__(256) void compose_kernel(ComposeArgs a) {
+  const int jc = blockIdx.x * 256 + threadIdx.x;
+  const int z = blockIdx.y;  // 2 c + i
+  if (jc >= a.N) return;
+  const int c = z >> 1, i = z & 1;
+  const uint32_t* k = a.k + (long long)z * a.kstride + jc;
+  const uint32_t* d = a.d + (long long)(3 * c + i) * a.dstride + jc;
+  uint32_t* o = (i ? a.out1 : a.out0) + (long long)c * a.ostride + jc;
+  const int64_t corr = round_correction(k, a.N, a.LK, a.logP, a.scheme, a.t, a.invP, a.pw);
+  const int sl = a.logP >> 5, rs = a.logP & 31;
+  const uint32_t ext = corr < 0 ? 0xFFFFFFFFu : 0u;
+  uint64_t carry = 0;
+  uint32_t klo = sl < a.LK ? k[(long long)sl * a.N] : 0u;
+  const int topbits = a.logq - 32 * (a.L - 1);
+  for (int l = 0; l < a.L; ++l) {
+    const uint32_t khi = (sl + l + 1 < a.LK) ? k[(long long)(sl + l + 1) * a.N] : 0u;
+    const uint32_t ks = rs ? ((klo >> rs) | (khi << (32 - rs))) : klo;
+    klo = khi;
+    const uint32_t cl = l == 0 ? (uint32_t)corr : ext;
+    const uint64_t sum = (uint64_t)d[(long long)l * a.N] + ks + cl + carry;
+    uint32_t wv = (uint32_t)sum;
+    carry = sum >> 32;
+    if (l == a.L - 1 && topbits < 32) wv &= (1u << topbits) - 1u;
+    o[(long long)l * a.N] = wv;
+  }
+}
+
+__global__ __launch_bounds__(256) void rescale_kernel(RescaleArgs a) {
+  const int jc = blockIdx.x * 256 + threadIdx.x;
+  const int z = blockIdx.y;
+  if (jc >= a.N) return;
+  const int c = z >> 1, i = z & 1;
+  const int Lin = (a.logq + 31) >> 5;
+  const int newq = a.logq - a.bits;
+  const int Lout = (newq + 31) >> 5;
+  const uint32_t* x = (i ? a.in1 : a.in0) + (long long)c * a.istride + jc;
+  uint32_t* o = (i ? a.out1 : a.out0) + (long long)c * a.ostride + jc;
+  const int64_t corr = round_correction(x, a.N, Lin, a.bits, a.scheme, a.t, a.invB, a.pw);
+  const int sl = a.bits >> 5, rs = a.bits & 31;
+  const uint32_t ext = corr < 0 ? 0xFFFFFFFFu : 0u;
+  uint64_t carry = 0;
+  uint32_t xlo = sl < Lin ? x[(long long)sl * a.N] : 0u;
+  const int topbits = newq - 32 * (Lout - 1);
+  for (int l = 0; l < Lout; ++l) {
+    // reads of limbs >= sl + l precede the write of limb l (in place is safe)
+    const uint32_t xhi = (sl + l + 1 < Lin) ? x[(long long)(sl + l + 1) * a.N] : 0u;
+    const uint32_t xs = rs ? ((xlo >> rs) | (xhi << (32 - rs))) : xlo;
+    xlo = xhi;
+    const uint32_t cl = l == 0 ? (uint32_t)corr : ext;
+    const uint64_t sum = (uint64_t)xs + cl + carry;
+    uint32_t wv = (uint32_t)sum;
+    carry = sum >> 32;
+    if (l == Lout - 1 && topbits < 32) wv &= (1u << topbits) - 1u;
+    o[(long long)l * a.N] = wv;
+  }
+}
+
+hipError_t launch_compose(const ComposeArgs& a, int cnum, hipStream_t st) {
+  dim3 grid((a.N + 255) / 256, 2 * cnum);
+  hipLaunchKernelGGL(compose_kernel, grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_rescale(const RescaleArgs& a, int cnum, hipStream_t st) {
+  dim3 grid((a.N + 255) / 256, 2 * cnum);
+  hipLaunchKernelGGL(rescale_kernel, grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace fhe
