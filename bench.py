@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Throughput of homomorphic multiplication (tensor + relinearization + rescale) on one
+MI355X, at N = 2^16, logq = 1555, logP = 1555 (CKKS, rescale by 40 bits).
+
+One step = one HE-mult + relin + rescale of a CipherTensor of ``--cnum`` ciphertext
+pairs (default 4, the paper's CipherTensor size) through the C ABI.  Inputs are
+seeded synthetic ciphertexts and key, uniform in [0, 2^logq) / [0, 2^(logP+logq))
+(the distribution of real RLWE ciphertexts), resident in HBM before timing starts.
+
+Prints one JSON line: the metric, the per-op comparison (cnum = 1 per launch), the
+roofline of the dominant kernel from HIP events recorded on the launch stream over
+the timed region, standalone NTT throughput, and the CPU oracle's rate on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+LOGN, LOGQ, LOGP, BITS = 16, 1555, 1555, 40
+PEAK_PRODUCTS = 256 * 64 * 2.4e9  # 32x32-bit products per second: 256 CUs x 64 lanes x 2.4 GHz
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline():
+    """The oracle (never tuned) on 2 of the 6 exact ring products of one HE-mult at this
+    size; the HE-mult time is 4 x (tensor-size product) + 2 x (relin-size product)."""
+    import numpy as np
+    from oracle import limbs, ring
+    import synth
+    rng = np.random.default_rng(7)
+    N = 1 << LOGN
+    a = limbs.poly_from_limbs(synth.uniform_limbs(rng, LOGQ, N))
+    b = limbs.poly_from_limbs(synth.uniform_limbs(rng, LOGQ, N))
+    k = limbs.poly_from_limbs(synth.uniform_limbs(rng, LOGQ + LOGP, N))
+    t0 = time.perf_counter()
+    d2 = ring.negacyclic_kronecker(a, b, 1 << LOGQ)
+    t1 = time.perf_counter()
+    ring.negacyclic_kronecker(d2, k, 1 << (LOGQ + LOGP))
+    t2 = time.perf_counter()
+    est = 4 * (t1 - t0) + 2 * (t2 - t1)
+    return {
+        "value": 1.0 / est, "unit": "HE-mults/s", "cores": 1, "kind": "oracle",
+        "sample": (f"2 of the 6 exact negacyclic products of one N=2^16 logq=1555 logP=1555 HE-mult "
+                   f"(c1*c1' in {t1 - t0:.1f}s, d2*b' in {t2 - t1:.1f}s), scaled 4x and 2x; "
+                   f"single-threaded Python ints + decimal"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cnum", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip per-op and NTT legs")
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="also run one plain device copy of this size (HBM counter calibration)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: HE-mult requests shard across GPUs with no exchange, "
+              "and this build runs on a single MI355X; use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2607_05920_amd as fhe
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    N = 1 << LOGN
+    L = synth.nlimbs(LOGQ)
+    Lo = synth.nlimbs(LOGQ - BITS)
+    cnum = args.cnum
+
+    log("context + inputs")
+    ctx = fhe.Context(LOGQ, LOGP)
+    rk, rm, _, _ = synth.streams(3)
+    eb = synth.uniform_limbs(rk, LOGQ + LOGP, N)
+    ea = synth.uniform_limbs(rk, LOGQ + LOGP, N)
+    evk = fhe.EvalKey(ctx, fhe.CKKS, 0, LOGN, LOGQ, LOGP, eb, ea)
+    evk.prepare(LOGQ)
+    xs = [fhe.to_device(synth.uniform_limbs(rm, LOGQ, N, count=cnum)).reshape(-1) for _ in range(4)]
+    o0 = torch.empty(cnum * Lo * N, dtype=torch.int32, device=dev)
+    o1 = torch.empty(cnum * Lo * N, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(c=cnum, ins=xs, outs=(o0, o1)):
+        ctx.mul_relin_rescale(evk, LOGQ, BITS, ins[0], ins[1], ins[2], ins[3], outs[0], outs[1], cnum=c)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # ---- timed region (per-kernel HIP events recorded on the launch stream)
+    log(f"timed: {args.steps} steps of cnum={cnum}")
+    ctx.profile(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    value = cnum * args.steps / (ms / 1e3)
+
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    d = prof[dom]
+    achieved = d["work"] / (d["ms"] / 1e3)
+    total_kernel_ms = sum(v["ms"] for v in prof.values())
+    roofline = {
+        "bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_PRODUCTS / 1e12,
+        "unit": "T word-products/s (32x32-bit)", "frac": achieved / PEAK_PRODUCTS, "traffic": None,
+        "avg_launch_ms": d["ms"] / max(1, d["launches"]), "launches": d["launches"],
+        "share_of_kernel_time": d["ms"] / total_kernel_ms if total_kernel_ms else None,
+    }
+    kernels = {k: {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
+                   "T_products_per_s": (v["work"] / (v["ms"] / 1e3) / 1e12) if v["ms"] and v["work"] else None}
+               for k, v in prof.items()}
+
+    extras = {}
+    if not args.no_extras:
+        # per-op: the same work as cnum separate launches of one pair each
+        log("per-op leg")
+        singles = [[x[i * L * N:(i + 1) * L * N] for x in xs] for i in range(cnum)]
+        so = [(o0[i * Lo * N:(i + 1) * Lo * N], o1[i * Lo * N:(i + 1) * Lo * N]) for i in range(cnum)]
+        for i in range(cnum):
+            step(1, singles[i], so[i])
+        torch.cuda.synchronize()
+        steps1 = max(2, args.steps // 2)
+        ev0.record(stream)
+        for _ in range(steps1):
+            for i in range(cnum):
+                step(1, singles[i], so[i])
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        extras["per_op_he_mults_per_s"] = cnum * steps1 / (ev0.elapsed_time(ev1) / 1e3)
+        extras["batched_over_per_op"] = value / extras["per_op_he_mults_per_s"]
+        # standalone NTT throughput: 64 polynomials of this size lifted to the tensor primes
+        log("NTT leg")
+        Kt = ctx.primes_needed(LOGN, LOGQ, LOGQ, 2)
+        del xs, o0, o1, singles, so
+        torch.cuda.empty_cache()
+        polys = fhe.to_device(synth.uniform_limbs(rm, LOGQ, N, count=64)).reshape(-1)
+        res = torch.empty(64 * Kt * N, dtype=torch.int32, device=dev)
+        ctx.lift(LOGN, L, Kt, polys, res, count=64)
+        ctx.ntt(LOGN, Kt, res, count=64)
+        ctx.ntt(LOGN, Kt, res, count=64, inverse=True)
+        torch.cuda.synchronize()
+        for inv in (False, True):
+            reps = 3
+            ev0.record(stream)
+            for _ in range(reps):
+                ctx.ntt(LOGN, Kt, res, count=64, inverse=inv)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            extras["ntt_inv_per_s" if inv else "ntt_fwd_per_s"] = reps * 64 * Kt / (ev0.elapsed_time(ev1) / 1e3)
+        extras["ntt_transforms_per_call"] = 64 * Kt
+        del polys, res
+        torch.cuda.empty_cache()
+
+    if args.copy_calib_mb:
+        nb = args.copy_calib_mb << 20
+        src = torch.empty(nb // 4, dtype=torch.int32, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        extras["copy_calib_bytes"] = nb
+
+    out = {
+        "metric": "HE-mults/s (N=2^16, logQ~1555) batched vs per-op; p50/p99 serve latency",
+        "value": value, "unit": "HE-mults/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"CKKS HE-mult + relinearization + rescale by {BITS} bits, N=2^16, logq=1555, "
+                               f"logP=1555, CipherTensor of {cnum} ciphertext pairs per step",
+                   "logN": LOGN, "logq": LOGQ, "logP": LOGP, "rescale_bits": BITS, "cnum": cnum,
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "kernels": kernels,
+        "wall_s": wall,
+        **extras,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)")
+        out["cpu_baseline"] = cpu_baseline()
+    evk.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -67,6 +67,10 @@ typedef struct fhe_evk fhe_evk;
 /* Text for a status code (static storage). */
 const char* fhe_strerror(int status);
 
+/* Text naming the last failing HIP call made by the library on the calling host
+ * thread, with the runtime's message (thread-local storage; empty if none). */
+const char* fhe_error_detail(void);
+
 /* Create a context on HIP device `device` able to hold ciphertexts with
  * logq <= logQ_max and keys with logP <= logP_max.  Builds on the device the
  * tables of Section 5.2 (twiddles psi^j and their inverses, n^-1, the limb
@@ -84,6 +88,19 @@ void fhe_ctx_destroy(fhe_ctx* ctx);
 
 /* Return and clear the sticky device error of the context. */
 int fhe_ctx_reset_error(fhe_ctx* ctx);
+
+/* Instrumentation.  fhe_ctx_profile(ctx, 1) starts recording a pair of HIP events
+ * on the launch stream around every kernel the context launches (and clears the
+ * totals); fhe_ctx_profile(ctx, 0) stops.  fhe_ctx_profile_read waits for the
+ * recorded events and returns, for one kernel class, the summed event time (ms),
+ * the summed algorithmic work (32x32-bit word products: Garner digits and limb
+ * sums, lift limb products, one constant product per NTT butterfly, one per
+ * pointwise product) and the number of launches (host outputs).  Kernel classes:
+ * 0 lift, 1 forward NTT column pass, 2 forward NTT row pass, 3 inverse NTT row
+ * pass, 4 inverse NTT column pass, 5 pointwise, 6 Garner, 7 relinearization
+ * compose, 8 rescale.  Errors: FHE_E_INVAL, FHE_E_STATE (not recording). */
+int fhe_ctx_profile(fhe_ctx* ctx, int enable);
+int fhe_ctx_profile_read(fhe_ctx* ctx, int kernel, double* ms, double* work, long long* launches);
 
 /* Number of primes in the context's table. */
 int fhe_prime_count(const fhe_ctx* ctx, int* count);

@@ -30,9 +30,13 @@ _I = ctypes.c_int
 _U = ctypes.c_uint32
 EXPORTS = {
     "fhe_strerror": (ctypes.c_char_p, [_I]),
+    "fhe_error_detail": (ctypes.c_char_p, []),
     "fhe_ctx_create": (_I, [_I, _I, _I, ctypes.POINTER(_P)]),
     "fhe_ctx_destroy": (None, [_P]),
     "fhe_ctx_reset_error": (_I, [_P]),
+    "fhe_ctx_profile": (_I, [_P, _I]),
+    "fhe_ctx_profile_read": (_I, [_P, _I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_longlong)]),
     "fhe_prime_count": (_I, [_P, ctypes.POINTER(_I)]),
     "fhe_prime_info": (_I, [_P, _I, ctypes.POINTER(_U), ctypes.POINTER(_U)]),
     "fhe_primes_needed": (_I, [_P, _I, _I, _I, _I, ctypes.POINTER(_I)]),
@@ -62,10 +66,16 @@ _lib = None
 
 
 def load_library(path: str = LIB_PATH):
-    """Load the HIP library (no GPU needed to load it)."""
+    """Load the HIP library (no GPU needed to load it).
+
+    torch is imported first so that the library binds to the HIP runtime torch
+    already carries (same soname): device pointers and stream handles from torch
+    are then valid in the library.  Loading the library first would bring a second
+    runtime into the process, which does not see torch's device state."""
     global _lib
     if _lib is not None:
         return _lib
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise LibraryMissing(f"{path} is not built; run paper_2607_05920_amd/build.py")
     lib = ctypes.CDLL(path)
@@ -79,7 +89,11 @@ def load_library(path: str = LIB_PATH):
 
 def _check(fn: str, status: int):
     if status != 0:
-        raise FheError(fn, status)
+        err = FheError(fn, status)
+        detail = _lib.fhe_error_detail() if _lib is not None else b""
+        if detail:
+            err.args = (f"{err.args[0]} [{detail.decode(errors='replace')}]",)
+        raise err
 
 
 def _ptr(t) -> int:
@@ -132,6 +146,21 @@ class Context:
     @property
     def handle(self):
         return self._h
+
+    KERNELS = ["lift", "ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "pointwise", "garner",
+               "compose", "rescale"]
+
+    def profile(self, enable: bool):
+        _check("fhe_ctx_profile", load_library().fhe_ctx_profile(self._h, int(enable)))
+
+    def profile_read(self) -> dict:
+        out = {}
+        for i, name in enumerate(self.KERNELS):
+            ms, work, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_longlong()
+            _check("fhe_ctx_profile_read", load_library().fhe_ctx_profile_read(
+                self._h, i, ctypes.byref(ms), ctypes.byref(work), ctypes.byref(n)))
+            out[name] = {"ms": ms.value, "work": work.value, "launches": n.value}
+        return out
 
     def prime_count(self) -> int:
         n = ctypes.c_int()

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -15,6 +16,13 @@
 using namespace fhe;
 
 namespace {
+
+// Text of the last failing HIP call on this host thread (see fhe_error_detail).
+thread_local char g_detail[256] = "";
+
+void note(const char* what, hipError_t e) {
+  snprintf(g_detail, sizeof g_detail, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
 
 // ---------------------------------------------------------------- host number theory
 
@@ -102,8 +110,13 @@ struct Big {
 template <typename T>
 hipError_t upload(T** dptr, const std::vector<T>& h) {
   hipError_t e = hipMalloc((void**)dptr, h.size() * sizeof(T));
-  if (e != hipSuccess) return e;
-  return hipMemcpy(*dptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    note("hipMalloc of a constant table", e);
+    return e;
+  }
+  e = hipMemcpy(*dptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (e != hipSuccess) note("hipMemcpy of a constant table", e);
+  return e;
 }
 
 int ceil_log2(int x) {
@@ -114,6 +127,7 @@ int ceil_log2(int x) {
 
 int status_of(hipError_t e) {
   if (e == hipSuccess) return FHE_OK;
+  note("HIP call", e);
   if (e == hipErrorOutOfMemory) return FHE_E_NOMEM;
   return FHE_E_DEVICE;
 }
@@ -125,6 +139,65 @@ int status_of(hipError_t e) {
 struct Workspace {
   void* ptr = nullptr;
   size_t bytes = 0;
+};
+
+// Per-kernel HIP-event timing (instrumentation; off unless enabled).
+struct Recorder : EventRecorder {
+  struct Pending {
+    int kid;
+    hipEvent_t a, b;
+    double work;
+  };
+  std::vector<hipEvent_t> pool;
+  std::vector<Pending> pending;
+  std::vector<std::pair<int, hipEvent_t>> open;
+  double ms[KID_COUNT] = {}, work[KID_COUNT] = {};
+  long long launches[KID_COUNT] = {};
+  hipEvent_t take() {
+    if (pool.empty()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      return e;
+    }
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  void begin(int kid, hipStream_t s) override {
+    hipEvent_t e = take();
+    if (e) hipEventRecord(e, s);
+    open.emplace_back(kid, e);
+  }
+  void end(int kid, hipStream_t s, double w) override {
+    hipEvent_t a = open.back().second;
+    open.pop_back();
+    hipEvent_t b = take();
+    if (b) hipEventRecord(b, s);
+    pending.push_back({kid, a, b, w});
+  }
+  void collect() {
+    for (auto& p : pending) {
+      if (p.a && p.b && hipEventSynchronize(p.b) == hipSuccess) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+          ms[p.kid] += t;
+          work[p.kid] += p.work;
+          launches[p.kid] += 1;
+        }
+      }
+      if (p.a) pool.push_back(p.a);
+      if (p.b) pool.push_back(p.b);
+    }
+    pending.clear();
+  }
+  void clear() {
+    collect();
+    for (int k = 0; k < KID_COUNT; ++k) ms[k] = work[k] = 0, launches[k] = 0;
+  }
+  ~Recorder() override {
+    collect();
+    for (auto e : pool) hipEventDestroy(e);
+  }
 };
 
 struct fhe_ctx {
@@ -153,6 +226,7 @@ struct fhe_ctx {
   std::map<std::pair<void*, int>, Workspace> ws;  // (stream, slot)
   std::recursive_mutex mu;
   int sticky = FHE_OK;
+  Recorder* rec = nullptr;  // non-null while profiling is on
 };
 
 struct fhe_evk {
@@ -165,6 +239,12 @@ struct fhe_evk {
 };
 
 namespace {
+
+// Installs the context's recorder (if profiling) for the duration of one call.
+struct RecGuard {
+  explicit RecGuard(fhe_ctx* c) { set_recorder(c->rec); }
+  ~RecGuard() { set_recorder(nullptr); }
+};
 
 int set_sticky(fhe_ctx* c, hipError_t e) {
   int st = status_of(e);
@@ -279,6 +359,7 @@ GarnerArgs garner_args(fhe_ctx* c, const uint32_t* res, int per_group, long long
   a.Ct = c->Ct;
   a.CS = c->CS;
   a.kstart = c->kstart;
+  a.mbits = c->mbits.data();
   return a;
 }
 
@@ -481,6 +562,8 @@ bool valid_t(int scheme, uint32_t t) {
 
 extern "C" {
 
+const char* fhe_error_detail(void) { return g_detail; }
+
 const char* fhe_strerror(int status) {
   switch (status) {
     case FHE_OK: return "ok";
@@ -498,7 +581,10 @@ int fhe_ctx_create(int device, int logQ_max, int logP_max, fhe_ctx** out) {
   if (!out || logQ_max < 1 || logP_max < 1 || logQ_max > 8192 || logP_max > 8192) return FHE_E_INVAL;
   *out = nullptr;
   hipError_t e = hipSetDevice(device);
-  if (e != hipSuccess) return FHE_E_DEVICE;
+  if (e != hipSuccess) {
+    note("hipSetDevice", e);
+    return FHE_E_DEVICE;
+  }
   fhe_ctx* c = new (std::nothrow) fhe_ctx();
   if (!c) return FHE_E_NOMEM;
   c->device = device;
@@ -648,8 +734,9 @@ int fhe_ctx_create(int device, int logQ_max, int logP_max, fhe_ctx** out) {
     }
   }
   if (e != hipSuccess) {
+    const int st = e == hipErrorOutOfMemory ? FHE_E_NOMEM : FHE_E_DEVICE;
     fhe_ctx_destroy(c);
-    return status_of(e);
+    return st;
   }
   *out = c;
   return FHE_OK;
@@ -670,6 +757,7 @@ void fhe_ctx_destroy(fhe_ctx* c) {
   for (auto& kv : c->pw) hipFree(kv.second);
   for (auto& kv : c->ws)
     if (kv.second.ptr) hipFree(kv.second.ptr);
+  delete c->rec;
   delete c;
 }
 
@@ -680,6 +768,32 @@ int fhe_ctx_reset_error(fhe_ctx* c) {
   c->sticky = FHE_OK;
   (void)hipGetLastError();
   return s;
+}
+
+int fhe_ctx_profile(fhe_ctx* c, int enable) {
+  if (!c || (enable != 0 && enable != 1)) return FHE_E_INVAL;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (enable) {
+    if (!c->rec) c->rec = new (std::nothrow) Recorder();
+    if (!c->rec) return FHE_E_NOMEM;
+    c->rec->clear();
+  } else if (c->rec) {
+    c->rec->collect();
+    delete c->rec;
+    c->rec = nullptr;
+  }
+  return FHE_OK;
+}
+
+int fhe_ctx_profile_read(fhe_ctx* c, int kernel, double* ms, double* work, long long* launches) {
+  if (!c || !ms || !work || !launches || kernel < 0 || kernel >= KID_COUNT) return FHE_E_INVAL;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (!c->rec) return FHE_E_STATE;
+  c->rec->collect();
+  *ms = c->rec->ms[kernel];
+  *work = c->rec->work[kernel];
+  *launches = c->rec->launches[kernel];
+  return FHE_OK;
 }
 
 int fhe_prime_count(const fhe_ctx* c, int* count) {
@@ -712,6 +826,7 @@ int fhe_lift(fhe_ctx* c, int logN, int L, int nprimes, const uint32_t* limbs, ui
   std::lock_guard<std::recursive_mutex> g(c->mu);
   if (c->sticky != FHE_OK) return c->sticky;
   hipSetDevice(c->device);
+  RecGuard rg(c);
   const int N = 1 << logN;
   hipError_t e = launch_lift(lift_args(c, limbs, res, (long long)L * N, (long long)nprimes * N, N, L, nprimes),
                              count, (hipStream_t)stream);
@@ -724,6 +839,7 @@ int fhe_ntt(fhe_ctx* c, int logN, int nprimes, int inverse, uint32_t* data, int 
   std::lock_guard<std::recursive_mutex> g(c->mu);
   if (c->sticky != FHE_OK) return c->sticky;
   hipSetDevice(c->device);
+  RecGuard rg(c);
   const long long N = 1LL << logN;
   hipError_t e = launch_ntt(ntt_args(c, data, logN, nprimes, nprimes, (long long)nprimes * N, inverse != 0,
                                      c->nscale[logN]),
@@ -739,6 +855,7 @@ int fhe_ring_mul(fhe_ctx* c, int logN, int logq, const uint32_t* a, const uint32
   std::lock_guard<std::recursive_mutex> g(c->mu);
   if (c->sticky != FHE_OK) return c->sticky;
   hipSetDevice(c->device);
+  RecGuard rg(c);
   hipStream_t st = (hipStream_t)stream;
   const int N = 1 << logN;
   const int L = (logq + 31) / 32;
@@ -800,6 +917,7 @@ int fhe_evk_prepare(fhe_evk* k, int logq, void* stream) {
   std::lock_guard<std::recursive_mutex> g(c->mu);
   if (c->sticky != FHE_OK) return c->sticky;
   hipSetDevice(c->device);
+  RecGuard rg(c);
   return evk_prepare_locked(k, logq, (hipStream_t)stream);
 }
 
@@ -823,6 +941,7 @@ int fhe_mul_relin(fhe_ctx* c, fhe_evk* k, int logN, int logq, const uint32_t* x0
   std::lock_guard<std::recursive_mutex> g(c->mu);
   if (c->sticky != FHE_OK) return c->sticky;
   hipSetDevice(c->device);
+  RecGuard rg(c);
   const long long ostride = (long long)((logq + 31) / 32) << logN;
   return mul_relin_locked(c, k, logN, logq, x0, x1, y0, y1, out0, out1, ostride, cnum, (hipStream_t)stream);
 }
@@ -840,6 +959,7 @@ int fhe_rescale(fhe_ctx* c, int scheme, uint32_t t, int logN, int logq, int bits
   std::lock_guard<std::recursive_mutex> g(c->mu);
   if (c->sticky != FHE_OK) return c->sticky;
   hipSetDevice(c->device);
+  RecGuard rg(c);
   return rescale_locked(c, scheme, t, logN, logq, bits, in0, in1, (long long)L << logN, out0, out1,
                         (long long)Lo << logN, cnum, (hipStream_t)stream);
 }
@@ -856,6 +976,7 @@ int fhe_mul_relin_rescale(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, 
   std::lock_guard<std::recursive_mutex> g(c->mu);
   if (c->sticky != FHE_OK) return c->sticky;
   hipSetDevice(c->device);
+  RecGuard rg(c);
   hipStream_t st = (hipStream_t)stream;
   const long long polyw = (long long)((logq + 31) / 32) << logN;
   // relinearized ciphertexts go to a scratch area of their own, then rescale into out

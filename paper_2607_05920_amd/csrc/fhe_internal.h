@@ -63,6 +63,7 @@ struct GarnerArgs {
   const uint32_t* Ct;  // Ct[k * CS + m] = radix-2^26 digit m of M_k
   int CS;
   const int* kstart;   // [m] = min k with M_k >= 2^(26 m)
+  const int* mbits;    // host: bit length of M_k (work accounting only)
 };
 
 struct ComposeArgs {
@@ -88,6 +89,29 @@ struct RescaleArgs {
   uint32_t t, invB;  // BGV: t and 2^-bits mod t
   const uint32_t* pw;
 };
+
+// Optional per-kernel timing: when a recorder is installed, every launcher records
+// a HIP event pair around its kernel on the launch stream.
+enum KernelId {
+  KID_LIFT = 0,
+  KID_NTT_FWD_COLS,
+  KID_NTT_FWD_ROWS,
+  KID_NTT_INV_ROWS,
+  KID_NTT_INV_COLS,
+  KID_POINTWISE,
+  KID_GARNER,
+  KID_COMPOSE,
+  KID_RESCALE,
+  KID_COUNT
+};
+
+struct EventRecorder {
+  virtual void begin(int kid, hipStream_t s) = 0;
+  virtual void end(int kid, hipStream_t s, double work) = 0;
+  virtual ~EventRecorder() {}
+};
+
+void set_recorder(EventRecorder* r);  // host thread-local
 
 hipError_t launch_ntt(const NttArgs& a, int ntransforms, bool inverse, hipStream_t s);
 hipError_t launch_lift(const LiftArgs& a, int npoly, hipStream_t s);

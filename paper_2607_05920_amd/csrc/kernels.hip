@@ -1,9 +1,28 @@
 // gfx950 kernels for the non-RNS HE-mult pipeline:
 //   lift (limbs -> residues), negacyclic NTT / iNTT, pointwise products,
 //   Garner reconstruction (residues -> limbs), relinearization compose, rescale.
+#include <algorithm>
+
 #include "fhe_internal.h"
 
 namespace fhe {
+
+static thread_local EventRecorder* g_rec = nullptr;
+void set_recorder(EventRecorder* r) { g_rec = r; }
+
+// Brackets one kernel launch with the recorder's events; `work` is the kernel's
+// algorithmic 32x32-bit word-product count (0 when not tracked).
+struct Bracket {
+  int kid;
+  hipStream_t s;
+  double work;
+  Bracket(int k, hipStream_t st, double w) : kid(k), s(st), work(w) {
+    if (g_rec) g_rec->begin(kid, s);
+  }
+  ~Bracket() {
+    if (g_rec) g_rec->end(kid, s, work);
+  }
+};
 
 // ============================================================================ NTT
 //
@@ -178,6 +197,9 @@ static hipError_t ntt_pass(const NttArgs& a, int ntr, hipStream_t st) {
   constexpr int NSUB = 256 / (n / 16);
   const int nsub_total = (1 << a.logN) / n;
   dim3 grid((nsub_total + NSUB - 1) / NSUB, ntr);
+  // algorithmic work: (N / 2) S butterflies per transform, one constant product each
+  Bracket br(INV ? (ROWS ? KID_NTT_INV_ROWS : KID_NTT_INV_COLS) : (ROWS ? KID_NTT_FWD_ROWS : KID_NTT_FWD_COLS), st,
+             (double)ntr * (double)((1 << a.logN) / 2) * S);
   hipLaunchKernelGGL((ntt_pass_kernel<S, INV, ROWS>), grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
@@ -262,6 +284,8 @@ __global__ __launch_bounds__(256) void lift_kernel(LiftArgs a) {
 hipError_t launch_lift(const LiftArgs& a, int npoly, hipStream_t st) {
   if (npoly <= 0) return hipSuccess;
   dim3 grid((a.K + kLiftPrimes - 1) / kLiftPrimes, (a.N + 255) / 256, npoly);
+  // algorithmic work: L limb-constant products per (coefficient, prime)
+  Bracket br(KID_LIFT, st, (double)npoly * a.N * a.K * a.L);
   hipLaunchKernelGGL((lift_kernel<kLiftPrimes>), grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
@@ -319,18 +343,21 @@ __global__ __launch_bounds__(256) void ring_pointwise_kernel(PointwiseArgs a) {
 
 hipError_t launch_tensor_pointwise(const PointwiseArgs& a, int cnum, hipStream_t st) {
   dim3 grid((a.N + 255) / 256, a.K, cnum);
+  Bracket br(KID_POINTWISE, st, 4.0 * cnum * a.K * a.N);
   hipLaunchKernelGGL(tensor_pointwise_kernel, grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_relin_pointwise(const PointwiseArgs& a, int cnum, hipStream_t st) {
   dim3 grid((a.N + 255) / 256, a.K, cnum);
+  Bracket br(KID_POINTWISE, st, 2.0 * cnum * a.K * a.N);
   hipLaunchKernelGGL(relin_pointwise_kernel, grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_ring_pointwise(const PointwiseArgs& a, int cnum, hipStream_t st) {
   dim3 grid((a.N + 255) / 256, a.K, cnum);
+  Bracket br(KID_POINTWISE, st, 1.0 * cnum * a.K * a.N);
   hipLaunchKernelGGL(ring_pointwise_kernel, grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
@@ -458,10 +485,20 @@ __global__ __launch_bounds__(64) void garner_kernel(GarnerArgs a) {
   }
 }
 
+// Word products Garner's method needs per coefficient: K(K-1)/2 for the
+// mixed-radix digits, plus one per limb of each M_k (up to Lout limbs) for the
+// limb-form sum.  mbits[k] is the bit length of M_k.
+static double garner_products(int K, int Lout, const int* mbits) {
+  double w = 0.5 * K * (K - 1);
+  for (int k = 0; k < K; ++k) w += std::min(Lout, (mbits[k] + 31) / 32);
+  return w;
+}
+
 hipError_t launch_garner(const GarnerArgs& a, int npoly, hipStream_t st) {
   if (npoly <= 0) return hipSuccess;
   dim3 grid((a.N + 63) / 64, npoly);
   const size_t lds = (size_t)a.K * 64 * sizeof(uint32_t);
+  Bracket br(KID_GARNER, st, (double)npoly * a.N * garner_products(a.K, a.Lout, a.mbits));
   hipLaunchKernelGGL(garner_kernel, grid, dim3(64), lds, st, a);
   return hipGetLastError();
 }
@@ -552,12 +589,14 @@ __global__ __launch_bounds__(256) void rescale_kernel(RescaleArgs a) {
 
 hipError_t launch_compose(const ComposeArgs& a, int cnum, hipStream_t st) {
   dim3 grid((a.N + 255) / 256, 2 * cnum);
+  Bracket br(KID_COMPOSE, st, 0.0);
   hipLaunchKernelGGL(compose_kernel, grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_rescale(const RescaleArgs& a, int cnum, hipStream_t st) {
   dim3 grid((a.N + 255) / 256, 2 * cnum);
+  Bracket br(KID_RESCALE, st, 0.0);
   hipLaunchKernelGGL(rescale_kernel, grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
