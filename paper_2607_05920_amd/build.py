@@ -22,6 +22,8 @@ def build(verbose: bool = False) -> str:
         hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
         # packed FP32 instructions are kept out of every code object
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        # the register-resident Garner kernels are fully unrolled straight-line code
+        "-mllvm", "-pragma-unroll-threshold=1000000",
         "-Wno-unused-result", "-Wno-unused-value", "-Wno-unused-command-line-argument",
         "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
         "-o", LIB + ".tmp",

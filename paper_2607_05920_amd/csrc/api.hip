@@ -363,6 +363,15 @@ GarnerArgs garner_args(fhe_ctx* c, const uint32_t* res, int per_group, long long
   return a;
 }
 
+// Garner launch with its digit scratch (slot 2 of the stream's scratch memory).
+hipError_t run_garner(fhe_ctx* c, void* stream, GarnerArgs a, int npoly) {
+  hipError_t e = hipSuccess;
+  const size_t words = (size_t)npoly * ((a.N + 63) / 64) * garner_wave_words(a.K);
+  a.dig = (uint32_t*)scratch(c, stream, 2, words * 4, &e);
+  if (!a.dig) return e;
+  return launch_garner(a, npoly, (hipStream_t)stream);
+}
+
 // Build the relinearization key's NTT form for level logq.
 int evk_prepare_locked(fhe_evk* k, int logq, hipStream_t stream) {
   fhe_ctx* c = k->ctx;
@@ -470,8 +479,8 @@ int mul_relin_locked(fhe_ctx* c, fhe_evk* k, int logN, int logq, const uint32_t*
                    true, st);
   // 5. Garner -> d0, d1, d2 mod 2^logq: Dl[c][i][L][N]
   if (e == hipSuccess)
-    e = launch_garner(garner_args(c, Rt, 3, 4LL * Kt * NN, (long long)Kt * NN, Dl, polyw, N, Kt, logq, owt),
-                      cnum * 3, st);
+    e = run_garner(c, st, garner_args(c, Rt, 3, 4LL * Kt * NN, (long long)Kt * NN, Dl, polyw, N, Kt, logq, owt),
+                   cnum * 3);
   // 6. lift d2 onto Kr primes
   if (e == hipSuccess)
     e = launch_lift(lift_args(c, Dl + 2 * polyw, Rr, 3 * polyw, (long long)Kr * NN, N, L, Kr), cnum, st);
@@ -497,9 +506,10 @@ int mul_relin_locked(fhe_ctx* c, fhe_evk* k, int logN, int logq, const uint32_t*
                    true, st);
   // 10. Garner -> k0, k1 mod 2^(logP + logq)
   if (e == hipSuccess)
-    e = launch_garner(garner_args(c, Rk, 2, 2LL * Kr * NN, (long long)Kr * NN, Kl, (long long)LK * NN, N, Kr,
-                                  logP + logq, owr),
-                      cnum * 2, st);
+    e = run_garner(c, st,
+                   garner_args(c, Rk, 2, 2LL * Kr * NN, (long long)Kr * NN, Kl, (long long)LK * NN, N, Kr,
+                               logP + logq, owr),
+                   cnum * 2);
   // 11. c_i = [d_i + R(k_i)]_(2^logq)
   if (e == hipSuccess) {
     ComposeArgs ca{};
@@ -608,6 +618,10 @@ int fhe_ctx_create(int device, int logQ_max, int logP_max, fhe_ctx** out) {
   }
   const int K = (int)c->q.size();
   c->K = K;
+  if (K + kGarnerBlock + kLiftPrimes > kGarnerGS) {
+    delete c;
+    return FHE_E_RANGE;
+  }
   c->Kpad = K + kGarnerBlock + kLiftPrimes;
   const int Kpad = c->Kpad;
   // psi: g^((q-1)/2^17) for the smallest g with order exactly 2^17
@@ -635,7 +649,7 @@ int fhe_ctx_create(int device, int logQ_max, int logP_max, fhe_ctx** out) {
   // I_k = [M_k^-1]_(q_k); mk[j][k] = [M_j]_(q_k)
   c->Ik.assign(K, 1);
   std::vector<uint32_t> Mmod(K, 1);  // running [M_j]_(q_k) for the current j
-  c->GS = Kpad;
+  c->GS = kGarnerGS;
   std::vector<uint32_t> Gt((size_t)K * c->GS, 0);
   for (int j = 0; j < K; ++j) {
     for (int k = j + 1; k < K; ++k) {
@@ -660,15 +674,37 @@ int fhe_ctx_create(int device, int logQ_max, int logP_max, fhe_ctx** out) {
   // column digits of M_k (radix 2^26) and first contributing k per column
   const int outbits_max = logP_max + logQ_max;
   c->Dmax = (outbits_max + kHornerDigitBits - 1) / kHornerDigitBits;
-  c->CS = c->Dmax + kHornerBlock;
-  std::vector<uint32_t> Ct((size_t)Kpad * c->CS, 0);
+  std::vector<uint32_t> Csq((size_t)Kpad * (c->Dmax + kHornerBlock), 0);
+  const int CW = c->Dmax + kHornerBlock;
   {
     Big Mk;
     for (int k = 0; k < K; ++k) {
-      for (int m = 0; m < c->Dmax; ++m) Ct[(size_t)k * c->CS + m] = Mk.bits_at(kHornerDigitBits * m, kHornerDigitBits);
+      for (int m = 0; m < c->Dmax; ++m) Csq[(size_t)k * CW + m] = Mk.bits_at(kHornerDigitBits * m, kHornerDigitBits);
       Mk.mul_small(c->q[k]);
     }
   }
+  // Both Garner tables are stored in the order the kernel consumes them, one 64-byte
+  // row of 16 constants after another, so scalar-cache lines are read sequentially
+  // and used whole.  Digit block b (digits 16b .. 16b+15): rows j = 0 .. 16b+15 of
+  // the 16 columns k = 16b .. 16b+15, segment at word 256 b (b + 1) / 2.  Column block
+  // c (radix-2^26 columns 16c .. 16c+15): rows k = 0 .. Kpad-1, segment at word
+  // c Kpad 16.
+  const int NB = (K + kGarnerBlock - 1) / kGarnerBlock;
+  std::vector<uint32_t> Gb((size_t)256 * NB * (NB + 1) / 2, 0);
+  for (int b = 0; b < NB; ++b) {
+    const size_t off = (size_t)256 * b * (b + 1) / 2;
+    for (int j = 0; j < 16 * b + 16; ++j)
+      for (int u = 0; u < 16; ++u) {
+        const int k = 16 * b + u;
+        if (j < K && k < K && j < k) Gb[off + (size_t)16 * j + u] = Gt[(size_t)j * c->GS + k];
+      }
+  }
+  const int NC = (c->Dmax + kHornerBlock - 1) / kHornerBlock;
+  std::vector<uint32_t> Cb((size_t)NC * Kpad * 16, 0);
+  for (int cb = 0; cb < NC; ++cb)
+    for (int k = 0; k < Kpad; ++k)
+      for (int m = 0; m < 16; ++m) Cb[((size_t)cb * Kpad + k) * 16 + m] = Csq[(size_t)k * CW + 16 * cb + m];
+  c->CS = Kpad * 16;  // words per column-block segment
   std::vector<int> kstart(c->Dmax + kHornerBlock, K);
   for (int m = 0; m < (int)kstart.size(); ++m)
     for (int k = 0; k < K; ++k)
@@ -726,7 +762,7 @@ int fhe_ctx_create(int device, int logQ_max, int logP_max, fhe_ctx** out) {
   // upload
   if ((e = upload(&c->pc, pc)) == hipSuccess && (e = upload(&c->tw, tw)) == hipSuccess &&
       (e = upload(&c->itw, itw)) == hipSuccess && (e = upload(&c->liftT, T)) == hipSuccess &&
-      (e = upload(&c->Gt, Gt)) == hipSuccess && (e = upload(&c->Ct, Ct)) == hipSuccess &&
+      (e = upload(&c->Gt, Gb)) == hipSuccess && (e = upload(&c->Ct, Cb)) == hipSuccess &&
       (e = upload(&c->kstart, kstart)) == hipSuccess) {
     for (int lg = FHE_LOGN_MIN; lg <= kLogNMax && e == hipSuccess; ++lg) {
       e = upload(&c->nscale[lg], ns[lg]);
@@ -885,7 +921,7 @@ int fhe_ring_mul(fhe_ctx* c, int logN, int logq, const uint32_t* a, const uint32
   }
   if (e == hipSuccess) e = launch_ntt(ntt_args(c, Ra, logN, K, K, KN, true, c->gscale[logN]), cnum * K, true, st);
   if (e == hipSuccess)
-    e = launch_garner(garner_args(c, Ra, 1, KN, 0, out, (long long)L * N, N, K, logq, ow), cnum, st);
+    e = run_garner(c, stream, garner_args(c, Ra, 1, KN, 0, out, (long long)L * N, N, K, logq, ow), cnum);
   return set_sticky(c, e);
 }
 

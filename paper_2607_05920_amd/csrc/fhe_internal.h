@@ -15,6 +15,7 @@ constexpr int kHornerDigitBits = 26;  // Garner output radix
 constexpr int kGarnerBlock = 16;      // digits finalized per block (accumulators)
 constexpr int kHornerBlock = 16;      // output columns per block
 constexpr int kLiftPrimes = 16;       // primes per lift thread
+constexpr int kGarnerGS = 256;        // row stride of the host's square digit table (K <= 224)
 
 // Negacyclic NTT over a set of transforms.  Transform tr (blockIdx.y) lives at
 // data + (tr / per_group) * group_stride + (tr % per_group) * N and uses prime
@@ -57,14 +58,19 @@ struct GarnerArgs {
   long long ostride;
   int N, K, outbits, Lout;
   const PrimeC* pc;
-  const uint32_t* Gt;  // Gt[j * GS + k] = [M_j I_k 2^32]_(q_k)
-  int GS;
+  const uint32_t* Gt;  // digit block b: 16-word rows j of [M_j I_k 2^32]_(q_k), k = 16b..16b+15,
+  int GS;              //   at word 256 b (b + 1) / 2 (GS unused)
   const uint32_t* Ow;  // [k] = [2^e I_k]_(q_k)
-  const uint32_t* Ct;  // Ct[k * CS + m] = radix-2^26 digit m of M_k
-  int CS;
+  const uint32_t* Ct;  // column block c: 16-word rows k of radix-2^26 digits 16c.. of M_k,
+  int CS;              //   at word c CS
   const int* kstart;   // [m] = min k with M_k >= 2^(26 m)
   const int* mbits;    // host: bit length of M_k (work accounting only)
+  uint32_t* dig;       // digit scratch: wave w's region at dig + w * garner_wave_words(K)
 };
+
+// Words of digit scratch per wave of 64 coefficients: the digits padded to the
+// 16-digit block plus one pair read ahead.
+__host__ __device__ inline long long garner_wave_words(int K) { return (long long)((K + 15) / 16 * 16 + 2) * 64; }
 
 struct ComposeArgs {
   const uint32_t* k;  // poly z (= 2 c + i): k + z * kstride, uint32[LK][N]

@@ -2,6 +2,7 @@
 //   lift (limbs -> residues), negacyclic NTT / iNTT, pointwise products,
 //   Garner reconstruction (residues -> limbs), relinearization compose, rescale.
 #include <algorithm>
+#include <utility>
 
 #include "fhe_internal.h"
 
@@ -385,10 +386,110 @@ hipError_t launch_ring_pointwise(const PointwiseArgs& a, int cnum, hipStream_t s
 // digits of M_k (each product < 2^56, so a column of up to 255 terms fits 64 bits),
 // then carried and re-packed into 32-bit limbs.
 
+// Tables are read through the constant address space so the compiler may treat
+// them as invariant and keep wave-uniform loads scalar.
+typedef __attribute__((address_space(4))) const uint32_t cu32;
+typedef __attribute__((address_space(4))) const PrimeC cprime;
+
+#define FHE_FENCE() __builtin_amdgcn_sched_barrier(0)
+
+__device__ __forceinline__ PrimeC load_prime(cprime* p) {
+  PrimeC r;
+  r.q = p->q;
+  r.qneg = p->qneg;
+  r.c32 = p->c32;
+  r.two_q = p->two_q;
+  return r;
+}
+
+struct Row16 {
+  uint32_t c[16];
+};
+
+__device__ __forceinline__ Row16 load_row(cu32* p) {
+  Row16 r;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) r.c[u] = p[u];
+  return r;
+}
+
+// Digits of the wave's 64 coefficients, two per lane word pair: digit k of lane l
+// at vd[(k / 2) * 128 + 2 l + (k % 2)], so one ds_read_b64 returns digits 2p, 2p+1.
+__device__ __forceinline__ uint2 load_pair(const uint32_t* vd, int pair, int lane) {
+  return *(const uint2*)(vd + pair * 128 + 2 * lane);
+}
+
+// Copies a wave-uniform value into a vector register (keeps it out of the scalar
+// register budget, which the pipelined constant rows need).
+__device__ __forceinline__ uint32_t to_vgpr(uint32_t x) {
+  uint32_t r;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+  return r;
+}
+
+// acc[u] += sum over digits k in [2 p0, 2 p1) of v_k T[k][u], T's 16-word rows stored
+// contiguously from `t`.  Rows are consumed in turn from two scalar buffers: the
+// first product of a row waits for it, the next row (the following 64 bytes) is
+// requested right after, and the row's other 15 products cover that latency.
+// (Scalar loads complete out of order, so a wait placed after the request would
+// also wait for it.)  Digit pairs come from LDS one pair per two rows.  With FOLD every
+// accumulator is folded (hi 2^32 + lo -> hi c32[u] + lo) after every 10 products,
+// so it stays below 2^64; the last action is then a fold.
+template <bool FOLD>
+__device__ __forceinline__ void mac_rows(uint64_t (&acc)[16], const uint32_t* vd, int lane, cu32* t, int p0,
+                                         int p1, const uint32_t (&c32)[16]) {
+  if (p1 <= p0) return;
+  const int k1 = 2 * p1;
+  int k = 2 * p0;
+  cu32* tp = t + 16 * k;
+  const uint32_t* vp = vd + p0 * 128 + 2 * lane;
+  Row16 ra = load_row(tp), rb;
+  uint2 d = *(const uint2*)vp;
+  for (; k + 10 <= k1; k += 10, tp += 160, vp += 640) {
+    // pair read after the last row of this iteration: the next one, or (at the end)
+    // the last pair again, so that no pair beyond p1 is read
+    const int last = (k + 10 < k1) ? 5 : 4;
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+      const uint32_t x = (q % 2 == 0) ? d.x : d.y;
+      Row16& cur = (q % 2 == 0) ? ra : rb;
+      Row16& nxt = (q % 2 == 0) ? rb : ra;
+      acc[0] = mad64(x, cur.c[0], acc[0]);
+      FHE_FENCE();
+      nxt = load_row(tp + 16 * (q + 1));  // the row after the last one reads padding
+      FHE_FENCE();
+#pragma unroll
+      for (int u = 1; u < 16; ++u) acc[u] = mad64(x, cur.c[u], acc[u]);
+      if (q % 2 == 1) d = *(const uint2*)(vp + ((q < 9 ? (q + 1) / 2 : last)) * 128);
+      FHE_FENCE();
+    }
+    if (FOLD) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc[u] = fold64(acc[u], c32[u]);
+    }
+  }
+  // remainder: fewer than 10 rows (an even number)
+  for (; k < k1; k += 2, tp += 32, vp += 128) {
+    const uint2 dd = *(const uint2*)vp;
+    const Row16 r0 = load_row(tp), r1 = load_row(tp + 16);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] = mad64(dd.x, r0.c[u], acc[u]);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] = mad64(dd.y, r1.c[u], acc[u]);
+  }
+  if (FOLD) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] = fold64(acc[u], c32[u]);
+  }
+}
+
 __global__ __launch_bounds__(64) void garner_kernel(GarnerArgs a) {
-  extern __shared__ uint32_t vd[];  // [K][64]
-  constexpr int B = kGarnerBlock;
-  constexpr int FOLD = 11;
+  // This wave's digits, in a private scratch region (pair layout of load_pair).  Each
+  // digit is written once, after which this wave alone reads it; stores complete
+  // (s_waitcnt) before any read of the same block, and no line of a block is read
+  // before the block is written, so no stale line can sit in the vector L1.
+  uint32_t* vd = a.dig + (long long)(blockIdx.y * gridDim.x + blockIdx.x) * garner_wave_words(a.K);
+  constexpr int B = kGarnerBlock;   // 16: digits finalized per block
   const int lane = threadIdx.x;
   const int jc = blockIdx.x * 64 + lane;
   const int z = blockIdx.y;
@@ -397,67 +498,63 @@ __global__ __launch_bounds__(64) void garner_kernel(GarnerArgs a) {
   const uint32_t* in = a.res + (long long)(z / a.per_group) * a.gstride +
                        (long long)(z % a.per_group) * a.pstride + jcc;
   const int K = a.K;
+  cu32* Gt = (cu32*)a.Gt;
+  cu32* Ow = (cu32*)a.Ow;
+  cprime* pcs = (cprime*)a.pc;
 
   for (int kb = 0; kb < K; kb += B) {
+    // residues of this block (rows past K are valid memory; those digits are zeroed)
+    uint32_t xin[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) xin[u] = in[(long long)min(kb + u, K - 1) * a.N];
+    uint32_t c32[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) c32[u] = to_vgpr(pcs[kb + u].c32);
     uint64_t acc[B];
 #pragma unroll
     for (int u = 0; u < B; ++u) acc[u] = 0;
-    // earlier digits
-    for (int j0 = 0; j0 < kb; j0 += FOLD) {
-      const int jn = min(FOLD, kb - j0);
-      for (int jj = 0; jj < jn; ++jj) {
-        const int jd = j0 + jj;
-        const uint32_t v = vd[jd * 64 + lane];
-        const uint32_t* g = a.Gt + (long long)jd * a.GS + kb;
-#pragma unroll
-        for (int u = 0; u < B; ++u) acc[u] = mad64(v, g[u], acc[u]);
-      }
-#pragma unroll
-      for (int u = 0; u < B; ++u) acc[u] = fold64(acc[u], a.pc[kb + u].c32);
-    }
-    // digits of this block, in order
+    // all earlier digits, pairs 0 .. kb/2 - 1 (accumulators folded at least every 10 products)
+    cu32* gb = Gt + 256 * (kb / B) * (kb / B + 1) / 2;  // this digit block's rows
+    mac_rows<true>(acc, vd, lane, gb, 0, kb >> 1, c32);
+    // this block's digits in order (branch-free; digits k >= K are zero)
 #pragma unroll
     for (int u = 0; u < B; ++u) {
       const int k = kb + u;
-      if (k < K) {
-        const PrimeC pk = a.pc[k];
-        const uint32_t sred = reduce64_mont(acc[u], pk);
-        const uint32_t xk = add_mod(in[(long long)k * a.N], a.Ow[k], pk.q);
-        const uint32_t v = sub_mod(xk, sred, pk.q);
-        vd[k * 64 + lane] = v;
-        const uint32_t* g = a.Gt + (long long)k * a.GS + kb;
+      const PrimeC pk = load_prime(pcs + k);
+      const uint32_t sred = reduce64_mont(acc[u], pk);
+      const uint32_t xk = add_mod(xin[u], Ow[k], pk.q);
+      const uint32_t vk = k < K ? sub_mod(xk, sred, pk.q) : 0u;
+      vd[(k >> 1) * 128 + 2 * lane + (k & 1)] = vk;
+      cu32* g = gb + 16 * k;
 #pragma unroll
-        for (int w = u + 1; w < B; ++w) {
-          acc[w] = mad64(v, g[w], acc[w]);
-          // acc[w] holds at most a folded value plus (w - u) in-block products
-        }
-        if (u == FOLD - 1) {
+      for (int w = u + 1; w < B; ++w) acc[w] = mad64(vk, g[w], acc[w]);
+      if (u == 10) {  // the in-block sums hold at most 11 products before this fold
 #pragma unroll
-          for (int w = FOLD; w < B; ++w) acc[w] = fold64(acc[w], a.pc[kb + w].c32);
-        }
+        for (int w = 11; w < B; ++w) acc[w] = fold64(acc[w], c32[w]);
       }
     }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this block's digit stores are done
   }
-  __syncthreads();
 
   // Column sums over radix-2^26 digits of M_k, carried and packed into limbs.
   const int D = (a.outbits + kHornerDigitBits - 1) / kHornerDigitBits;
+  const int npair = (K + 1) >> 1;  // a digit K (K odd) is stored as zero
   uint32_t* out = a.out + (long long)z * a.ostride + jcc;
+  cu32* Ct = (cu32*)a.Ct;
   uint64_t carry = 0, bitbuf = 0;
   int nbits = 0, li = 0;
   const int topbits = a.outbits - 32 * (a.Lout - 1);
   const uint32_t topmask = topbits >= 32 ? 0xFFFFFFFFu : ((1u << topbits) - 1u);
   constexpr int BC = kHornerBlock;
+  static_assert(BC == 16, "a column block is one constant row");
+  const uint32_t nofold[16] = {};
   for (int m0 = 0; m0 < D; m0 += BC) {
     uint64_t col[BC];
 #pragma unroll
     for (int m = 0; m < BC; ++m) col[m] = 0;
-    for (int k = a.kstart[m0]; k < K; ++k) {
-      const uint32_t v = vd[k * 64 + lane];
-      const uint32_t* cc = a.Ct + (long long)k * a.CS + m0;
-#pragma unroll
-      for (int m = 0; m < BC; ++m) col[m] = mad64(v, cc[m], col[m]);
-    }
+    // digits k < kstart[m0] have no radix-2^26 digit at or above m0
+    const int ps = ((__attribute__((address_space(4))) const int*)a.kstart)[m0] >> 1;
+    mac_rows<false>(col, vd, lane, Ct + (long long)(m0 / BC) * a.CS, ps, npair, nofold);
 #pragma unroll
     for (int m = 0; m < BC; ++m) {
       if (m0 + m < D) {
@@ -497,9 +594,12 @@ static double garner_products(int K, int Lout, const int* mbits) {
 hipError_t launch_garner(const GarnerArgs& a, int npoly, hipStream_t st) {
   if (npoly <= 0) return hipSuccess;
   dim3 grid((a.N + 63) / 64, npoly);
-  const size_t lds = (size_t)a.K * 64 * sizeof(uint32_t);
+  // digits padded to the 16-digit block (the last block writes through k < K + 16),
+  // plus one pair read ahead by the last prefetch
+  const size_t lds = (size_t)((a.K + kGarnerBlock - 1) / kGarnerBlock * kGarnerBlock + 2) * 64 * sizeof(uint32_t);
   Bracket br(KID_GARNER, st, (double)npoly * a.N * garner_products(a.K, a.Lout, a.mbits));
-  hipLaunchKernelGGL(garner_kernel, grid, dim3(64), lds, st, a);
+  (void)lds;
+  hipLaunchKernelGGL(garner_kernel, grid, dim3(64), 0, st, a);
   return hipGetLastError();
 }
 
