@@ -17,9 +17,9 @@ constexpr int kHornerBlock = 16;      // output columns per block
 constexpr int kLiftPrimes = 16;       // primes per lift thread
 constexpr int kGarnerGS = 256;        // row stride of the host's square digit table (K <= 224)
 
-// Negacyclic NTT over a set of transforms.  Transform tr (blockIdx.y) lives at
-// data + (tr / per_group) * group_stride + (tr % per_group) * N and uses prime
-// (tr % per_group) % K.
+// Negacyclic NTT over a set of transforms.  Transform (group g, row r) lives at
+// data + g * group_stride + r * N and uses prime r % K; per_group (rows per group)
+// and the number of transforms are multiples of K.
 struct NttArgs {
   uint32_t* data;
   int logN;
@@ -29,6 +29,7 @@ struct NttArgs {
   const uint2* tw;     // [prime][kNMax] (w, floor(w 2^32 / q)), bit-reversed powers
   const PrimeC* pc;
   const uint2* scale;  // inverse only: per-prime final factor (w, w')
+  int ntr;             // number of transforms (set by launch_ntt; a multiple of K)
 };
 
 struct LiftArgs {
@@ -36,6 +37,7 @@ struct LiftArgs {
   uint32_t* res;          // poly z at res + z * out_stride, uint32[K][N]
   long long in_stride, out_stride;
   int N, L, K;
+  int npoly;          // set by launch_lift
   const uint32_t* T;  // [prime][TS]: 2^(28 i) 2^32 mod q
   int TS;
   const PrimeC* pc;

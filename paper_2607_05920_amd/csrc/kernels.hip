@@ -74,12 +74,22 @@ __global__ __launch_bounds__(256) void ntt_pass_kernel(NttArgs a) {
 
   const int N = 1 << a.logN;
   const int nsub_total = N / n;  // blocks (ROWS) or columns (COLS)
-  const int sg = blockIdx.x * NSUB + s;
+  // Workgroup w runs on XCD w % 8 (round-robin dispatch).  XCD x takes the primes
+  // p = x (mod 8), one at a time, and every transform of that prime in turn, so a
+  // prime's twiddle table is read into one L2 once.
+  const int nwg = (nsub_total + NSUB - 1) / NSUB;  // workgroups per transform
+  const int npp = a.ntr / a.K;                     // transforms per prime
+  const int w = blockIdx.x, xcd = w & 7, l = w >> 3;
+  const int per_prime = npp * nwg;
+  const int p = (l / per_prime) * 8 + xcd;
+  if (p >= a.K) return;  // whole workgroup exits (primes not a multiple of 8)
+  const int rem = l % per_prime;
+  const int jp = rem / nwg;  // transform index among those of prime p
+  const int sg = (rem % nwg) * NSUB + s;
   const bool valid = sg < nsub_total;
-
-  const int tr = blockIdx.y;
-  const int grp = tr / a.per_group, r = tr % a.per_group;
-  const int p = r % a.K;
+  // transform jp of prime p: polynomial i of group grp, row r = i K + p
+  const int pk = a.per_group / a.K;  // polynomials per group
+  const int grp = jp / pk, r = (jp % pk) * a.K + p;
   uint32_t* base = a.data + (long long)grp * a.group_stride + (long long)r * N;
   const PrimeC pc = a.pc[p];
   const uint32_t q = pc.q, two_q = pc.two_q;
@@ -197,7 +207,9 @@ static hipError_t ntt_pass(const NttArgs& a, int ntr, hipStream_t st) {
   constexpr int n = 1 << S;
   constexpr int NSUB = 256 / (n / 16);
   const int nsub_total = (1 << a.logN) / n;
-  dim3 grid((nsub_total + NSUB - 1) / NSUB, ntr);
+  const int nwg = (nsub_total + NSUB - 1) / NSUB;
+  const int kx = (a.K + 7) / 8;  // primes per XCD (the largest share)
+  dim3 grid(8 * kx * (ntr / a.K) * nwg);
   // algorithmic work: (N / 2) S butterflies per transform, one constant product each
   Bracket br(INV ? (ROWS ? KID_NTT_INV_ROWS : KID_NTT_INV_COLS) : (ROWS ? KID_NTT_FWD_ROWS : KID_NTT_FWD_COLS), st,
              (double)ntr * (double)((1 << a.logN) / 2) * S);
@@ -216,8 +228,11 @@ static hipError_t ntt_pass_s(int S, const NttArgs& a, int ntr, hipStream_t st) {
   }
 }
 
-hipError_t launch_ntt(const NttArgs& a, int ntr, bool inverse, hipStream_t st) {
+hipError_t launch_ntt(const NttArgs& a0, int ntr, bool inverse, hipStream_t st) {
   if (ntr <= 0) return hipSuccess;
+  if (ntr % a0.K != 0 || a0.per_group % a0.K != 0) return hipErrorInvalidValue;
+  NttArgs a = a0;
+  a.ntr = ntr;
   const int s_rows = a.logN / 2, s_cols = a.logN - s_rows;
   hipError_t e;
   if (!inverse) {
@@ -238,9 +253,17 @@ hipError_t launch_ntt(const NttArgs& a, int ntr, bool inverse, hipStream_t st) {
 
 template <int PB>
 __global__ __launch_bounds__(256) void lift_kernel(LiftArgs a) {
-  const int jc = blockIdx.y * 256 + threadIdx.x;  // coefficient
-  const int p0 = blockIdx.x * PB;
-  const int z = blockIdx.z;
+  // Workgroup w runs on XCD w % 8.  The prime groups of one (polynomial,
+  // coefficient block) unit are consecutive workgroups of one XCD, so the unit's
+  // limbs are read from HBM once and then from that XCD's L2.
+  const int G = (a.K + PB - 1) / PB;
+  const int nb = (a.N + 255) / 256;
+  const int w = blockIdx.x, xcd = w & 7, l = w >> 3;
+  const int unit = (l / G) * 8 + xcd;
+  if (unit >= nb * a.npoly) return;
+  const int p0 = (l % G) * PB;
+  const int z = unit / nb;
+  const int jc = (unit % nb) * 256 + threadIdx.x;  // coefficient
   if (jc >= a.N) return;
   const uint32_t* src = a.limbs + (long long)z * a.in_stride + jc;
   uint64_t acc[PB];
@@ -284,10 +307,14 @@ __global__ __launch_bounds__(256) void lift_kernel(LiftArgs a) {
 
 hipError_t launch_lift(const LiftArgs& a, int npoly, hipStream_t st) {
   if (npoly <= 0) return hipSuccess;
-  dim3 grid((a.K + kLiftPrimes - 1) / kLiftPrimes, (a.N + 255) / 256, npoly);
+  LiftArgs b = a;
+  b.npoly = npoly;
+  const int G = (a.K + kLiftPrimes - 1) / kLiftPrimes;
+  const int units = ((a.N + 255) / 256) * npoly;
+  dim3 grid(8 * ((units + 7) / 8) * G);
   // algorithmic work: L limb-constant products per (coefficient, prime)
   Bracket br(KID_LIFT, st, (double)npoly * a.N * a.K * a.L);
-  hipLaunchKernelGGL((lift_kernel<kLiftPrimes>), grid, dim3(256), 0, st, a);
+  hipLaunchKernelGGL((lift_kernel<kLiftPrimes>), grid, dim3(256), 0, st, b);
   return hipGetLastError();
 }
 
