@@ -56,6 +56,67 @@ def cpu_baseline():
     }
 
 
+def batched_uneven(fhe, torch, synth, dev, stream, njobs):
+    """`njobs` CKKS HE-mults + relin + rescale(40) with logN ~ U{13..16} and logq ~
+    U{218, 438, 874, 1555} drawn independently from the workload-4 schedule stream;
+    one key per N at logQ = logP = 1555.  One autotuned, graph-captured plan run
+    against the same jobs as separate per-op calls; outputs compared bit for bit."""
+    import numpy as np
+
+    rk, rm, _, rs = synth.streams(4)
+    ctx = fhe.Context(LOGQ, LOGP)
+    keys = {n: fhe.EvalKey(ctx, fhe.CKKS, 0, n, LOGQ, LOGP, synth.uniform_limbs(rk, LOGQ + LOGP, 1 << n),
+                           synth.uniform_limbs(rk, LOGQ + LOGP, 1 << n)) for n in (13, 14, 15, 16)}
+    logNs = rs.integers(13, 17, size=njobs)
+    logqs = np.array([218, 438, 874, 1555])[rs.integers(0, 4, size=njobs)]
+    jobs, ref = [], []
+    for n, q in zip(logNs.tolist(), logqs.tolist()):
+        N = 1 << n
+        ins = [fhe.to_device(synth.uniform_limbs(rm, q, N)).reshape(-1) for _ in range(4)]
+        Lo = synth.nlimbs(q - BITS)
+        outs = [torch.zeros(Lo * N, dtype=torch.int32, device=dev) for _ in range(2)]
+        ref.append([torch.zeros(Lo * N, dtype=torch.int32, device=dev) for _ in range(2)])
+        jobs.append((keys[n], q, BITS, *ins, *outs))
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def per_op():
+        for j, r in zip(jobs, ref):
+            ctx.mul_relin_rescale(j[0], j[1], j[2], j[3], j[4], j[5], j[6], r[0], r[1])
+
+    per_op()  # prepares every key level; warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = fhe.BatchPlan(ctx, jobs, flags=fhe.PLAN_GRAPH | fhe.PLAN_AUTOTUNE)
+    plan_s = time.perf_counter() - t0
+    info = plan.info()
+    plan.run()
+    torch.cuda.synchronize()
+    reps = 3
+    ev0.record(stream)
+    for _ in range(reps):
+        plan.run()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    batched = reps * njobs / (ev0.elapsed_time(ev1) / 1e3)
+    ev0.record(stream)
+    for _ in range(reps):
+        per_op()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    perop = reps * njobs / (ev0.elapsed_time(ev1) / 1e3)
+    exact = all(torch.equal(j[7], r[0]) and torch.equal(j[8], r[1]) for j, r in zip(jobs, ref))
+    out = {"jobs": njobs, "cells": info["cells"], "kernels_per_run": info["kernels"], "graphed": info["graphed"],
+           "plan_seconds": plan_s, "he_mults_per_s": batched, "per_op_he_mults_per_s": perop,
+           "speedup_vs_per_op": batched / perop, "bit_exact_vs_per_op": bool(exact),
+           "workload": "CKKS, logN ~ U{13..16}, logq ~ U{218,438,874,1555}, rescale 40, one key per N at "
+                       "logQ = logP = 1555 (seed 4000)"}
+    plan.close()
+    for k in keys.values():
+        k.close()
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +125,8 @@ def main():
     ap.add_argument("--cnum", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip per-op and NTT legs")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched uneven leg")
+    ap.add_argument("--batch-jobs", type=int, default=256)
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run one plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -175,6 +238,10 @@ def main():
         extras["ntt_transforms_per_call"] = 64 * Kt
         del polys, res
         torch.cuda.empty_cache()
+
+    if not args.no_extras and not args.no_batch:
+        log("batched uneven leg")
+        extras["batched_uneven"] = batched_uneven(fhe, torch, synth, dev, stream, args.batch_jobs)
 
     if args.copy_calib_mb:
         nb = args.copy_calib_mb << 20

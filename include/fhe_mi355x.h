@@ -63,6 +63,7 @@ extern "C" {
 
 typedef struct fhe_ctx fhe_ctx;
 typedef struct fhe_evk fhe_evk;
+typedef struct fhe_plan fhe_plan;
 
 /* Text for a status code (static storage). */
 const char* fhe_strerror(int status);
@@ -190,6 +191,44 @@ int fhe_mul_relin_rescale(fhe_ctx* ctx, fhe_evk* evk, int logN, int logq, int bi
                           const uint32_t* x0, const uint32_t* x1, const uint32_t* y0,
                           const uint32_t* y1, uint32_t* out0, uint32_t* out1, int cnum,
                           void* stream);
+
+/* ---------------------------------------------------------------- batches
+ * A batch of HE-mults of uneven ring degree and level (the CipherTensor of Section
+ * 6.1 generalised: ciphertexts of one cell share parameters, cells differ).
+ * One job = fhe_mul_relin on one ciphertext pair, then rescale by `bits` (0: none).
+ * All pointers are caller-owned device buffers: x0..y1 uint32[L][N], outputs
+ * uint32[L'][N] with L = ceil(logq / 32), L' = ceil((logq - bits) / 32), N = 2^logN
+ * of the job's key.  Outputs must not alias inputs or other jobs' outputs. */
+typedef struct {
+  fhe_evk* evk;  /* relinearization key; its logN, scheme and t apply */
+  int logq;      /* level of both operands, <= the key's logQ */
+  int bits;      /* rescale after relinearization: 0 or 1 <= bits < logq */
+  const uint32_t *x0, *x1, *y0, *y1;
+  uint32_t *out0, *out1;
+} fhe_job;
+
+#define FHE_PLAN_GRAPH 1    /* capture the whole batch in one hipGraph */
+#define FHE_PLAN_AUTOTUNE 2 /* time launch-parameter candidates per cell at plan time */
+
+/* Build a plan for `njobs` jobs (host array, read during the call).  Jobs are grouped
+ * into cells of equal (key, logq, bits); each cell runs as one CipherTensor pipeline
+ * reading and writing the jobs' buffers through device pointer arrays.  The plan
+ * owns its scratch memory, the prepared key levels it needs, and (FHE_PLAN_GRAPH)
+ * an instantiated hipGraph.  Planning prepares keys and, with FHE_PLAN_AUTOTUNE, runs
+ * every cell a few times on `stream` (writing the outputs); it synchronizes.  The
+ * job buffers must stay valid for the plan's lifetime.  Errors: FHE_E_INVAL,
+ * FHE_E_SHAPE, FHE_E_RANGE, FHE_E_NOMEM, FHE_E_DEVICE. */
+int fhe_batch_plan(fhe_ctx* ctx, const fhe_job* jobs, int njobs, int flags, void* stream, fhe_plan** out);
+
+/* Queue one execution of the plan on `stream` (graph launch, or the cells' kernels
+ * in order).  Errors: FHE_E_INVAL, FHE_E_DEVICE. */
+int fhe_batch_run(fhe_plan* plan, void* stream);
+
+/* Cells, kernel launches per run, and whether the plan is a graph (host outputs). */
+int fhe_batch_info(const fhe_plan* plan, int* cells, int* kernels, int* graphed);
+
+/* Release a plan (waits for the device).  NULL is a no-op. */
+void fhe_batch_destroy(fhe_plan* plan);
 
 #ifdef __cplusplus
 }

@@ -49,7 +49,20 @@ EXPORTS = {
     "fhe_mul_relin": (_I, [_P, _P, _I, _I, _P, _P, _P, _P, _P, _P, _I, _P]),
     "fhe_rescale": (_I, [_P, _I, _U, _I, _I, _I, _P, _P, _P, _P, _I, _P]),
     "fhe_mul_relin_rescale": (_I, [_P, _P, _I, _I, _I, _P, _P, _P, _P, _P, _P, _I, _P]),
+    "fhe_batch_plan": (_I, [_P, _P, _I, _I, _P, ctypes.POINTER(_P)]),
+    "fhe_batch_run": (_I, [_P, _P]),
+    "fhe_batch_info": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "fhe_batch_destroy": (None, [_P]),
 }
+
+PLAN_GRAPH = 1
+PLAN_AUTOTUNE = 2
+
+
+class Job(ctypes.Structure):
+    """fhe_job: one HE-mult (+ optional rescale) of a batch; pointers are device addresses."""
+    _fields_ = [("evk", _P), ("logq", _I), ("bits", _I), ("x0", _P), ("x1", _P), ("y0", _P), ("y1", _P),
+                ("out0", _P), ("out1", _P)]
 
 
 class LibraryMissing(RuntimeError):
@@ -260,6 +273,49 @@ class EvalKey:
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
             load_library().fhe_evk_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchPlan:
+    """A planned batch of uneven HE-mults (fhe_batch_plan).  `jobs` is a list of
+    (evk, logq, bits, x0, x1, y0, y1, out0, out1) with torch CUDA tensors; the tensors
+    must stay alive while the plan exists."""
+
+    def __init__(self, ctx: Context, jobs, flags: int = PLAN_GRAPH, stream=None):
+        lib = load_library()
+        arr = (Job * len(jobs))()
+        self._keep = []
+        for i, (evk, logq, bits, x0, x1, y0, y1, o0, o1) in enumerate(jobs):
+            w = nlimbs(logq) << evk.logN
+            wo = nlimbs(logq - bits) << evk.logN
+            for t, n in ((x0, w), (x1, w), (y0, w), (y1, w), (o0, wo), (o1, wo)):
+                _need(t, n, "job buffer")
+            arr[i] = Job(evk.handle.value, logq, bits, _ptr(x0), _ptr(x1), _ptr(y0), _ptr(y1), _ptr(o0), _ptr(o1))
+            self._keep.append((evk, x0, x1, y0, y1, o0, o1))
+        h = ctypes.c_void_p()
+        _check("fhe_batch_plan", lib.fhe_batch_plan(ctx.handle, arr, len(jobs), flags, _stream(stream),
+                                                    ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+
+    def run(self, stream=None):
+        _check("fhe_batch_run", load_library().fhe_batch_run(self._h, _stream(stream)))
+
+    def info(self) -> dict:
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check("fhe_batch_info", load_library().fhe_batch_info(self._h, ctypes.byref(a), ctypes.byref(b),
+                                                               ctypes.byref(c)))
+        return {"cells": a.value, "kernels": b.value, "graphed": bool(c.value)}
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load_library().fhe_batch_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -227,6 +227,25 @@ struct fhe_ctx {
   std::recursive_mutex mu;
   int sticky = FHE_OK;
   Recorder* rec = nullptr;  // non-null while profiling is on
+  std::map<std::vector<int>, Tuning> tuned;  // autotuner results by (logN, logq, logP, K_t, K_r)
+};
+
+// One cell of a batch plan: jobs sharing (key, logq, bits), run as a CipherTensor.
+struct PlanCell {
+  fhe_evk* evk = nullptr;
+  int logN = 0, logq = 0, bits = 0, cnum = 0;
+  uint32_t** ptrs = nullptr;  // device: x0s, x1s, y0s, y1s, out0s, out1s (cnum each)
+  Tuning tune;
+};
+
+struct fhe_plan {
+  fhe_ctx* ctx = nullptr;
+  std::vector<PlanCell> cells;
+  uint32_t *ws = nullptr, *stage = nullptr, *dig = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int kernels = 0;
 };
 
 struct fhe_evk {
@@ -310,7 +329,7 @@ int check_logN(int logN) { return (logN >= FHE_LOGN_MIN && logN <= FHE_LOGN_MAX)
 
 NttArgs ntt_args(fhe_ctx* c, uint32_t* data, int logN, int K, int per_group, long long gstride,
                  bool inverse, const uint2* scale) {
-  NttArgs a;
+  NttArgs a{};
   a.data = data;
   a.logN = logN;
   a.K = K;
@@ -324,7 +343,7 @@ NttArgs ntt_args(fhe_ctx* c, uint32_t* data, int logN, int K, int per_group, lon
 
 LiftArgs lift_args(fhe_ctx* c, const uint32_t* limbs, uint32_t* res, long long in_stride,
                    long long out_stride, int N, int L, int K) {
-  LiftArgs a;
+  LiftArgs a{};
   a.limbs = limbs;
   a.res = res;
   a.in_stride = in_stride;
@@ -341,7 +360,7 @@ LiftArgs lift_args(fhe_ctx* c, const uint32_t* limbs, uint32_t* res, long long i
 GarnerArgs garner_args(fhe_ctx* c, const uint32_t* res, int per_group, long long gstride,
                        long long pstride, uint32_t* out, long long ostride, int N, int K,
                        int outbits, const uint32_t* ow) {
-  GarnerArgs a;
+  GarnerArgs a{};
   a.res = res;
   a.per_group = per_group;
   a.gstride = gstride;
@@ -418,51 +437,71 @@ int evk_prepare_locked(fhe_evk* k, int logq, hipStream_t stream) {
   return FHE_OK;
 }
 
-// The HE-mult pipeline; writes out0/out1 ([cnum][L][N]) = [d + R(k)]_(2^logq).
-int mul_relin_locked(fhe_ctx* c, fhe_evk* k, int logN, int logq, const uint32_t* x0,
-                     const uint32_t* x1, const uint32_t* y0, const uint32_t* y1, uint32_t* out0,
-                     uint32_t* out1, long long ostride, int cnum, hipStream_t st) {
+// Inputs and outputs of one HE-mult pipeline run over cnum ciphertext pairs: either
+// CipherTensor base pointers ([cnum][L][N], outputs [cnum][L'][N]) or device arrays of
+// per-ciphertext pointers (x0s[c] ...), as used by batch plans.
+struct PipeIO {
+  const uint32_t *x0 = nullptr, *x1 = nullptr, *y0 = nullptr, *y1 = nullptr;
+  uint32_t *out0 = nullptr, *out1 = nullptr;
+  const uint32_t* const* ins = nullptr;  // device: x0s, x1s, y0s, y1s (4 cnum pointers)
+  uint32_t* const* outs = nullptr;       // device: out0s, out1s (2 cnum pointers)
+};
+
+// Scratch words of one pipeline run (main area, staging of the relinearized
+// ciphertexts before rescale, Garner digit scratch).
+struct PipeSize {
+  int Kt = 0, Kr = 0, L = 0, LK = 0;
+  long long main_words = 0, stage_words = 0, digit_words = 0;
+};
+
+PipeSize pipe_size(const fhe_ctx* c, const fhe_evk* k, int logN, int logq, int cnum) {
+  PipeSize z;
+  const long long NN = 1LL << logN;
+  z.L = (logq + 31) / 32;
+  z.LK = (k->logP + logq + 31) / 32;
+  z.Kt = primes_for_e(c, 2 * logq + logN + 1);
+  z.Kr = primes_for_e(c, logN + 2 * logq + k->logP);
+  if (z.Kt < 0 || z.Kr < 0) return z;
+  z.main_words = (long long)cnum * NN * (4LL * z.Kt + 3LL * z.L + z.Kr + 2LL * z.Kr + 2LL * z.LK);
+  z.stage_words = 2LL * cnum * z.L * NN;
+  z.digit_words = std::max((long long)cnum * 3 * (NN / 64) * garner_wave_words(z.Kt),
+                           (long long)cnum * 2 * (NN / 64) * garner_wave_words(z.Kr));
+  return z;
+}
+
+// The HE-mult pipeline: lift, NTT, tensor products, iNTT, Garner (d0, d1, d2 mod
+// 2^logq); lift d2, NTT, products with the resident key, iNTT, Garner (k0, k1 mod
+// 2^(logP+logq)); c_i = [d_i + R(k_i)]_(2^logq); then, if bits > 0, the rescale.
+int pipeline(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, const PipeIO& io, int cnum, hipStream_t st,
+             uint32_t* ws, uint32_t* stage, uint32_t* dig, const Tuning& tu) {
   const int N = 1 << logN;
-  const int L = (logq + 31) / 32;
+  const PipeSize z = pipe_size(c, k, logN, logq, cnum);
+  if (z.Kt < 0 || z.Kr < 0) return FHE_E_RANGE;
+  const int Kt = z.Kt, Kr = z.Kr, L = z.L, LK = z.LK;
   const int logP = k->logP;
-  const int LK = (logP + logq + 31) / 32;
-  const int et = 2 * logq + logN + 1;
-  const int er = logN + 2 * logq + logP;
-  const int Kt = primes_for_e(c, et);
-  const int Kr = primes_for_e(c, er);
-  if (Kt < 0 || Kr < 0) return FHE_E_RANGE;
-  int rc = evk_prepare_locked(k, logq, st);
-  if (rc != FHE_OK) return rc;
+  const uint32_t* evk_ntt = k->ntt.at(logq);
   hipError_t e = hipSuccess;
-  const uint32_t* owt = offsets(c, et, &e);
+  const uint32_t* owt = offsets(c, 2 * logq + logN + 1, &e);
   if (!owt) return set_sticky(c, e);
-  const uint32_t* owr = offsets(c, er, &e);
+  const uint32_t* owr = offsets(c, logN + 2 * logq + logP, &e);
   if (!owr) return set_sticky(c, e);
   const long long NN = N;
-  // scratch layout (words)
-  const long long szRt = (long long)cnum * 4 * Kt * NN;  // tensor residues
-  const long long szDl = (long long)cnum * 3 * L * NN;   // d0, d1, d2 limbs
-  const long long szRr = (long long)cnum * Kr * NN;      // d2 residues
-  const long long szK = (long long)cnum * 2 * Kr * NN;   // k0, k1 residues
-  const long long szKl = (long long)cnum * 2 * LK * NN;  // k0, k1 limbs
-  const long long words = szRt + szDl + szRr + szK + szKl;
-  uint32_t* ws = (uint32_t*)scratch(c, st, 0, (size_t)words * 4, &e);
-  if (!ws) return set_sticky(c, e);
-  uint32_t* Rt = ws;
-  uint32_t* Dl = Rt + szRt;
-  uint32_t* Rr = Dl + szDl;
-  uint32_t* Rk = Rr + szRr;
-  uint32_t* Kl = Rk + szK;
+  uint32_t* Rt = ws;                                    // [cnum][4][Kt][N]
+  uint32_t* Dl = Rt + (long long)cnum * 4 * Kt * NN;    // [cnum][3][L][N]
+  uint32_t* Rr = Dl + (long long)cnum * 3 * L * NN;     // [cnum][Kr][N]
+  uint32_t* Rk = Rr + (long long)cnum * Kr * NN;        // [cnum][2][Kr][N]
+  uint32_t* Kl = Rk + (long long)cnum * 2 * Kr * NN;    // [cnum][2][LK][N]
   const long long polyw = (long long)L * NN;
-  const long long cstride = polyw;  // inputs are [cnum][L][N]
   // 1. lift the four inputs: Rt[c][i][Kt][N], i = x0, x1, y0, y1
-  const uint32_t* ins[4] = {x0, x1, y0, y1};
-  for (int i = 0; i < 4 && e == hipSuccess; ++i)
-    e = launch_lift(lift_args(c, ins[i], Rt + (long long)i * Kt * NN, cstride, 4LL * Kt * NN, N, L, Kt),
-                    cnum, st);
+  const uint32_t* ins[4] = {io.x0, io.x1, io.y0, io.y1};
+  for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+    LiftArgs la = lift_args(c, ins[i], Rt + (long long)i * Kt * NN, polyw, 4LL * Kt * NN, N, L, Kt);
+    if (io.ins) la.in_ptrs = io.ins + (long long)i * cnum;
+    e = launch_lift(la, cnum, st, tu);
+  }
   // 2. forward NTT of all 4 cnum Kt transforms
   if (e == hipSuccess)
-    e = launch_ntt(ntt_args(c, Rt, logN, Kt, 4 * Kt, 4LL * Kt * NN, false, nullptr), cnum * 4 * Kt, false, st);
+    e = launch_ntt(ntt_args(c, Rt, logN, Kt, 4 * Kt, 4LL * Kt * NN, false, nullptr), cnum * 4 * Kt, false, st, tu);
   // 3. tensor products into slots 0..2
   if (e == hipSuccess) {
     PointwiseArgs pa{};
@@ -473,25 +512,26 @@ int mul_relin_locked(fhe_ctx* c, fhe_evk* k, int logN, int logq, const uint32_t*
     pa.pc = c->pc;
     e = launch_tensor_pointwise(pa, cnum, st);
   }
-  // 4. inverse NTT of slots 0..2 (factor N^-1 2^32 I_k)
+  // 4. inverse NTT of slots 0..2 (final factor N^-1 2^32 I_k)
   if (e == hipSuccess)
-    e = launch_ntt(ntt_args(c, Rt, logN, Kt, 3 * Kt, 4LL * Kt * NN, true, c->gscale[logN]), cnum * 3 * Kt,
-                   true, st);
+    e = launch_ntt(ntt_args(c, Rt, logN, Kt, 3 * Kt, 4LL * Kt * NN, true, c->gscale[logN]), cnum * 3 * Kt, true,
+                   st, tu);
   // 5. Garner -> d0, d1, d2 mod 2^logq: Dl[c][i][L][N]
+  if (e == hipSuccess) {
+    GarnerArgs ga = garner_args(c, Rt, 3, 4LL * Kt * NN, (long long)Kt * NN, Dl, polyw, N, Kt, logq, owt);
+    ga.dig = dig;
+    e = launch_garner(ga, cnum * 3, st);
+  }
+  // 6. lift d2 onto Kr primes; 7. forward NTT
   if (e == hipSuccess)
-    e = run_garner(c, st, garner_args(c, Rt, 3, 4LL * Kt * NN, (long long)Kt * NN, Dl, polyw, N, Kt, logq, owt),
-                   cnum * 3);
-  // 6. lift d2 onto Kr primes
+    e = launch_lift(lift_args(c, Dl + 2 * polyw, Rr, 3 * polyw, (long long)Kr * NN, N, L, Kr), cnum, st, tu);
   if (e == hipSuccess)
-    e = launch_lift(lift_args(c, Dl + 2 * polyw, Rr, 3 * polyw, (long long)Kr * NN, N, L, Kr), cnum, st);
-  // 7. forward NTT of d2
-  if (e == hipSuccess)
-    e = launch_ntt(ntt_args(c, Rr, logN, Kr, Kr, (long long)Kr * NN, false, nullptr), cnum * Kr, false, st);
+    e = launch_ntt(ntt_args(c, Rr, logN, Kr, Kr, (long long)Kr * NN, false, nullptr), cnum * Kr, false, st, tu);
   // 8. products with the resident key: Rk[c][0..1][Kr][N]
   if (e == hipSuccess) {
     PointwiseArgs pa{};
     pa.a = Rr;
-    pa.b = k->ntt[logq];
+    pa.b = evk_ntt;
     pa.out = Rk;
     pa.group_stride = (long long)Kr * NN;
     pa.out_stride = 2LL * Kr * NN;
@@ -500,26 +540,37 @@ int mul_relin_locked(fhe_ctx* c, fhe_evk* k, int logN, int logq, const uint32_t*
     pa.pc = c->pc;
     e = launch_relin_pointwise(pa, cnum, st);
   }
-  // 9. inverse NTT
+  // 9. inverse NTT; 10. Garner -> k0, k1 mod 2^(logP + logq)
   if (e == hipSuccess)
-    e = launch_ntt(ntt_args(c, Rk, logN, Kr, 2 * Kr, 2LL * Kr * NN, true, c->gscale[logN]), cnum * 2 * Kr,
-                   true, st);
-  // 10. Garner -> k0, k1 mod 2^(logP + logq)
-  if (e == hipSuccess)
-    e = run_garner(c, st,
-                   garner_args(c, Rk, 2, 2LL * Kr * NN, (long long)Kr * NN, Kl, (long long)LK * NN, N, Kr,
-                               logP + logq, owr),
-                   cnum * 2);
-  // 11. c_i = [d_i + R(k_i)]_(2^logq)
+    e = launch_ntt(ntt_args(c, Rk, logN, Kr, 2 * Kr, 2LL * Kr * NN, true, c->gscale[logN]), cnum * 2 * Kr, true,
+                   st, tu);
+  if (e == hipSuccess) {
+    GarnerArgs ga = garner_args(c, Rk, 2, 2LL * Kr * NN, (long long)Kr * NN, Kl, (long long)LK * NN, N, Kr,
+                                logP + logq, owr);
+    ga.dig = dig;
+    e = launch_garner(ga, cnum * 2, st);
+  }
+  // 11. c_i = [d_i + R(k_i)]_(2^logq), to the outputs or (rescale follows) the staging area
+  const uint32_t* pwt = nullptr;
+  if (e == hipSuccess && k->scheme == FHE_BGV) pwt = pow_table(c, k->t, &e);
   if (e == hipSuccess) {
     ComposeArgs ca{};
     ca.k = Kl;
     ca.kstride = (long long)LK * NN;
     ca.d = Dl;
     ca.dstride = polyw;
-    ca.out0 = out0;
-    ca.out1 = out1;
-    ca.ostride = ostride;
+    if (bits > 0) {
+      ca.out0 = stage;
+      ca.out1 = stage + (long long)cnum * polyw;
+      ca.ostride = polyw;
+    } else if (io.outs) {
+      ca.out0s = io.outs;
+      ca.out1s = io.outs + cnum;
+    } else {
+      ca.out0 = io.out0;
+      ca.out1 = io.out1;
+      ca.ostride = polyw;
+    }
     ca.N = N;
     ca.L = L;
     ca.LK = LK;
@@ -529,11 +580,56 @@ int mul_relin_locked(fhe_ctx* c, fhe_evk* k, int logN, int logq, const uint32_t*
     if (k->scheme == FHE_BGV) {
       ca.t = k->t;
       ca.invP = (uint32_t)invmod(powmod(2, logP, k->t), k->t);
-      ca.pw = pow_table(c, k->t, &e);
+      ca.pw = pwt;
     }
-    if (e == hipSuccess) e = launch_compose(ca, cnum, st);
+    e = launch_compose(ca, cnum, st);
+  }
+  // 12. rescale into the outputs
+  if (e == hipSuccess && bits > 0) {
+    RescaleArgs ra{};
+    ra.in0 = stage;
+    ra.in1 = stage + (long long)cnum * polyw;
+    ra.istride = polyw;
+    if (io.outs) {
+      ra.out0s = io.outs;
+      ra.out1s = io.outs + cnum;
+    } else {
+      ra.out0 = io.out0;
+      ra.out1 = io.out1;
+      ra.ostride = (long long)((logq - bits + 31) / 32) * NN;
+    }
+    ra.N = N;
+    ra.logq = logq;
+    ra.bits = bits;
+    ra.scheme = k->scheme;
+    if (k->scheme == FHE_BGV) {
+      ra.t = k->t;
+      ra.invB = (uint32_t)invmod(powmod(2, bits, k->t), k->t);
+      ra.pw = pwt;
+    }
+    e = launch_rescale(ra, cnum, st);
   }
   return set_sticky(c, e);
+}
+
+// Per-op entry: scratch from the stream's slots, key prepared for the level.
+int mul_relin_locked(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, const PipeIO& io, int cnum,
+                     hipStream_t st) {
+  int rc = evk_prepare_locked(k, logq, st);
+  if (rc != FHE_OK) return rc;
+  const PipeSize z = pipe_size(c, k, logN, logq, cnum);
+  if (z.Kt < 0 || z.Kr < 0) return FHE_E_RANGE;
+  hipError_t e = hipSuccess;
+  uint32_t* ws = (uint32_t*)scratch(c, st, 0, (size_t)z.main_words * 4, &e);
+  if (!ws) return set_sticky(c, e);
+  uint32_t* stage = nullptr;
+  if (bits > 0) {
+    stage = (uint32_t*)scratch(c, st, 1, (size_t)z.stage_words * 4, &e);
+    if (!stage) return set_sticky(c, e);
+  }
+  uint32_t* dig = (uint32_t*)scratch(c, st, 2, (size_t)z.digit_words * 4, &e);
+  if (!dig) return set_sticky(c, e);
+  return pipeline(c, k, logN, logq, bits, io, cnum, st, ws, stage, dig, Tuning());
 }
 
 int rescale_locked(fhe_ctx* c, int scheme, uint32_t t, int logN, int logq, int bits,
@@ -559,6 +655,89 @@ int rescale_locked(fhe_ctx* c, int scheme, uint32_t t, int logN, int logq, int b
   }
   e = launch_rescale(ra, cnum, st);
   return set_sticky(c, e);
+}
+
+// Runs every cell of a plan on `st` (no graph).
+int plan_run_cells(fhe_plan* pl, hipStream_t st) {
+  for (PlanCell& cell : pl->cells) {
+    PipeIO io;
+    io.ins = cell.ptrs;
+    io.outs = cell.ptrs + 4LL * cell.cnum;
+    const int rc = pipeline(pl->ctx, cell.evk, cell.logN, cell.logq, cell.bits, io, cell.cnum, st, pl->ws,
+                            pl->stage, pl->dig, cell.tune);
+    if (rc != FHE_OK) return rc;
+  }
+  return FHE_OK;
+}
+
+// Autotuner: times each candidate launch configuration of one cell (one warm-up, then
+// the median of three runs) and keeps the fastest.  Candidates: lift primes per
+// thread 8 / 16 / 32; for odd logN, which NTT pass takes the extra stage.
+int plan_autotune(fhe_plan* pl, PlanCell& cell, hipStream_t st) {
+  fhe_ctx* c = pl->ctx;
+  const PipeSize z = pipe_size(c, cell.evk, cell.logN, cell.logq, cell.cnum);
+  const std::vector<int> key = {cell.logN, cell.logq, cell.evk->logP, z.Kt, z.Kr, cell.cnum};
+  auto it = c->tuned.find(key);
+  if (it != c->tuned.end()) {
+    cell.tune = it->second;
+    return FHE_OK;
+  }
+  std::vector<Tuning> cands;
+  for (int lp : {8, 16, 32})
+    for (int cf : {1, 0}) {
+      if (cf == 0 && (cell.logN % 2 == 0)) continue;  // same split either way
+      Tuning t;
+      t.lift_primes = lp;
+      t.ntt_cols_first = cf;
+      cands.push_back(t);
+    }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return FHE_E_DEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return FHE_E_DEVICE;
+  }
+  PipeIO io;
+  io.ins = cell.ptrs;
+  io.outs = cell.ptrs + 4LL * cell.cnum;
+  float best = 1e30f;
+  Tuning bt = cands[0];
+  int rc = FHE_OK;
+  for (const Tuning& t : cands) {
+    float ts[3];
+    rc = pipeline(c, cell.evk, cell.logN, cell.logq, cell.bits, io, cell.cnum, st, pl->ws, pl->stage, pl->dig, t);
+    for (int r = 0; r < 3 && rc == FHE_OK; ++r) {
+      hipEventRecord(e0, st);
+      rc = pipeline(c, cell.evk, cell.logN, cell.logq, cell.bits, io, cell.cnum, st, pl->ws, pl->stage, pl->dig,
+                    t);
+      hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ts[r], e0, e1) != hipSuccess)
+        rc = FHE_E_DEVICE;
+    }
+    if (rc != FHE_OK) break;
+    std::sort(ts, ts + 3);
+    if (ts[1] < best) {
+      best = ts[1];
+      bt = t;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != FHE_OK) return rc;
+  cell.tune = bt;
+  c->tuned[key] = bt;
+  return FHE_OK;
+}
+
+void plan_free(fhe_plan* pl) {
+  if (pl->exec) hipGraphExecDestroy(pl->exec);
+  if (pl->graph) hipGraphDestroy(pl->graph);
+  if (pl->cap) hipStreamDestroy(pl->cap);
+  for (PlanCell& cell : pl->cells)
+    if (cell.ptrs) hipFree(cell.ptrs);
+  for (void* p : {(void*)pl->ws, (void*)pl->stage, (void*)pl->dig})
+    if (p) hipFree(p);
+  delete pl;
 }
 
 bool valid_t(int scheme, uint32_t t) {
@@ -978,8 +1157,14 @@ int fhe_mul_relin(fhe_ctx* c, fhe_evk* k, int logN, int logq, const uint32_t* x0
   if (c->sticky != FHE_OK) return c->sticky;
   hipSetDevice(c->device);
   RecGuard rg(c);
-  const long long ostride = (long long)((logq + 31) / 32) << logN;
-  return mul_relin_locked(c, k, logN, logq, x0, x1, y0, y1, out0, out1, ostride, cnum, (hipStream_t)stream);
+  PipeIO io;
+  io.x0 = x0;
+  io.x1 = x1;
+  io.y0 = y0;
+  io.y1 = y1;
+  io.out0 = out0;
+  io.out1 = out1;
+  return mul_relin_locked(c, k, logN, logq, 0, io, cnum, (hipStream_t)stream);
 }
 
 int fhe_rescale(fhe_ctx* c, int scheme, uint32_t t, int logN, int logq, int bits, const uint32_t* in0,
@@ -1013,18 +1198,164 @@ int fhe_mul_relin_rescale(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, 
   if (c->sticky != FHE_OK) return c->sticky;
   hipSetDevice(c->device);
   RecGuard rg(c);
+  PipeIO io;
+  io.x0 = x0;
+  io.x1 = x1;
+  io.y0 = y0;
+  io.y1 = y1;
+  io.out0 = out0;
+  io.out1 = out1;
+  return mul_relin_locked(c, k, logN, logq, bits, io, cnum, (hipStream_t)stream);
+}
+
+int fhe_batch_plan(fhe_ctx* c, const fhe_job* jobs, int njobs, int flags, void* stream, fhe_plan** out) {
+  if (!c || !out || njobs < 0 || (njobs > 0 && !jobs) || (flags & ~(FHE_PLAN_GRAPH | FHE_PLAN_AUTOTUNE)))
+    return FHE_E_INVAL;
+  *out = nullptr;
+  for (int i = 0; i < njobs; ++i) {
+    const fhe_job& j = jobs[i];
+    if (!j.evk || !j.x0 || !j.x1 || !j.y0 || !j.y1 || !j.out0 || !j.out1) return FHE_E_INVAL;
+    if (j.evk->ctx != c) return FHE_E_STATE;
+    if (j.logq < 1 || j.logq > j.evk->logQ) return FHE_E_RANGE;
+    if (j.bits < 0 || j.bits >= j.logq) return FHE_E_INVAL;
+  }
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (c->sticky != FHE_OK) return c->sticky;
+  hipSetDevice(c->device);
   hipStream_t st = (hipStream_t)stream;
-  const long long polyw = (long long)((logq + 31) / 32) << logN;
-  // relinearized ciphertexts go to a scratch area of their own, then rescale into out
-  hipError_t e = hipSuccess;
-  const size_t extra = (size_t)2 * cnum * polyw * 4;
-  uint32_t* tmp = (uint32_t*)scratch(c, stream, 1, extra, &e);
-  if (!tmp) return set_sticky(c, e);
-  int rc = mul_relin_locked(c, k, logN, logq, x0, x1, y0, y1, tmp, tmp + (long long)cnum * polyw, polyw, cnum, st);
-  if (rc != FHE_OK) return rc;
-  const long long ostride = (long long)((logq - bits + 31) / 32) << logN;
-  return rescale_locked(c, k->scheme, k->t, logN, logq, bits, tmp, tmp + (long long)cnum * polyw, polyw, out0,
-                        out1, ostride, cnum, st);
+  fhe_plan* pl = new (std::nothrow) fhe_plan();
+  if (!pl) return FHE_E_NOMEM;
+  pl->ctx = c;
+  // cells in order of first appearance
+  std::vector<std::vector<int>> members;
+  for (int i = 0; i < njobs; ++i) {
+    size_t ci = 0;
+    for (; ci < pl->cells.size(); ++ci) {
+      const PlanCell& cc = pl->cells[ci];
+      if (cc.evk == jobs[i].evk && cc.logq == jobs[i].logq && cc.bits == jobs[i].bits) break;
+    }
+    if (ci == pl->cells.size()) {
+      PlanCell nc;
+      nc.evk = jobs[i].evk;
+      nc.logN = jobs[i].evk->logN;
+      nc.logq = jobs[i].logq;
+      nc.bits = jobs[i].bits;
+      pl->cells.push_back(nc);
+      members.emplace_back();
+    }
+    members[ci].push_back(i);
+  }
+  int rc = FHE_OK;
+  long long mw = 0, sw = 0, dw = 0;
+  for (size_t ci = 0; ci < pl->cells.size() && rc == FHE_OK; ++ci) {
+    PlanCell& cell = pl->cells[ci];
+    cell.cnum = (int)members[ci].size();
+    rc = evk_prepare_locked(cell.evk, cell.logq, st);
+    if (rc != FHE_OK) break;
+    {
+      // tables the pipeline would otherwise upload lazily (not allowed under capture)
+      hipError_t e = hipSuccess;
+      if (!offsets(c, 2 * cell.logq + cell.logN + 1, &e) ||
+          !offsets(c, cell.logN + 2 * cell.logq + cell.evk->logP, &e) ||
+          (cell.evk->scheme == FHE_BGV && !pow_table(c, cell.evk->t, &e))) {
+        rc = set_sticky(c, e);
+        break;
+      }
+    }
+    const PipeSize z = pipe_size(c, cell.evk, cell.logN, cell.logq, cell.cnum);
+    if (z.Kt < 0 || z.Kr < 0) {
+      rc = FHE_E_RANGE;
+      break;
+    }
+    mw = std::max(mw, z.main_words);
+    sw = std::max(sw, z.stage_words);
+    dw = std::max(dw, z.digit_words);
+    std::vector<const uint32_t*> h(6 * (size_t)cell.cnum);
+    for (int m = 0; m < cell.cnum; ++m) {
+      const fhe_job& j = jobs[members[ci][m]];
+      h[m] = j.x0;
+      h[cell.cnum + m] = j.x1;
+      h[2 * cell.cnum + m] = j.y0;
+      h[3 * cell.cnum + m] = j.y1;
+      h[4 * cell.cnum + m] = j.out0;
+      h[5 * cell.cnum + m] = j.out1;
+    }
+    hipError_t e = hipMalloc((void**)&cell.ptrs, h.size() * sizeof(void*));
+    if (e == hipSuccess) e = hipMemcpy(cell.ptrs, h.data(), h.size() * sizeof(void*), hipMemcpyHostToDevice);
+    if (e != hipSuccess) rc = set_sticky(c, e);
+  }
+  if (rc == FHE_OK) {
+    hipError_t e = hipMalloc((void**)&pl->ws, (size_t)std::max(mw, 1LL) * 4);
+    if (e == hipSuccess) e = hipMalloc((void**)&pl->stage, (size_t)std::max(sw, 1LL) * 4);
+    if (e == hipSuccess) e = hipMalloc((void**)&pl->dig, (size_t)std::max(dw, 1LL) * 4);
+    if (e != hipSuccess) rc = set_sticky(c, e);
+  }
+  if (rc == FHE_OK && (flags & FHE_PLAN_AUTOTUNE)) {
+    set_recorder(nullptr);
+    for (PlanCell& cell : pl->cells)
+      if ((rc = plan_autotune(pl, cell, st)) != FHE_OK) break;
+  }
+  if (rc == FHE_OK) {
+    const long long k0 = kernel_launch_count();
+    set_recorder(nullptr);
+    if (flags & FHE_PLAN_GRAPH) {
+      hipError_t e = hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        rc = plan_run_cells(pl, pl->cap);
+        hipGraph_t gr = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(pl->cap, &gr);
+        pl->graph = gr;
+        if (rc == FHE_OK && e2 != hipSuccess) e = e2;
+      }
+      if (rc == FHE_OK && e == hipSuccess) e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
+      if (rc == FHE_OK && e != hipSuccess) rc = set_sticky(c, e);
+      pl->kernels = (int)(kernel_launch_count() - k0);
+    } else {
+      // count the launches of one run without running it twice: plan runs are
+      // deterministic, so run once now (the first execution)
+      rc = plan_run_cells(pl, st);
+      pl->kernels = (int)(kernel_launch_count() - k0);
+    }
+  }
+  if (rc == FHE_OK) {
+    const hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) rc = set_sticky(c, e);
+  }
+  if (rc != FHE_OK) {
+    plan_free(pl);
+    return rc;
+  }
+  *out = pl;
+  return FHE_OK;
+}
+
+int fhe_batch_run(fhe_plan* pl, void* stream) {
+  if (!pl || !pl->ctx) return FHE_E_INVAL;
+  fhe_ctx* c = pl->ctx;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (c->sticky != FHE_OK) return c->sticky;
+  hipSetDevice(c->device);
+  if (pl->exec) return set_sticky(c, hipGraphLaunch(pl->exec, (hipStream_t)stream));
+  RecGuard rg(c);
+  return plan_run_cells(pl, (hipStream_t)stream);
+}
+
+int fhe_batch_info(const fhe_plan* pl, int* cells, int* kernels, int* graphed) {
+  if (!pl || !cells || !kernels || !graphed) return FHE_E_INVAL;
+  *cells = (int)pl->cells.size();
+  *kernels = pl->kernels;
+  *graphed = pl->exec != nullptr;
+  return FHE_OK;
+}
+
+void fhe_batch_destroy(fhe_plan* pl) {
+  if (!pl) return;
+  if (pl->ctx) {
+    hipSetDevice(pl->ctx->device);
+    hipDeviceSynchronize();
+  }
+  plan_free(pl);
 }
 
 }  // extern "C"

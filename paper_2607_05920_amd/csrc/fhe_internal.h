@@ -14,60 +14,61 @@ constexpr int kLiftDigitBits = 28;    // lift input digits: 8 digits = 7 limbs
 constexpr int kHornerDigitBits = 26;  // Garner output radix
 constexpr int kGarnerBlock = 16;      // digits finalized per block (accumulators)
 constexpr int kHornerBlock = 16;      // output columns per block
-constexpr int kLiftPrimes = 16;       // primes per lift thread
+constexpr int kLiftPrimes = 32;       // largest primes-per-thread choice of the lift
 constexpr int kGarnerGS = 256;        // row stride of the host's square digit table (K <= 224)
 
 // Negacyclic NTT over a set of transforms.  Transform (group g, row r) lives at
 // data + g * group_stride + r * N and uses prime r % K; per_group (rows per group)
 // and the number of transforms are multiples of K.
 struct NttArgs {
-  uint32_t* data;
-  int logN;
-  int K;
-  int per_group;
-  long long group_stride;
-  const uint2* tw;     // [prime][kNMax] (w, floor(w 2^32 / q)), bit-reversed powers
-  const PrimeC* pc;
-  const uint2* scale;  // inverse only: per-prime final factor (w, w')
-  int ntr;             // number of transforms (set by launch_ntt; a multiple of K)
+  uint32_t* data = nullptr;
+  int logN = 0;
+  int K = 0;
+  int per_group = 0;
+  long long group_stride = 0;
+  const uint2* tw = nullptr; // [prime][kNMax] (w, floor(w 2^32 / q)), bit-reversed powers
+  const PrimeC* pc = nullptr;
+  const uint2* scale = nullptr; // inverse only: per-prime final factor (w, w')
+  int ntr = 0;         // number of transforms (set by launch_ntt; a multiple of K)
 };
 
 struct LiftArgs {
-  const uint32_t* limbs;  // poly z at limbs + z * in_stride, uint32[L][N]
-  uint32_t* res;          // poly z at res + z * out_stride, uint32[K][N]
-  long long in_stride, out_stride;
-  int N, L, K;
-  int npoly;          // set by launch_lift
-  const uint32_t* T;  // [prime][TS]: 2^(28 i) 2^32 mod q
-  int TS;
-  const PrimeC* pc;
+  const uint32_t* limbs = nullptr; // poly z at limbs + z * in_stride, uint32[L][N] (or in_ptrs[z])
+  const uint32_t* const* in_ptrs = nullptr;  // optional device array of per-poly inputs
+  uint32_t* res = nullptr;          // poly z at res + z * out_stride, uint32[K][N]
+  long long in_stride = 0, out_stride = 0;
+  int N = 0, L = 0, K = 0;
+  int npoly = 0;          // set by launch_lift
+  const uint32_t* T = nullptr; // [prime][TS]: 2^(28 i) 2^32 mod q
+  int TS = 0;
+  const PrimeC* pc = nullptr;
 };
 
 struct PointwiseArgs {
-  uint32_t* a;        // tensor: group c at a + c * group_stride, 4 x [K][N] (x0, x1, y0, y1)
-  const uint32_t* b;  // relin: key (B', A') [2][K][N]; ring: second operand
-  uint32_t* out;
-  long long group_stride, out_stride;
-  int N, K;
-  const PrimeC* pc;
+  uint32_t* a = nullptr; // tensor: group c at a + c * group_stride, 4 x [K][N] (x0, x1, y0, y1)
+  const uint32_t* b = nullptr; // relin: key (B', A') [2][K][N]; ring: second operand
+  uint32_t* out = nullptr;
+  long long group_stride = 0, out_stride = 0;
+  int N = 0, K = 0;
+  const PrimeC* pc = nullptr;
 };
 
 struct GarnerArgs {
-  const uint32_t* res;  // poly z: res + (z / per_group) * gstride + (z % per_group) * pstride
-  int per_group;
-  long long gstride, pstride;
-  uint32_t* out;  // poly z: out + z * ostride, uint32[Lout][N]
-  long long ostride;
-  int N, K, outbits, Lout;
-  const PrimeC* pc;
-  const uint32_t* Gt;  // digit block b: 16-word rows j of [M_j I_k 2^32]_(q_k), k = 16b..16b+15,
-  int GS;              //   at word 256 b (b + 1) / 2 (GS unused)
-  const uint32_t* Ow;  // [k] = [2^e I_k]_(q_k)
-  const uint32_t* Ct;  // column block c: 16-word rows k of radix-2^26 digits 16c.. of M_k,
-  int CS;              //   at word c CS
-  const int* kstart;   // [m] = min k with M_k >= 2^(26 m)
-  const int* mbits;    // host: bit length of M_k (work accounting only)
-  uint32_t* dig;       // digit scratch: wave w's region at dig + w * garner_wave_words(K)
+  const uint32_t* res = nullptr; // poly z: res + (z / per_group) * gstride + (z % per_group) * pstride
+  int per_group = 0;
+  long long gstride = 0, pstride = 0;
+  uint32_t* out = nullptr;  // poly z: out + z * ostride, uint32[Lout][N]
+  long long ostride = 0;
+  int N = 0, K = 0, outbits = 0, Lout = 0;
+  const PrimeC* pc = nullptr;
+  const uint32_t* Gt = nullptr; // digit block b: 16-word rows j of [M_j I_k 2^32]_(q_k), k = 16b..16b+15,
+  int GS = 0;          //   at word 256 b (b + 1) / 2 (GS unused)
+  const uint32_t* Ow = nullptr; // [k] = [2^e I_k]_(q_k)
+  const uint32_t* Ct = nullptr;  // column block c: 16-word rows k of radix-2^26 digits 16c.. of M_k,
+  int CS = 0;              //   at word c CS
+  const int* kstart = nullptr; // [m] = min k with M_k >= 2^(26 m)
+  const int* mbits = nullptr; // host: bit length of M_k (work accounting only)
+  uint32_t* dig = nullptr; // digit scratch: wave w's region at dig + w * garner_wave_words(K)
 };
 
 // Words of digit scratch per wave of 64 coefficients: the digits padded to the
@@ -75,27 +76,31 @@ struct GarnerArgs {
 __host__ __device__ inline long long garner_wave_words(int K) { return (long long)((K + 15) / 16 * 16 + 2) * 64; }
 
 struct ComposeArgs {
-  const uint32_t* k;  // poly z (= 2 c + i): k + z * kstride, uint32[LK][N]
-  long long kstride;
-  const uint32_t* d;  // d_i of ciphertext c at d + (3 c + i) * dstride, uint32[L][N]
-  long long dstride;
-  uint32_t* out0;
-  uint32_t* out1;
-  long long ostride;  // per ciphertext, uint32[L][N]
-  int N, L, LK, logq, logP, scheme;
-  uint32_t t, invP;  // BGV: t and 2^-logP mod t
-  const uint32_t* pw;  // BGV: pw[l] = 2^(32 l) mod t
+  const uint32_t* k = nullptr; // poly z (= 2 c + i): k + z * kstride, uint32[LK][N]
+  long long kstride = 0;
+  const uint32_t* d = nullptr; // d_i of ciphertext c at d + (3 c + i) * dstride, uint32[L][N]
+  long long dstride = 0;
+  uint32_t* out0 = nullptr;
+  uint32_t* out1 = nullptr;
+  long long ostride = 0;  // per ciphertext, uint32[L][N]
+  uint32_t* const* out0s = nullptr;  // optional device arrays of per-ciphertext outputs
+  uint32_t* const* out1s = nullptr;
+  int N = 0, L = 0, LK = 0, logq = 0, logP = 0, scheme = 0;
+  uint32_t t = 0, invP = 0;  // BGV: t and 2^-logP mod t
+  const uint32_t* pw = nullptr; // BGV: pw[l] = 2^(32 l) mod t
 };
 
 struct RescaleArgs {
-  const uint32_t* in0;
-  const uint32_t* in1;
-  uint32_t* out0;
-  uint32_t* out1;
-  long long istride, ostride;
-  int N, logq, bits, scheme;
-  uint32_t t, invB;  // BGV: t and 2^-bits mod t
-  const uint32_t* pw;
+  const uint32_t* in0 = nullptr;
+  const uint32_t* in1 = nullptr;
+  uint32_t* out0 = nullptr;
+  uint32_t* out1 = nullptr;
+  long long istride = 0, ostride = 0;
+  uint32_t* const* out0s = nullptr;  // optional device arrays of per-ciphertext outputs
+  uint32_t* const* out1s = nullptr;
+  int N = 0, logq = 0, bits = 0, scheme = 0;
+  uint32_t t = 0, invB = 0;  // BGV: t and 2^-bits mod t
+  const uint32_t* pw = nullptr;
 };
 
 // Optional per-kernel timing: when a recorder is installed, every launcher records
@@ -120,9 +125,18 @@ struct EventRecorder {
 };
 
 void set_recorder(EventRecorder* r);  // host thread-local
+long long kernel_launch_count();      // kernels launched by this host thread so far
 
-hipError_t launch_ntt(const NttArgs& a, int ntransforms, bool inverse, hipStream_t s);
-hipError_t launch_lift(const LiftArgs& a, int npoly, hipStream_t s);
+// Launch parameters chosen by the autotuner (defaults: 16 primes per lift thread,
+// NTT column pass of ceil(logN / 2) stages).
+struct Tuning {
+  int lift_primes = 16;  // 8, 16 or 32
+  int ntt_cols_first = 1;  // 1: column pass takes ceil(logN/2) stages; 0: floor
+};
+
+hipError_t launch_ntt(const NttArgs& a, int ntransforms, bool inverse, hipStream_t s,
+                      const Tuning& t = Tuning());
+hipError_t launch_lift(const LiftArgs& a, int npoly, hipStream_t s, const Tuning& t = Tuning());
 hipError_t launch_tensor_pointwise(const PointwiseArgs& a, int cnum, hipStream_t s);
 hipError_t launch_relin_pointwise(const PointwiseArgs& a, int cnum, hipStream_t s);
 hipError_t launch_ring_pointwise(const PointwiseArgs& a, int cnum, hipStream_t s);

@@ -9,7 +9,9 @@
 namespace fhe {
 
 static thread_local EventRecorder* g_rec = nullptr;
+static thread_local long long g_launches = 0;
 void set_recorder(EventRecorder* r) { g_rec = r; }
+long long kernel_launch_count() { return g_launches; }
 
 // Brackets one kernel launch with the recorder's events; `work` is the kernel's
 // algorithmic 32x32-bit word-product count (0 when not tracked).
@@ -18,6 +20,7 @@ struct Bracket {
   hipStream_t s;
   double work;
   Bracket(int k, hipStream_t st, double w) : kid(k), s(st), work(w) {
+    ++g_launches;
     if (g_rec) g_rec->begin(kid, s);
   }
   ~Bracket() {
@@ -228,12 +231,14 @@ static hipError_t ntt_pass_s(int S, const NttArgs& a, int ntr, hipStream_t st) {
   }
 }
 
-hipError_t launch_ntt(const NttArgs& a0, int ntr, bool inverse, hipStream_t st) {
+hipError_t launch_ntt(const NttArgs& a0, int ntr, bool inverse, hipStream_t st, const Tuning& tu) {
   if (ntr <= 0) return hipSuccess;
   if (ntr % a0.K != 0 || a0.per_group % a0.K != 0) return hipErrorInvalidValue;
   NttArgs a = a0;
   a.ntr = ntr;
-  const int s_rows = a.logN / 2, s_cols = a.logN - s_rows;
+  // the split groups the same stages differently and does not change the result
+  const int s_cols = tu.ntt_cols_first ? a.logN - a.logN / 2 : a.logN / 2;
+  const int s_rows = a.logN - s_cols;
   hipError_t e;
   if (!inverse) {
     if ((e = ntt_pass_s<false, false>(s_cols, a, ntr, st)) != hipSuccess) return e;
@@ -265,7 +270,7 @@ __global__ __launch_bounds__(256) void lift_kernel(LiftArgs a) {
   const int z = unit / nb;
   const int jc = (unit % nb) * 256 + threadIdx.x;  // coefficient
   if (jc >= a.N) return;
-  const uint32_t* src = a.limbs + (long long)z * a.in_stride + jc;
+  const uint32_t* src = (a.in_ptrs ? a.in_ptrs[z] : a.limbs + (long long)z * a.in_stride) + jc;
   uint64_t acc[PB];
 #pragma unroll
   for (int pp = 0; pp < PB; ++pp) acc[pp] = 0;
@@ -305,16 +310,25 @@ __global__ __launch_bounds__(256) void lift_kernel(LiftArgs a) {
   }
 }
 
-hipError_t launch_lift(const LiftArgs& a, int npoly, hipStream_t st) {
+template <int PB>
+static void lift_launch(const LiftArgs& b, int npoly, hipStream_t st) {
+  const int G = (b.K + PB - 1) / PB;
+  const int units = ((b.N + 255) / 256) * npoly;
+  dim3 grid(8 * ((units + 7) / 8) * G);
+  hipLaunchKernelGGL((lift_kernel<PB>), grid, dim3(256), 0, st, b);
+}
+
+hipError_t launch_lift(const LiftArgs& a, int npoly, hipStream_t st, const Tuning& t) {
   if (npoly <= 0) return hipSuccess;
   LiftArgs b = a;
   b.npoly = npoly;
-  const int G = (a.K + kLiftPrimes - 1) / kLiftPrimes;
-  const int units = ((a.N + 255) / 256) * npoly;
-  dim3 grid(8 * ((units + 7) / 8) * G);
   // algorithmic work: L limb-constant products per (coefficient, prime)
   Bracket br(KID_LIFT, st, (double)npoly * a.N * a.K * a.L);
-  hipLaunchKernelGGL((lift_kernel<kLiftPrimes>), grid, dim3(256), 0, st, b);
+  switch (t.lift_primes) {
+    case 8: lift_launch<8>(b, npoly, st); break;
+    case 32: lift_launch<32>(b, npoly, st); break;
+    default: lift_launch<16>(b, npoly, st); break;
+  }
   return hipGetLastError();
 }
 
@@ -664,7 +678,7 @@ __global__ __launch_bounds__(256) void compose_kernel(ComposeArgs a) {
   const int c = z >> 1, i = z & 1;
   const uint32_t* k = a.k + (long long)z * a.kstride + jc;
   const uint32_t* d = a.d + (long long)(3 * c + i) * a.dstride + jc;
-  uint32_t* o = (i ? a.out1 : a.out0) + (long long)c * a.ostride + jc;
+  uint32_t* o = (a.out0s ? (i ? a.out1s[c] : a.out0s[c]) : (i ? a.out1 : a.out0) + (long long)c * a.ostride) + jc;
   const int64_t corr = round_correction(k, a.N, a.LK, a.logP, a.scheme, a.t, a.invP, a.pw);
   const int sl = a.logP >> 5, rs = a.logP & 31;
   const uint32_t ext = corr < 0 ? 0xFFFFFFFFu : 0u;
@@ -693,7 +707,7 @@ __global__ __launch_bounds__(256) void rescale_kernel(RescaleArgs a) {
   const int newq = a.logq - a.bits;
   const int Lout = (newq + 31) >> 5;
   const uint32_t* x = (i ? a.in1 : a.in0) + (long long)c * a.istride + jc;
-  uint32_t* o = (i ? a.out1 : a.out0) + (long long)c * a.ostride + jc;
+  uint32_t* o = (a.out0s ? (i ? a.out1s[c] : a.out0s[c]) : (i ? a.out1 : a.out0) + (long long)c * a.ostride) + jc;
   const int64_t corr = round_correction(x, a.N, Lin, a.bits, a.scheme, a.t, a.invB, a.pw);
   const int sl = a.bits >> 5, rs = a.bits & 31;
   const uint32_t ext = corr < 0 ? 0xFFFFFFFFu : 0u;

@@ -1,0 +1,100 @@
+"""GPU: batched uneven HE-mults (fhe_batch_plan / fhe_batch_run) against per-op calls
+and the oracle, eager and graph-captured, with the autotuner on and off."""
+import numpy as np
+import pytest
+
+import paper_2607_05920_amd as fhe
+import synth
+from oracle import scheme
+from tests.gpu_helpers import dev, host, ints, oracle_ct, say
+
+pytestmark = pytest.mark.gpu
+
+LOGQ_TOP = LOGP = 438
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    assert torch.cuda.is_available()
+    say("batch setup")
+    ctx = fhe.Context(LOGQ_TOP, LOGP)
+    rk, rm, _, rs = synth.streams(4)
+    keys, khost = {}, {}
+    for logN in (13, 14, 15, 16):
+        N = 1 << logN
+        eb = synth.uniform_limbs(rk, LOGQ_TOP + LOGP, N)
+        ea = synth.uniform_limbs(rk, LOGQ_TOP + LOGP, N)
+        keys[logN] = fhe.EvalKey(ctx, fhe.CKKS, 0, logN, LOGQ_TOP, LOGP, eb, ea)
+        khost[logN] = (eb, ea)
+    # 14 jobs over 8 cells: every logN with logq 218 and 438, some cells repeated
+    shapes = [(13, 218), (14, 438), (15, 218), (16, 438), (13, 438), (14, 218), (15, 438), (16, 218),
+              (13, 218), (16, 438), (14, 438), (13, 218), (15, 218), (16, 218)]
+    jobs, data = [], []
+    for logN, logq in shapes:
+        N = 1 << logN
+        x = [synth.uniform_limbs(rm, logq, N) for _ in range(2)]
+        y = [synth.uniform_limbs(rm, logq, N) for _ in range(2)]
+        Lo = synth.nlimbs(logq - 40)
+        outs = [torch.zeros(Lo * N, dtype=torch.int32, device="cuda") for _ in range(2)]
+        ins = [dev(v) for v in x + y]
+        jobs.append((keys[logN], logq, 40, *ins, *outs))
+        data.append((logN, logq, x, y))
+    yield ctx, keys, khost, jobs, data
+    for k in keys.values():
+        k.close()
+    ctx.close()
+
+
+def per_op(ctx, jobs):
+    import torch
+    res = []
+    for (evk, logq, bits, x0, x1, y0, y1, o0, o1) in jobs:
+        a, b = torch.empty_like(o0), torch.empty_like(o1)
+        ctx.mul_relin_rescale(evk, logq, bits, x0, x1, y0, y1, a, b)
+        res.append((a, b))
+    torch.cuda.synchronize()
+    return res
+
+
+@pytest.mark.parametrize("flags", [0, fhe.PLAN_GRAPH, fhe.PLAN_GRAPH | fhe.PLAN_AUTOTUNE])
+def test_batch_equals_per_op(setup, flags):
+    import torch
+    ctx, keys, khost, jobs, data = setup
+    say(f"batch flags={flags}")
+    ref = per_op(ctx, jobs)
+    for j in jobs:
+        j[7].zero_()
+        j[8].zero_()
+    plan = fhe.BatchPlan(ctx, jobs, flags=flags)
+    info = plan.info()
+    assert info["cells"] == 8 and info["graphed"] == bool(flags & fhe.PLAN_GRAPH)
+    for rep in range(3):
+        for j in jobs:           # eager work between replays
+            j[7].fill_(rep + 1)
+            j[8].fill_(-rep)
+        plan.run()
+        torch.cuda.synchronize()
+        for (j, (a, b)) in zip(jobs, ref):
+            assert torch.equal(j[7], a) and torch.equal(j[8], b)
+    plan.close()
+
+
+def test_batch_sampled_jobs_match_oracle(setup):
+    import torch
+    ctx, keys, khost, jobs, data = setup
+    say("batch vs oracle")
+    plan = fhe.BatchPlan(ctx, jobs, flags=fhe.PLAN_GRAPH)
+    plan.run()
+    torch.cuda.synchronize()
+    for i in (0, 5):   # (13, 218) and (14, 218): full oracle products are cheap
+        logN, logq, x, y = data[i]
+        N = 1 << logN
+        eb, ea = khost[logN]
+        evk = scheme.EvalKey(ints(eb), ints(ea), logN, LOGQ_TOP, LOGP)
+        want = scheme.mult_rescale(oracle_ct(*x, logN, logq, scheme.CKKS, 0), oracle_ct(*y, logN, logq, scheme.CKKS, 0),
+                                   evk, 40)
+        Lo = synth.nlimbs(logq - 40)
+        assert ints(host(jobs[i][7], (Lo, N))) == want.c0
+        assert ints(host(jobs[i][8], (Lo, N))) == want.c1
+    plan.close()
