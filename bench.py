@@ -117,6 +117,95 @@ def batched_uneven(fhe, torch, synth, dev, stream, njobs):
     return out
 
 
+def serving(fhe, torch, synth, dev, nreq, loads=(0.5, 0.8, 0.95), nstreams=4, max_batch=16,
+            budget=96 << 30):
+    """The request loop under open-loop Poisson arrivals.  Requests: CKKS with
+    probability 0.7 (rescale 40) else BGV (t = 65537, rescale 32); logN ~ U{15, 16};
+    logq ~ U{218, 438, 874, 1555}; four resident keys (scheme x N) at logQ = logP = 1555.
+    Operands come from a pool of 8 sets per (scheme, N, logq) cell; a request writes
+    the output pair of its pool index, so overlapping writers hold the same values.
+    mu_sat = completed / makespan of the whole stream queued at once; then Poisson
+    streams at load x mu_sat, served by the batching loop and by per-op FIFO launches
+    (one stream, batch of one).  Latency = completion seen by the scheduler - scheduled
+    arrival."""
+    import numpy as np
+
+    rk, rm, _, rs = synth.streams(5)
+    ctx = fhe.Context(LOGQ, LOGP)
+    keys = {}
+    for sch, t in ((fhe.CKKS, 0), (fhe.BGV, 65537)):
+        for n in (15, 16):
+            keys[(sch, n)] = fhe.EvalKey(ctx, sch, t, n, LOGQ, LOGP, synth.uniform_limbs(rk, LOGQ + LOGP, 1 << n),
+                                         synth.uniform_limbs(rk, LOGQ + LOGP, 1 << n))
+    sch_draw = np.where(rs.random(nreq) < 0.7, fhe.CKKS, fhe.BGV)
+    n_draw = rs.integers(15, 17, size=nreq)
+    q_draw = np.array([218, 438, 874, 1555])[rs.integers(0, 4, size=nreq)]
+    pool, reqs, used = {}, [], {}
+    for sch, n, q in zip(sch_draw.tolist(), n_draw.tolist(), q_draw.tolist()):
+        cell = (sch, n, q)
+        if cell not in pool:
+            N = 1 << n
+            bits = BITS if sch == fhe.CKKS else 32
+            Lo = synth.nlimbs(q - bits)
+            sets = []
+            for _ in range(8):
+                ins = [fhe.to_device(synth.uniform_limbs(rm, q, N)).reshape(-1) for _ in range(4)]
+                outs = [torch.zeros(Lo * N, dtype=torch.int32, device=dev) for _ in range(2)]
+                ref = [torch.zeros(Lo * N, dtype=torch.int32, device=dev) for _ in range(2)]
+                ctx.mul_relin_rescale(keys[(sch, n)], q, bits, *ins, *ref)
+                sets.append((ins, outs, ref))
+            pool[cell] = (bits, sets)
+        bits, sets = pool[cell]
+        k = used.get(cell, 0)
+        used[cell] = k + 1
+        ins, outs, _ = sets[k % 8]
+        reqs.append((keys[(sch, n)], q, bits, *ins, *outs))
+    torch.cuda.synchronize()
+
+    def run(rate, streams, batch, seed):
+        for _, sets in pool.values():
+            for _, outs, _ in sets:
+                for o in outs:
+                    o.zero_()
+        torch.cuda.synchronize()
+        srv = fhe.Server(ctx, budget, nstreams=streams, max_batch=batch)
+        rng = np.random.default_rng(seed)
+        t0 = fhe.clock_ns() + 200_000_000
+        gaps = np.zeros(nreq) if rate is None else rng.exponential(1e9 / rate, nreq)
+        for r, ta in zip(reqs, t0 + np.cumsum(gaps).astype(np.int64)):
+            srv.submit(r, int(ta))
+        srv.drain()
+        done = srv.poll(nreq + 16)
+        srv.close()
+        ok = len(done) == nreq and all(d.status == 0 for d in done)
+        lat = np.array([d.t_done - d.t_arrive for d in done], dtype=np.float64) / 1e6
+        span = (max(d.t_done for d in done) - t0) / 1e9
+        exact = all(torch.equal(o, r) for _, sets in pool.values() for _, outs, ref in sets
+                    for o, r in zip(outs, ref))
+        return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "throughput_per_s": nreq / span, "mean_batch": float(np.mean([d.batch for d in done])),
+                "all_ok": bool(ok), "bit_exact_vs_alone": bool(exact)}
+
+    log(f"serving: saturation ({nreq} requests at once)")
+    sat = run(None, nstreams, max_batch, 0)
+    mu = sat["throughput_per_s"]
+    runs = []
+    for i, f in enumerate(loads):
+        log(f"serving: load {f} of {mu:.0f}/s")
+        b = run(f * mu, nstreams, max_batch, 10 + i)
+        p = run(f * mu, 1, 1, 10 + i)
+        runs.append({"load": f, "rate_per_s": f * mu, "batched": b, "per_op_fifo": p,
+                     "p99_speedup_vs_per_op": p["p99_ms"] / b["p99_ms"]})
+    for k in keys.values():
+        k.close()
+    ctx.close()
+    return {"requests": nreq, "mu_sat_per_s": mu, "saturation_run": sat, "nstreams": nstreams,
+            "max_batch": max_batch, "hbm_budget_bytes": budget, "runs": runs,
+            "workload": "70% CKKS (rescale 40) / 30% BGV t=65537 (rescale 32), logN ~ U{15,16}, "
+                        "logq ~ U{218,438,874,1555}, 4 resident keys at logQ = logP = 1555, 8 operand sets "
+                        "per cell, open-loop Poisson arrivals (seed 5000)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +216,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip per-op and NTT legs")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched uneven leg")
     ap.add_argument("--batch-jobs", type=int, default=256)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run one plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -242,6 +333,10 @@ def main():
     if not args.no_extras and not args.no_batch:
         log("batched uneven leg")
         extras["batched_uneven"] = batched_uneven(fhe, torch, synth, dev, stream, args.batch_jobs)
+
+    if not args.no_extras and not args.no_serve:
+        log("serving leg")
+        extras["serving"] = serving(fhe, torch, synth, dev, args.serve_requests)
 
     if args.copy_calib_mb:
         nb = args.copy_calib_mb << 20

@@ -230,6 +230,53 @@ int fhe_batch_info(const fhe_plan* plan, int* cells, int* kernels, int* graphed)
 /* Release a plan (waits for the device).  NULL is a no-op. */
 void fhe_batch_destroy(fhe_plan* plan);
 
+/* ---------------------------------------------------------------- serving
+ * A request loop for HE-mult requests (one fhe_job each) that arrive over time.
+ * A scheduler thread keeps `nstreams` device streams busy: whenever one is free it
+ * forms a batch from the oldest pending request and the other pending requests of
+ * the same cell (key, logq, bits), up to `max_batch`, and launches it as one
+ * CipherTensor pipeline (continuous batching; batches on different streams overlap
+ * on the device).  Admission is by HBM footprint: the device scratch the server
+ * holds (every stream's workspace, rescale staging and Garner digits, sized to the
+ * batches it runs) never exceeds `hbm_budget` bytes.  A batch waits while it would
+ * not fit, idle streams give their scratch back when the budget requires it, a
+ * batch is cut to the size that fits, and a request that cannot fit even alone
+ * completes with status FHE_E_NOMEM.  The caller's operand and output buffers and
+ * the evaluation keys are not part of the budget.  Keys stay resident;
+ * key levels are prepared on first use (call fhe_evk_prepare first to keep that
+ * out of the loop).  Times are fhe_clock_ns() values. */
+typedef struct fhe_server fhe_server;
+
+typedef struct {
+  uint64_t ticket;   /* as returned by fhe_server_submit */
+  int status;        /* FHE_OK or an error code */
+  int batch;         /* size of the batch the request ran in */
+  uint64_t t_arrive; /* arrival time given at submit */
+  uint64_t t_start;  /* launch of its batch */
+  uint64_t t_done;   /* completion of its batch as seen by the scheduler */
+} fhe_done;
+
+/* Monotonic clock in nanoseconds (the server's time base). */
+uint64_t fhe_clock_ns(void);
+
+/* Start a server on a context.  nstreams in [1, 16], max_batch in [1, 256]. */
+int fhe_server_create(fhe_ctx* ctx, size_t hbm_budget, int nstreams, int max_batch, fhe_server** out);
+
+/* Queue one request (job fields as in fhe_batch_plan; the buffers must stay valid
+ * until the request is reported done).  arrival_ns = 0 means "now"; a time in the
+ * future (fhe_clock_ns base) makes the request eligible only from then on, so an
+ * arrival schedule can be queued ahead.  Latency is reported from arrival_ns. */
+int fhe_server_submit(fhe_server* srv, const fhe_job* job, uint64_t arrival_ns, uint64_t* ticket);
+
+/* Move up to `max` completed requests to `out` (host array); *n receives the count. */
+int fhe_server_poll(fhe_server* srv, fhe_done* out, int max, int* n);
+
+/* Block until every submitted request has completed. */
+int fhe_server_drain(fhe_server* srv);
+
+/* Stop the scheduler after the pending work completes and release the server. */
+void fhe_server_destroy(fhe_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -53,6 +53,12 @@ EXPORTS = {
     "fhe_batch_run": (_I, [_P, _P]),
     "fhe_batch_info": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "fhe_batch_destroy": (None, [_P]),
+    "fhe_clock_ns": (ctypes.c_uint64, []),
+    "fhe_server_create": (_I, [_P, ctypes.c_size_t, _I, _I, ctypes.POINTER(_P)]),
+    "fhe_server_submit": (_I, [_P, _P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]),
+    "fhe_server_poll": (_I, [_P, _P, _I, ctypes.POINTER(_I)]),
+    "fhe_server_drain": (_I, [_P]),
+    "fhe_server_destroy": (None, [_P]),
 }
 
 PLAN_GRAPH = 1
@@ -316,6 +322,57 @@ class BatchPlan:
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
             load_library().fhe_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Done(ctypes.Structure):
+    """fhe_done: completion record of one served request."""
+    _fields_ = [("ticket", ctypes.c_uint64), ("status", _I), ("batch", _I), ("t_arrive", ctypes.c_uint64),
+                ("t_start", ctypes.c_uint64), ("t_done", ctypes.c_uint64)]
+
+
+def clock_ns() -> int:
+    return int(load_library().fhe_clock_ns())
+
+
+class Server:
+    """Continuous-batching request loop (fhe_server_*).  Jobs are tuples
+    (evk, logq, bits, x0, x1, y0, y1, out0, out1) of torch CUDA tensors, which must stay
+    alive until reported done."""
+
+    def __init__(self, ctx: Context, hbm_budget: int, nstreams: int = 4, max_batch: int = 16):
+        h = ctypes.c_void_p()
+        _check("fhe_server_create", load_library().fhe_server_create(ctx.handle, hbm_budget, nstreams, max_batch,
+                                                                     ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+
+    def submit(self, job, arrival_ns: int = 0) -> int:
+        evk, logq, bits, x0, x1, y0, y1, o0, o1 = job
+        j = Job(evk.handle.value, logq, bits, _ptr(x0), _ptr(x1), _ptr(y0), _ptr(y1), _ptr(o0), _ptr(o1))
+        t = ctypes.c_uint64()
+        _check("fhe_server_submit", load_library().fhe_server_submit(self._h, ctypes.byref(j), arrival_ns,
+                                                                     ctypes.byref(t)))
+        return t.value
+
+    def poll(self, max_n: int = 1024):
+        buf = (Done * max_n)()
+        n = ctypes.c_int()
+        _check("fhe_server_poll", load_library().fhe_server_poll(self._h, buf, max_n, ctypes.byref(n)))
+        return [buf[i] for i in range(n.value)]
+
+    def drain(self):
+        _check("fhe_server_drain", load_library().fhe_server_drain(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load_library().fhe_server_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

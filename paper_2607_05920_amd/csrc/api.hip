@@ -3,11 +3,18 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
 #include <cstdio>
+#include <deque>
+#include <thread>
+#include <tuple>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <new>
+#include <queue>
 #include <vector>
 
 #include "fhe_internal.h"
@@ -740,6 +747,273 @@ void plan_free(fhe_plan* pl) {
   delete pl;
 }
 
+// ---------------------------------------------------------------- serving loop
+
+uint64_t now_ns() {
+  return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+struct SrvReq {
+  uint64_t ticket = 0, t_arrive = 0;
+  fhe_job job{};
+};
+
+// Orders scheduled arrivals earliest first (ties by ticket).
+struct SrvLater {
+  bool operator()(const SrvReq& a, const SrvReq& b) const {
+    return a.t_arrive != b.t_arrive ? a.t_arrive > b.t_arrive : a.ticket > b.ticket;
+  }
+};
+
+// Scratch words one batch needs (main workspace, rescale staging, Garner digits).
+struct SrvNeed {
+  long long main = 0, stage = 0, dig = 0;
+};
+
+// One worker stream with its own scratch and pointer staging.
+struct SrvSlot {
+  hipStream_t st = nullptr;
+  hipEvent_t done = nullptr;
+  bool busy = false;
+  std::vector<SrvReq> reqs;
+  uint64_t t_start = 0;
+  uint32_t *ws = nullptr, *stage = nullptr, *dig = nullptr;
+  long long ws_words = 0, stage_words = 0, dig_words = 0;
+  const uint32_t** hptr = nullptr;  // pinned host staging of the pointer arrays
+  uint32_t** dptr = nullptr;        // device pointer arrays (6 max_batch)
+};
+
+// Grows a device buffer to exactly `need` words when it holds fewer.
+hipError_t grow(uint32_t** p, long long* have, long long need, hipStream_t st) {
+  if (*have >= need) return hipSuccess;
+  if (*p) {
+    hipStreamSynchronize(st);
+    hipFree(*p);
+    *p = nullptr;
+    *have = 0;
+  }
+  hipError_t e = hipMalloc((void**)p, (size_t)std::max(need, 1LL) * 4);
+  if (e == hipSuccess) *have = need;
+  return e;
+}
+
+// Requests of one cell (key, logq, rescale bits) run together in one pipeline.
+typedef std::tuple<const fhe_evk*, int, int> SrvCell;
+
+SrvCell cell_of(const fhe_job& j) { return SrvCell(j.evk, j.logq, j.bits); }
+
+SrvNeed batch_need(const fhe_ctx* c, const fhe_job& j, int cnum) {
+  const PipeSize z = pipe_size(c, j.evk, j.evk->logN, j.logq, cnum);
+  SrvNeed n;
+  n.main = z.main_words;
+  n.stage = j.bits > 0 ? z.stage_words : 0;
+  n.dig = z.digit_words;
+  return n;
+}
+
+size_t need_bytes(const SrvNeed& n) { return (size_t)(n.main + n.stage + n.dig) * 4; }
+
+size_t slot_held(const SrvSlot& s) { return (size_t)(s.ws_words + s.stage_words + s.dig_words) * 4; }
+
+// Bytes the slot holds once grown for `n`.
+size_t slot_after(const SrvSlot& s, const SrvNeed& n) {
+  return (size_t)(std::max(s.ws_words, n.main) + std::max(s.stage_words, n.stage) +
+                  std::max(s.dig_words, n.dig)) *
+         4;
+}
+
+// Frees an idle slot's scratch (its last batch has completed).
+void slot_release(SrvSlot& s) {
+  hipStreamSynchronize(s.st);
+  for (uint32_t** p : {&s.ws, &s.stage, &s.dig})
+    if (*p) hipFree(*p), *p = nullptr;
+  s.ws_words = s.stage_words = s.dig_words = 0;
+}
+
+}  // namespace
+
+struct fhe_server {
+  fhe_ctx* ctx = nullptr;
+  size_t budget = 0;
+  int max_batch = 1;
+  std::vector<SrvSlot> slots;
+  std::map<SrvCell, std::deque<SrvReq>> queues;  // arrived requests per cell, in arrival order
+  size_t npending = 0;
+  std::priority_queue<SrvReq, std::vector<SrvReq>, SrvLater> future;  // scheduled arrivals
+  std::vector<fhe_done> done;
+  std::mutex m;
+  std::condition_variable cv;
+  std::thread th;
+  bool stop = false;
+  uint64_t next_ticket = 1, submitted = 0, finished = 0;
+};
+
+namespace {
+
+// Launches `reqs` (one cell) on a slot.  Called by the scheduler thread (the only
+// thread that touches slot buffers) without the server lock.
+int srv_launch(fhe_server* sv, SrvSlot& sl, std::vector<SrvReq>& reqs, const SrvNeed& need) {
+  fhe_ctx* c = sv->ctx;
+  const int cnum = (int)reqs.size();
+  const fhe_job& j0 = reqs[0].job;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (c->sticky != FHE_OK) return c->sticky;
+  hipSetDevice(c->device);
+  int rc = evk_prepare_locked(j0.evk, j0.logq, sl.st);
+  if (rc != FHE_OK) return rc;
+  hipError_t e = grow(&sl.ws, &sl.ws_words, need.main, sl.st);
+  if (e == hipSuccess) e = grow(&sl.stage, &sl.stage_words, need.stage, sl.st);
+  if (e == hipSuccess) e = grow(&sl.dig, &sl.dig_words, need.dig, sl.st);
+  if (e != hipSuccess) return set_sticky(c, e);
+  // the previous batch of this slot has completed, so its staging may be rewritten
+  for (int m = 0; m < cnum; ++m) {
+    const fhe_job& j = reqs[m].job;
+    sl.hptr[m] = j.x0;
+    sl.hptr[cnum + m] = j.x1;
+    sl.hptr[2 * cnum + m] = j.y0;
+    sl.hptr[3 * cnum + m] = j.y1;
+    sl.hptr[4 * cnum + m] = j.out0;
+    sl.hptr[5 * cnum + m] = j.out1;
+  }
+  e = hipMemcpyAsync(sl.dptr, sl.hptr, 6 * (size_t)cnum * sizeof(void*), hipMemcpyHostToDevice, sl.st);
+  if (e != hipSuccess) return set_sticky(c, e);
+  PipeIO io;
+  io.ins = sl.dptr;
+  io.outs = sl.dptr + 4LL * cnum;
+  rc = pipeline(c, j0.evk, j0.evk->logN, j0.logq, j0.bits, io, cnum, sl.st, sl.ws, sl.stage, sl.dig, Tuning());
+  if (rc != FHE_OK) return rc;
+  return set_sticky(c, hipEventRecord(sl.done, sl.st));
+}
+
+void srv_finish(fhe_server* sv, const std::vector<SrvReq>& reqs, int status, uint64_t t0, uint64_t t1) {
+  for (const SrvReq& r : reqs) {
+    fhe_done d;
+    d.ticket = r.ticket;
+    d.status = status;
+    d.batch = (int)reqs.size();
+    d.t_arrive = r.t_arrive;
+    d.t_start = t0;
+    d.t_done = t1;
+    sv->done.push_back(d);
+  }
+  sv->finished += reqs.size();
+}
+
+// Picks an idle slot for a batch needing `need` and makes room for it within the
+// budget, freeing other idle slots' scratch (largest first) only when it must.
+// Returns null when the batch has to wait for running batches to complete.
+SrvSlot* srv_place(fhe_server* sv, const SrvNeed& need) {
+  SrvSlot* best = nullptr;
+  size_t best_grow = SIZE_MAX, best_held = SIZE_MAX, held = 0;
+  for (SrvSlot& sl : sv->slots) {
+    held += slot_held(sl);
+    if (sl.busy) continue;
+    const size_t g = slot_after(sl, need) - slot_held(sl);
+    if (g < best_grow || (g == best_grow && slot_held(sl) < best_held)) {
+      best = &sl;
+      best_grow = g;
+      best_held = slot_held(sl);
+    }
+  }
+  if (!best) return nullptr;
+  size_t after = held + best_grow;
+  while (after > sv->budget) {
+    SrvSlot* v = nullptr;
+    for (SrvSlot& sl : sv->slots)
+      if (!sl.busy && &sl != best && slot_held(sl) > 0 && (!v || slot_held(sl) > slot_held(*v))) v = &sl;
+    if (!v) break;
+    after -= slot_held(*v);
+    slot_release(*v);
+  }
+  if (after > sv->budget && after - slot_after(*best, need) + need_bytes(need) <= sv->budget) {
+    // the chosen slot's own buffers are oversized for this batch: refit them exactly
+    after = after - slot_after(*best, need) + need_bytes(need);
+    slot_release(*best);
+  }
+  return after <= sv->budget ? best : nullptr;
+}
+
+void srv_loop(fhe_server* sv) {
+  hipSetDevice(sv->ctx->device);
+  std::unique_lock<std::mutex> lk(sv->m);
+  for (;;) {
+    bool progress = false;
+    // completions
+    for (SrvSlot& sl : sv->slots) {
+      if (sl.busy && hipEventQuery(sl.done) == hipSuccess) {
+        srv_finish(sv, sl.reqs, FHE_OK, sl.t_start, now_ns());
+        sl.busy = false;
+        sl.reqs.clear();
+        progress = true;
+      }
+    }
+    // scheduled arrivals that are due join the queue in arrival order
+    uint64_t now = now_ns();
+    while (!sv->future.empty() && sv->future.top().t_arrive <= now) {
+      sv->queues[cell_of(sv->future.top().job)].push_back(sv->future.top());
+      ++sv->npending;
+      sv->future.pop();
+    }
+    const uint64_t next_arrival = sv->future.empty() ? UINT64_MAX : sv->future.top().t_arrive;
+    // admissions: the oldest request first, batched with the requests of its cell
+    while (sv->npending > 0) {
+      std::deque<SrvReq>* q = nullptr;
+      for (auto& kv : sv->queues) {
+        if (kv.second.empty()) continue;
+        const SrvReq& f = kv.second.front();
+        if (!q || f.t_arrive < q->front().t_arrive ||
+            (f.t_arrive == q->front().t_arrive && f.ticket < q->front().ticket))
+          q = &kv.second;
+      }
+      const fhe_job head = q->front().job;
+      int take = std::min((int)q->size(), sv->max_batch);
+      SrvNeed need = batch_need(sv->ctx, head, take);
+      while (take > 1 && need_bytes(need) > sv->budget) need = batch_need(sv->ctx, head, --take);
+      if (need_bytes(need) > sv->budget) {  // cannot run even alone
+        std::vector<SrvReq> one{q->front()};
+        q->pop_front();
+        --sv->npending;
+        const uint64_t t = now_ns();
+        srv_finish(sv, one, FHE_E_NOMEM, t, t);
+        progress = true;
+        continue;
+      }
+      SrvSlot* sl = srv_place(sv, need);
+      if (!sl) break;  // wait for a slot or for memory
+      std::vector<SrvReq> batch(q->begin(), q->begin() + take);
+      q->erase(q->begin(), q->begin() + take);
+      sv->npending -= take;
+      sl->busy = true;
+      sl->t_start = now_ns();
+      lk.unlock();
+      const int rc = srv_launch(sv, *sl, batch, need);
+      lk.lock();
+      if (rc != FHE_OK) {
+        srv_finish(sv, batch, rc, sl->t_start, now_ns());
+        sl->busy = false;
+      } else {
+        sl->reqs = std::move(batch);
+      }
+      progress = true;
+      now = now_ns();
+    }
+    bool busy = false;
+    for (SrvSlot& sl : sv->slots) busy = busy || sl.busy;
+    if (sv->stop && sv->npending == 0 && sv->future.empty() && !busy) break;
+    if (progress) {
+      sv->cv.notify_all();
+    } else {
+      // sleep until a completion may be due, the next scheduled arrival, or a submit
+      uint64_t wait = busy ? 20000 : 500000;
+      if (next_arrival != UINT64_MAX) wait = std::min(wait, next_arrival > now ? next_arrival - now : 0);
+      if (wait > 0) sv->cv.wait_for(lk, std::chrono::nanoseconds(wait));
+    }
+  }
+  sv->cv.notify_all();
+}
+
 bool valid_t(int scheme, uint32_t t) {
   if (scheme == FHE_CKKS) return true;
   return scheme == FHE_BGV && t >= 3 && (t & 1) && t < (1u << 24);
@@ -1356,6 +1630,96 @@ void fhe_batch_destroy(fhe_plan* pl) {
     hipDeviceSynchronize();
   }
   plan_free(pl);
+}
+
+uint64_t fhe_clock_ns(void) { return now_ns(); }
+
+int fhe_server_create(fhe_ctx* c, size_t hbm_budget, int nstreams, int max_batch, fhe_server** out) {
+  if (!c || !out || nstreams < 1 || nstreams > 16 || max_batch < 1 || max_batch > 256) return FHE_E_INVAL;
+  *out = nullptr;
+  hipSetDevice(c->device);
+  fhe_server* sv = new (std::nothrow) fhe_server();
+  if (!sv) return FHE_E_NOMEM;
+  sv->ctx = c;
+  sv->budget = hbm_budget;
+  sv->max_batch = max_batch;
+  sv->slots.resize(nstreams);
+  hipError_t e = hipSuccess;
+  for (SrvSlot& sl : sv->slots) {
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&sl.hptr, 6 * (size_t)max_batch * sizeof(void*), 0);
+    if (e == hipSuccess) e = hipMalloc((void**)&sl.dptr, 6 * (size_t)max_batch * sizeof(void*));
+  }
+  if (e != hipSuccess) {
+    sv->stop = true;
+    fhe_server_destroy(sv);
+    return status_of(e);
+  }
+  sv->th = std::thread(srv_loop, sv);
+  *out = sv;
+  return FHE_OK;
+}
+
+int fhe_server_submit(fhe_server* sv, const fhe_job* j, uint64_t arrival_ns, uint64_t* ticket) {
+  if (!sv || !j || !ticket) return FHE_E_INVAL;
+  if (!j->evk || !j->x0 || !j->x1 || !j->y0 || !j->y1 || !j->out0 || !j->out1) return FHE_E_INVAL;
+  if (j->evk->ctx != sv->ctx) return FHE_E_STATE;
+  if (j->logq < 1 || j->logq > j->evk->logQ) return FHE_E_RANGE;
+  if (j->bits < 0 || j->bits >= j->logq) return FHE_E_INVAL;
+  std::lock_guard<std::mutex> lk(sv->m);
+  if (sv->stop) return FHE_E_STATE;
+  SrvReq r;
+  r.ticket = sv->next_ticket++;
+  r.t_arrive = arrival_ns ? arrival_ns : now_ns();
+  r.job = *j;
+  if (r.t_arrive > now_ns()) {
+    sv->future.push(r);
+  } else {
+    sv->queues[cell_of(r.job)].push_back(r);
+    ++sv->npending;
+  }
+  ++sv->submitted;
+  *ticket = r.ticket;
+  sv->cv.notify_all();
+  return FHE_OK;
+}
+
+int fhe_server_poll(fhe_server* sv, fhe_done* out, int max, int* n) {
+  if (!sv || !n || max < 0 || (max > 0 && !out)) return FHE_E_INVAL;
+  std::lock_guard<std::mutex> lk(sv->m);
+  const int k = std::min(max, (int)sv->done.size());
+  for (int i = 0; i < k; ++i) out[i] = sv->done[i];
+  sv->done.erase(sv->done.begin(), sv->done.begin() + k);
+  *n = k;
+  return FHE_OK;
+}
+
+int fhe_server_drain(fhe_server* sv) {
+  if (!sv) return FHE_E_INVAL;
+  std::unique_lock<std::mutex> lk(sv->m);
+  sv->cv.wait(lk, [&] { return sv->finished == sv->submitted; });
+  return FHE_OK;
+}
+
+void fhe_server_destroy(fhe_server* sv) {
+  if (!sv) return;
+  {
+    std::lock_guard<std::mutex> lk(sv->m);
+    sv->stop = true;
+    sv->cv.notify_all();
+  }
+  if (sv->th.joinable()) sv->th.join();
+  hipSetDevice(sv->ctx->device);
+  for (SrvSlot& sl : sv->slots) {
+    if (sl.st) hipStreamSynchronize(sl.st);
+    for (void* p : {(void*)sl.ws, (void*)sl.stage, (void*)sl.dig, (void*)sl.dptr})
+      if (p) hipFree(p);
+    if (sl.hptr) hipHostFree(sl.hptr);
+    if (sl.done) hipEventDestroy(sl.done);
+    if (sl.st) hipStreamDestroy(sl.st);
+  }
+  delete sv;
 }
 
 }  // extern "C"
