@@ -315,14 +315,14 @@ def main():
         polys = fhe.to_device(synth.uniform_limbs(rm, LOGQ, N, count=64)).reshape(-1)
         res = torch.empty(64 * Kt * N, dtype=torch.int32, device=dev)
         ctx.lift(LOGN, L, Kt, polys, res, count=64)
-        ctx.ntt(LOGN, Kt, res, count=64)
-        ctx.ntt(LOGN, Kt, res, count=64, inverse=True)
+        ctx.ntt(LOGN, Kt, res, count=64, bitrev=True)
+        ctx.ntt(LOGN, Kt, res, count=64, inverse=True, bitrev=True)
         torch.cuda.synchronize()
         for inv in (False, True):
             reps = 3
             ev0.record(stream)
             for _ in range(reps):
-                ctx.ntt(LOGN, Kt, res, count=64, inverse=inv)
+                ctx.ntt(LOGN, Kt, res, count=64, inverse=inv, bitrev=True)
             ev1.record(stream)
             torch.cuda.synchronize()
             extras["ntt_inv_per_s" if inv else "ntt_fwd_per_s"] = reps * 64 * Kt / (ev0.elapsed_time(ev1) / 1e3)

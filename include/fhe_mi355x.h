@@ -126,14 +126,21 @@ int fhe_primes_needed(const fhe_ctx* ctx, int logN, int bits_a, int bits_b, int 
 int fhe_lift(fhe_ctx* ctx, int logN, int L, int nprimes, const uint32_t* limbs,
              uint32_t* res, int count, void* stream);
 
-/* Standalone negacyclic NTT over primes 0..nprimes-1, in place on
- * data = uint32[count][nprimes][N] (device), values in [0, q_p).
- * inverse = 0: Eq. negacyclic_ntt, output in bit-reversed order: position r holds
- *              abar_i with r = bitrev_(logN)(i).
- * inverse = 1: Eq. negacyclic_intt, input in that bit-reversed order, natural-order
- *              output.
- * Errors: FHE_E_INVAL, FHE_E_RANGE (logN outside [10, 16], too many primes). */
-int fhe_ntt(fhe_ctx* ctx, int logN, int nprimes, int inverse, uint32_t* data, int count,
+/* Standalone negacyclic NTT (Section 2.3, Eq. negacyclic_ntt / negacyclic_intt, with
+ * the twist by powers of psi merged into the butterflies as Section 5.1 describes)
+ * over primes prime0 .. prime0+nprimes-1 of the context's table, in place on
+ * data = uint32[count][nprimes][N] (device), values in [0, q_p).  For N < 2^16 the
+ * root is psi_N = psi^(2^16 / N), psi from fhe_prime_info.
+ * flags = 0:                    forward, abar_i at position i (natural order).
+ * flags = FHE_NTT_BITREV:       forward, abar_i at position bitrev_(logN)(i), the
+ *                               order the transform produces (no permutation pass).
+ * flags = FHE_NTT_INVERSE:      inverse of the natural-order forward.
+ * flags = INVERSE | BITREV:     inverse taking the bit-reversed order.
+ * Errors: FHE_E_INVAL (flags, null, negative sizes), FHE_E_RANGE (logN outside
+ * [10, 16], prime0 + nprimes beyond the table). */
+#define FHE_NTT_INVERSE 1
+#define FHE_NTT_BITREV 2
+int fhe_ntt(fhe_ctx* ctx, int logN, int prime0, int nprimes, int flags, uint32_t* data, int count,
             void* stream);
 
 /* Ring multiply (Section 2.3, Eq. schoolbook then Eq. reduction, mod Q = 2^logq):
@@ -229,6 +236,52 @@ int fhe_batch_info(const fhe_plan* plan, int* cells, int* kernels, int* graphed)
 
 /* Release a plan (waits for the device).  NULL is a no-op. */
 void fhe_batch_destroy(fhe_plan* plan);
+
+/* ---------------------------------------------------------------- test helpers
+ * Encoding, encryption and decryption (Section 6.2 operation list; the readings of
+ * the scheme are those of the CPU oracle).  All randomness is passed in, so the
+ * results can be compared bit for bit with the oracle.  Keys are not generated here.
+ * Sign conventions: "[x]_m" is the representative in [0, m); the centered one lies
+ * in (-m/2, m/2]. */
+
+/* CKKS encoding with sparse packing (host arrays; no device needed).
+ * z_j = re[j] + i im[j], j < n = 2^logslots <= N/2.  With zeta = exp(2 pi i / 4n),
+ * r_j = 5^j mod 4n and gap = N / 2n:
+ *   u_k = (1/n) Re(sum_j z_j zeta^(-r_j k)),   k < 2n,
+ *   m_(k gap) = floor(2^logp u_k + 1/2), other coefficients 0,
+ * written as [m]_(2^logq) into m = uint32[L][N], L = ceil(logq / 32).  Computed in
+ * double precision through a length-2n FFT, so a coefficient can differ by one from
+ * an exact evaluation where 2^logp u_k + 1/2 lies within rounding of an integer.
+ * Errors: FHE_E_INVAL (null), FHE_E_RANGE (logN outside [10, 16], logslots outside
+ * [0, logN-1], logp outside [1, 62], |2^logp u_k| >= 2^62, logq outside [1, 4096]). */
+int fhe_ckks_encode(int logN, int logslots, int logp, int logq, const double* re, const double* im,
+                    uint32_t* m);
+
+/* CKKS decoding (host arrays): mu = centered representative of the phase
+ * uint32[L][N] (mod 2^logq), z_j = 2^-logp sum_(k<2n) mu_(k gap) zeta^(r_j k),
+ * in double precision.  Errors as for fhe_ckks_encode. */
+int fhe_ckks_decode(int logN, int logslots, int logp, int logq, const uint32_t* phase, double* re,
+                    double* im);
+
+/* Public-key encryption at level logq (device arrays, on `stream`):
+ *   c0 = [v pk_b + m + e0']_(Q_l),  c1 = [v pk_a + e1']_(Q_l),  Q_l = 2^logq,
+ * e' = e (CKKS) or t e (BGV).  pk_b, pk_a: uint32[L'][N] with L' >= L, a public key
+ * at a modulus 2^logQ >= Q_l (its low L limb rows, top row masked, are the key
+ * mod Q_l).  m: uint32[L][N] in [0, Q_l).  v: int8[N] (ternary), e0, e1: int32[N].
+ * c0, c1: uint32[L][N], caller-owned.  t is ignored for CKKS; BGV needs odd t in
+ * [3, 2^24).  Errors: FHE_E_INVAL, FHE_E_RANGE (logN, logq beyond the context). */
+int fhe_encrypt(fhe_ctx* ctx, int scheme, uint32_t t, int logN, int logq, const uint32_t* pk_b,
+                const uint32_t* pk_a, const uint32_t* m, const int8_t* v, const int32_t* e0,
+                const int32_t* e1, uint32_t* c0, uint32_t* c1, void* stream);
+
+/* Decryption (device arrays): the phase [c0 + c1 s]_(Q_l), s: int8[N] the ternary
+ * secret.  CKKS: out = the phase, uint32[L][N] (decode it with fhe_ckks_decode).
+ * BGV: out = uint32[N], m_j = gamma^-1 [[phase_j]] mod t (centered phase, then mod t),
+ * where gamma is the ciphertext's factor (1 after encryption; a multiplication
+ * multiplies the factors, a rescale by k bits multiplies by 2^-k mod t).
+ * Errors: FHE_E_INVAL (gamma not invertible mod t, bad t), FHE_E_RANGE. */
+int fhe_decrypt(fhe_ctx* ctx, int scheme, uint32_t t, uint32_t gamma, int logN, int logq,
+                const uint32_t* c0, const uint32_t* c1, const int8_t* s, uint32_t* out, void* stream);
 
 /* ---------------------------------------------------------------- serving
  * A request loop for HE-mult requests (one fhe_job each) that arrive over time.

@@ -41,7 +41,7 @@ EXPORTS = {
     "fhe_prime_info": (_I, [_P, _I, ctypes.POINTER(_U), ctypes.POINTER(_U)]),
     "fhe_primes_needed": (_I, [_P, _I, _I, _I, _I, ctypes.POINTER(_I)]),
     "fhe_lift": (_I, [_P, _I, _I, _I, _P, _P, _I, _P]),
-    "fhe_ntt": (_I, [_P, _I, _I, _I, _P, _I, _P]),
+    "fhe_ntt": (_I, [_P, _I, _I, _I, _I, _P, _I, _P]),
     "fhe_ring_mul": (_I, [_P, _I, _I, _P, _P, _P, _I, _P]),
     "fhe_evk_create": (_I, [_P, _I, _U, _I, _I, _I, _P, _P, ctypes.POINTER(_P)]),
     "fhe_evk_prepare": (_I, [_P, _I, _P]),
@@ -53,6 +53,10 @@ EXPORTS = {
     "fhe_batch_run": (_I, [_P, _P]),
     "fhe_batch_info": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "fhe_batch_destroy": (None, [_P]),
+    "fhe_ckks_encode": (_I, [_I, _I, _I, _I, _P, _P, _P]),
+    "fhe_ckks_decode": (_I, [_I, _I, _I, _I, _P, _P, _P]),
+    "fhe_encrypt": (_I, [_P, _I, _U, _I, _I, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "fhe_decrypt": (_I, [_P, _I, _U, _U, _I, _I, _P, _P, _P, _P, _P]),
     "fhe_clock_ns": (ctypes.c_uint64, []),
     "fhe_server_create": (_I, [_P, ctypes.c_size_t, _I, _I, ctypes.POINTER(_P)]),
     "fhe_server_submit": (_I, [_P, _P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]),
@@ -63,6 +67,8 @@ EXPORTS = {
 
 PLAN_GRAPH = 1
 PLAN_AUTOTUNE = 2
+NTT_INVERSE = 1
+NTT_BITREV = 2
 
 
 class Job(ctypes.Structure):
@@ -208,10 +214,40 @@ class Context:
         _check("fhe_lift", load_library().fhe_lift(self._h, logN, L, nprimes, _ptr(limbs), _ptr(res), count,
                                                    _stream(stream)))
 
-    def ntt(self, logN: int, nprimes: int, data, count: int = 1, inverse: bool = False, stream=None):
+    def ntt(self, logN: int, nprimes: int, data, count: int = 1, inverse: bool = False, bitrev: bool = False,
+            prime0: int = 0, stream=None):
+        """In-place negacyclic NTT of uint32[count][nprimes][N] over primes prime0.. ;
+        natural order unless bitrev (the transform's own order, no permutation)."""
         _need(data, count * nprimes << logN, "data")
-        _check("fhe_ntt", load_library().fhe_ntt(self._h, logN, nprimes, int(inverse), _ptr(data), count,
+        flags = (NTT_INVERSE if inverse else 0) | (NTT_BITREV if bitrev else 0)
+        _check("fhe_ntt", load_library().fhe_ntt(self._h, logN, prime0, nprimes, flags, _ptr(data), count,
                                                  _stream(stream)))
+
+    def encrypt(self, scheme: int, t: int, logN: int, logq: int, pk_b, pk_a, m, v, e0, e1, c0, c1, stream=None):
+        """c0 = [v pk_b + m + e0']_(2^logq), c1 = [v pk_a + e1']; v int8, e0/e1 int32 device tensors."""
+        import torch
+        N = 1 << logN
+        L = nlimbs(logq)
+        for t_, n in ((pk_b, "pk_b"), (pk_a, "pk_a"), (m, "m"), (c0, "c0"), (c1, "c1")):
+            _need(t_, L * N, n)
+        _small(v, torch.int8, N, "v")
+        _small(e0, torch.int32, N, "e0")
+        _small(e1, torch.int32, N, "e1")
+        _check("fhe_encrypt", load_library().fhe_encrypt(
+            self._h, scheme, t, logN, logq, _ptr(pk_b), _ptr(pk_a), _ptr(m), v.data_ptr(), e0.data_ptr(),
+            e1.data_ptr(), _ptr(c0), _ptr(c1), _stream(stream)))
+
+    def decrypt(self, scheme: int, t: int, gamma: int, logN: int, logq: int, c0, c1, s, out, stream=None):
+        """CKKS: out = phase [c0 + c1 s] (uint32[L][N]); BGV: out = message uint32[N]."""
+        import torch
+        N = 1 << logN
+        L = nlimbs(logq)
+        _need(c0, L * N, "c0")
+        _need(c1, L * N, "c1")
+        _need(out, L * N if scheme == CKKS else N, "out")
+        _small(s, torch.int8, N, "s")
+        _check("fhe_decrypt", load_library().fhe_decrypt(
+            self._h, scheme, t, gamma, logN, logq, _ptr(c0), _ptr(c1), s.data_ptr(), _ptr(out), _stream(stream)))
 
     def ring_mul(self, logN: int, logq: int, a, b, out, cnum: int = 1, stream=None):
         w = cnum * nlimbs(logq) << logN
@@ -380,6 +416,44 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def _small(t, dtype, n: int, name: str):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name}: contiguous CUDA {dtype} tensor expected")
+    _need(t, n, name)
+
+
+def ckks_encode(z, logN: int, logp: int, logq: int):
+    """Host CKKS encoding of complex slots z (length n = 2^logslots <= N/2) into
+    [m]_(2^logq) limbs uint32[L][N] (numpy)."""
+    import numpy as np
+    z = np.ascontiguousarray(z, dtype=np.complex128)
+    n = z.shape[0]
+    logs = n.bit_length() - 1
+    if n < 1 or n != 1 << logs:
+        raise ValueError("slot count must be a power of two")
+    re = np.ascontiguousarray(z.real)
+    im = np.ascontiguousarray(z.imag)
+    m = np.zeros((nlimbs(logq), 1 << logN), dtype=np.uint32)
+    _check("fhe_ckks_encode", load_library().fhe_ckks_encode(
+        logN, logs, logp, logq, re.ctypes.data_as(_P), im.ctypes.data_as(_P), m.ctypes.data_as(_P)))
+    return m
+
+
+def ckks_decode(phase, logN: int, logslots: int, logp: int, logq: int):
+    """Host CKKS decoding of a phase uint32[L][N] (numpy) into n = 2^logslots complex slots."""
+    import numpy as np
+    ph = np.ascontiguousarray(phase, dtype=np.uint32)
+    if ph.shape != (nlimbs(logq), 1 << logN):
+        raise ValueError("phase must be uint32[L][N]")
+    n = 1 << logslots
+    re = np.zeros(n)
+    im = np.zeros(n)
+    _check("fhe_ckks_decode", load_library().fhe_ckks_decode(
+        logN, logslots, logp, logq, ph.ctypes.data_as(_P), re.ctypes.data_as(_P), im.ctypes.data_as(_P)))
+    return re + 1j * im
 
 
 def to_device(arr, device: int = 0):

@@ -14,6 +14,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <numeric>
 #include <queue>
 #include <vector>
 
@@ -46,8 +47,19 @@ uint64_t powmod(uint64_t b, uint64_t e, uint64_t m) {
   return r;
 }
 
-uint64_t invmod(uint64_t a, uint64_t m) {  // m prime
-  return powmod(a % m, m - 2, m);
+// a^-1 mod m for gcd(a, m) = 1 (extended Euclid; m need not be prime).
+uint64_t invmod(uint64_t a, uint64_t m) {
+  long long r0 = (long long)m, r1 = (long long)(a % m), s0 = 0, s1 = 1;
+  while (r1 != 0) {
+    const long long qt = r0 / r1;
+    long long t = r0 - qt * r1;
+    r0 = r1;
+    r1 = t;
+    t = s0 - qt * s1;
+    s0 = s1;
+    s1 = t;
+  }
+  return (uint64_t)(s0 < 0 ? s0 + (long long)m : s0);
 }
 
 bool is_prime32(uint32_t n) {
@@ -1014,6 +1026,43 @@ void srv_loop(fhe_server* sv) {
   sv->cv.notify_all();
 }
 
+// c = a b in Z_(2^logq)[X]/(X^N + 1) for cnum pairs (lift, NTT, pointwise, iNTT,
+// Garner); the caller holds the context lock and has checked the arguments.
+int ring_mul_locked(fhe_ctx* c, int logN, int logq, const uint32_t* a, const uint32_t* b, uint32_t* out, int cnum,
+                    void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const int N = 1 << logN;
+  const int L = (logq + 31) / 32;
+  const int eb = 2 * logq + logN;
+  const int K = primes_for_e(c, eb);
+  if (K < 0) return FHE_E_RANGE;
+  hipError_t e = hipSuccess;
+  const uint32_t* ow = offsets(c, eb, &e);
+  if (!ow) return set_sticky(c, e);
+  const long long KN = (long long)K * N;
+  uint32_t* R = (uint32_t*)scratch(c, stream, 0, (size_t)2 * cnum * KN * 4, &e);
+  if (!R) return set_sticky(c, e);
+  uint32_t* Ra = R;
+  uint32_t* Rb = R + (long long)cnum * KN;
+  e = launch_lift(lift_args(c, a, Ra, (long long)L * N, KN, N, L, K), cnum, st);
+  if (e == hipSuccess) e = launch_lift(lift_args(c, b, Rb, (long long)L * N, KN, N, L, K), cnum, st);
+  if (e == hipSuccess) e = launch_ntt(ntt_args(c, R, logN, K, K, KN, false, nullptr), 2 * cnum * K, false, st);
+  if (e == hipSuccess) {
+    PointwiseArgs pa{};
+    pa.a = Ra;
+    pa.b = Rb;
+    pa.group_stride = KN;
+    pa.N = N;
+    pa.K = K;
+    pa.pc = c->pc;
+    e = launch_ring_pointwise(pa, cnum, st);
+  }
+  if (e == hipSuccess) e = launch_ntt(ntt_args(c, Ra, logN, K, K, KN, true, c->gscale[logN]), cnum * K, true, st);
+  if (e == hipSuccess)
+    e = run_garner(c, stream, garner_args(c, Ra, 1, KN, 0, out, (long long)L * N, N, K, logq, ow), cnum);
+  return set_sticky(c, e);
+}
+
 bool valid_t(int scheme, uint32_t t) {
   if (scheme == FHE_CKKS) return true;
   return scheme == FHE_BGV && t >= 3 && (t & 1) && t < (1u << 24);
@@ -1322,17 +1371,26 @@ int fhe_lift(fhe_ctx* c, int logN, int L, int nprimes, const uint32_t* limbs, ui
   return set_sticky(c, e);
 }
 
-int fhe_ntt(fhe_ctx* c, int logN, int nprimes, int inverse, uint32_t* data, int count, void* stream) {
-  if (!c || !data || count < 0 || nprimes < 1 || (inverse != 0 && inverse != 1)) return FHE_E_INVAL;
-  if (check_logN(logN) != FHE_OK || nprimes > c->K) return FHE_E_RANGE;
+int fhe_ntt(fhe_ctx* c, int logN, int prime0, int nprimes, int flags, uint32_t* data, int count, void* stream) {
+  if (!c || !data || count < 0 || nprimes < 1 || prime0 < 0 || (flags & ~(FHE_NTT_INVERSE | FHE_NTT_BITREV)))
+    return FHE_E_INVAL;
+  if (check_logN(logN) != FHE_OK || prime0 + nprimes > c->K) return FHE_E_RANGE;
+  if (count == 0) return FHE_OK;
   std::lock_guard<std::recursive_mutex> g(c->mu);
   if (c->sticky != FHE_OK) return c->sticky;
   hipSetDevice(c->device);
   RecGuard rg(c);
+  hipStream_t st = (hipStream_t)stream;
   const long long N = 1LL << logN;
-  hipError_t e = launch_ntt(ntt_args(c, data, logN, nprimes, nprimes, (long long)nprimes * N, inverse != 0,
-                                     c->nscale[logN]),
-                            count * nprimes, inverse != 0, (hipStream_t)stream);
+  const bool inverse = (flags & FHE_NTT_INVERSE) != 0, natural = !(flags & FHE_NTT_BITREV);
+  const long long rows = (long long)count * nprimes;
+  NttArgs a = ntt_args(c, data, logN, nprimes, nprimes, (long long)nprimes * N, inverse, c->nscale[logN] + prime0);
+  a.tw += (long long)prime0 * kNMax;
+  a.pc += prime0;
+  hipError_t e = hipSuccess;
+  if (inverse && natural) e = launch_bitrev(data, logN, rows, st);
+  if (e == hipSuccess) e = launch_ntt(a, (int)rows, inverse, st);
+  if (e == hipSuccess && !inverse && natural) e = launch_bitrev(data, logN, rows, st);
   return set_sticky(c, e);
 }
 
@@ -1345,36 +1403,67 @@ int fhe_ring_mul(fhe_ctx* c, int logN, int logq, const uint32_t* a, const uint32
   if (c->sticky != FHE_OK) return c->sticky;
   hipSetDevice(c->device);
   RecGuard rg(c);
+  return ring_mul_locked(c, logN, logq, a, b, out, cnum, stream);
+}
+
+int fhe_encrypt(fhe_ctx* c, int scheme, uint32_t t, int logN, int logq, const uint32_t* pk_b, const uint32_t* pk_a,
+                const uint32_t* m, const int8_t* v, const int32_t* e0, const int32_t* e1, uint32_t* c0, uint32_t* c1,
+                void* stream) {
+  if (!c || !pk_b || !pk_a || !m || !v || !e0 || !e1 || !c0 || !c1 || logq < 1) return FHE_E_INVAL;
+  if (!valid_t(scheme, t)) return FHE_E_INVAL;
+  if (check_logN(logN) != FHE_OK || logq > c->logQ_max + c->logP_max) return FHE_E_RANGE;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (c->sticky != FHE_OK) return c->sticky;
+  hipSetDevice(c->device);
+  RecGuard rg(c);
   hipStream_t st = (hipStream_t)stream;
-  const int N = 1 << logN;
-  const int L = (logq + 31) / 32;
-  const int eb = 2 * logq + logN;
-  const int K = primes_for_e(c, eb);
-  if (K < 0) return FHE_E_RANGE;
+  const int N = 1 << logN, L = (logq + 31) / 32;
+  const uint32_t top = (logq & 31) ? (1u << (logq & 31)) - 1u : 0xFFFFFFFFu;
+  const long long LN = (long long)L * N;
   hipError_t e = hipSuccess;
-  const uint32_t* ow = offsets(c, eb, &e);
-  if (!ow) return set_sticky(c, e);
-  const long long KN = (long long)K * N;
-  uint32_t* R = (uint32_t*)scratch(c, stream, 0, (size_t)2 * cnum * KN * 4, &e);
-  if (!R) return set_sticky(c, e);
-  uint32_t* Ra = R;
-  uint32_t* Rb = R + (long long)cnum * KN;
-  e = launch_lift(lift_args(c, a, Ra, (long long)L * N, KN, N, L, K), cnum, st);
-  if (e == hipSuccess) e = launch_lift(lift_args(c, b, Rb, (long long)L * N, KN, N, L, K), cnum, st);
-  if (e == hipSuccess) e = launch_ntt(ntt_args(c, R, logN, K, K, KN, false, nullptr), 2 * cnum * K, false, st);
-  if (e == hipSuccess) {
-    PointwiseArgs pa{};
-    pa.a = Ra;
-    pa.b = Rb;
-    pa.group_stride = KN;
-    pa.N = N;
-    pa.K = K;
-    pa.pc = c->pc;
-    e = launch_ring_pointwise(pa, cnum, st);
-  }
-  if (e == hipSuccess) e = launch_ntt(ntt_args(c, Ra, logN, K, K, KN, true, c->gscale[logN]), cnum * K, true, st);
+  // [v, v] against [pk_b, pk_a] mod Q_l as one pair of ring products
+  uint32_t* S = (uint32_t*)scratch(c, stream, 3, (size_t)6 * LN * 4, &e);
+  if (!S) return set_sticky(c, e);
+  uint32_t *A = S, *B = S + 2 * LN, *P = S + 4 * LN;
+  e = launch_small_to_limbs(v, A, N, L, top, st);
+  if (e == hipSuccess) e = launch_small_to_limbs(v, A + LN, N, L, top, st);
+  if (e == hipSuccess) e = launch_mask_rows(pk_b, B, N, L, top, st);
+  if (e == hipSuccess) e = launch_mask_rows(pk_a, B + LN, N, L, top, st);
+  if (e != hipSuccess) return set_sticky(c, e);
+  int rc = ring_mul_locked(c, logN, logq, A, B, P, 2, stream);
+  if (rc != FHE_OK) return rc;
+  const long long mult = scheme == FHE_BGV ? (long long)t : 1;
+  e = launch_add_small(P, m, e0, mult, c0, N, L, top, st);
+  if (e == hipSuccess) e = launch_add_small(P + LN, nullptr, e1, mult, c1, N, L, top, st);
+  return set_sticky(c, e);
+}
+
+int fhe_decrypt(fhe_ctx* c, int scheme, uint32_t t, uint32_t gamma, int logN, int logq, const uint32_t* c0,
+                const uint32_t* c1, const int8_t* s, uint32_t* out, void* stream) {
+  if (!c || !c0 || !c1 || !s || !out || logq < 1) return FHE_E_INVAL;
+  if (!valid_t(scheme, t)) return FHE_E_INVAL;
+  if (scheme == FHE_BGV && (gamma % t == 0 || std::gcd((uint64_t)gamma, (uint64_t)t) != 1)) return FHE_E_INVAL;
+  if (check_logN(logN) != FHE_OK || logq > c->logQ_max + c->logP_max) return FHE_E_RANGE;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (c->sticky != FHE_OK) return c->sticky;
+  hipSetDevice(c->device);
+  RecGuard rg(c);
+  hipStream_t st = (hipStream_t)stream;
+  const int N = 1 << logN, L = (logq + 31) / 32;
+  const uint32_t top = (logq & 31) ? (1u << (logq & 31)) - 1u : 0xFFFFFFFFu;
+  const long long LN = (long long)L * N;
+  hipError_t e = hipSuccess;
+  uint32_t* S = (uint32_t*)scratch(c, stream, 3, (size_t)3 * LN * 4, &e);
+  if (!S) return set_sticky(c, e);
+  uint32_t *SL = S, *P = S + LN, *PH = S + 2 * LN;
+  e = launch_small_to_limbs(s, SL, N, L, top, st);
+  if (e != hipSuccess) return set_sticky(c, e);
+  int rc = ring_mul_locked(c, logN, logq, c1, SL, P, 1, stream);
+  if (rc != FHE_OK) return rc;
+  if (scheme == FHE_CKKS) return set_sticky(c, launch_add_small(P, c0, nullptr, 0, out, N, L, top, st));
+  e = launch_add_small(P, c0, nullptr, 0, PH, N, L, top, st);
   if (e == hipSuccess)
-    e = run_garner(c, stream, garner_args(c, Ra, 1, KN, 0, out, (long long)L * N, N, K, logq, ow), cnum);
+    e = launch_bgv_decode(PH, out, N, L, logq, t, (uint32_t)powmod(2, logq, t), (uint32_t)invmod(gamma, t), st);
   return set_sticky(c, e);
 }
 

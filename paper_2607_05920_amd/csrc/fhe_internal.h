@@ -143,5 +143,12 @@ hipError_t launch_ring_pointwise(const PointwiseArgs& a, int cnum, hipStream_t s
 hipError_t launch_garner(const GarnerArgs& a, int npoly, hipStream_t s);
 hipError_t launch_compose(const ComposeArgs& a, int cnum, hipStream_t s);
 hipError_t launch_rescale(const RescaleArgs& a, int cnum, hipStream_t s);
+hipError_t launch_small_to_limbs(const int8_t* v, uint32_t* out, int N, int L, uint32_t topmask, hipStream_t s);
+hipError_t launch_mask_rows(const uint32_t* in, uint32_t* out, int N, int L, uint32_t topmask, hipStream_t s);
+hipError_t launch_add_small(const uint32_t* x, const uint32_t* y, const int32_t* e, long long mult, uint32_t* out,
+                            int N, int L, uint32_t topmask, hipStream_t s);
+hipError_t launch_bgv_decode(const uint32_t* ph, uint32_t* m, int N, int L, int logq, uint32_t t, uint32_t qmodt,
+                             uint32_t ginv, hipStream_t s);
+hipError_t launch_bitrev(uint32_t* data, int logN, long long rows, hipStream_t s);
 
 }  // namespace fhe

@@ -742,4 +742,124 @@ hipError_t launch_rescale(const RescaleArgs& a, int cnum, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ============================================================================ encryption helpers
+// Limb kernels for encryption and decryption (Section 6.2 encrypt / decrypt): the
+// ring products go through the exact ring multiply above; these do the rest.
+// One thread per (coefficient, limb) or per coefficient; limb-major layout keeps
+// every access of a wave on consecutive words of one limb row.
+
+// [v]_(2^logq) of small signed coefficients: limb 0 holds v mod 2^32, higher limbs
+// the sign extension, the top limb masked to logq bits.
+__global__ __launch_bounds__(256) void small_to_limbs_kernel(const int8_t* __restrict__ v, uint32_t* __restrict__ out,
+                                                             int N, int L, uint32_t topmask) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int l = blockIdx.y;
+  if (j >= N) return;
+  const int32_t x = v[j];
+  uint32_t w = l == 0 ? (uint32_t)x : (x < 0 ? 0xFFFFFFFFu : 0u);
+  if (l == L - 1) w &= topmask;
+  out[(long long)l * N + j] = w;
+}
+
+// The low L limb rows of a polynomial, the top one masked: [x]_(2^logq).
+__global__ __launch_bounds__(256) void mask_rows_kernel(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                        int N, int L, uint32_t topmask) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int l = blockIdx.y;
+  if (j >= N) return;
+  uint32_t w = in[(long long)l * N + j];
+  if (l == L - 1) w &= topmask;
+  out[(long long)l * N + j] = w;
+}
+
+// out = [x + y + mult * e]_(2^logq); y and e may be null.  The signed addend is
+// taken in two's complement over all limbs; one carry chain per coefficient.
+__global__ __launch_bounds__(256) void add_small_kernel(const uint32_t* __restrict__ x, const uint32_t* __restrict__ y,
+                                                        const int32_t* __restrict__ e, long long mult,
+                                                        uint32_t* __restrict__ out, int N, int L, uint32_t topmask) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= N) return;
+  const long long s = e ? mult * (long long)e[j] : 0;
+  const uint32_t ext = s < 0 ? 0xFFFFFFFFu : 0u;
+  uint64_t carry = 0;
+  for (int l = 0; l < L; ++l) {
+    const long long o = (long long)l * N + j;
+    const uint32_t a = l == 0 ? (uint32_t)s : (l == 1 ? (uint32_t)((unsigned long long)s >> 32) : ext);
+    const uint64_t t = (uint64_t)x[o] + (y ? y[o] : 0u) + a + carry;
+    uint32_t w = (uint32_t)t;
+    carry = t >> 32;
+    if (l == L - 1) w &= topmask;
+    out[o] = w;
+  }
+}
+
+// BGV decoding of a phase x in [0, 2^logq): m = gamma^-1 [[x]]_(2^logq) mod t, with
+// the centered representative (x > 2^(logq-1) maps to x - 2^logq).
+__global__ __launch_bounds__(256) void bgv_decode_kernel(const uint32_t* __restrict__ ph, uint32_t* __restrict__ m,
+                                                         int N, int L, int logq, uint32_t t, uint32_t qmodt,
+                                                         uint32_t ginv) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= N) return;
+  const int hb = (logq - 1) & 31, hl = (logq - 1) >> 5;
+  uint64_t r = 0;
+  bool top = false, low = false;
+  for (int l = L - 1; l >= 0; --l) {
+    const uint32_t w = ph[(long long)l * N + j];
+    r = ((r << 32) | w) % t;
+    if (l == hl) {
+      top = (w >> hb) & 1u;
+      low = low || (w & ((1u << hb) - 1u)) != 0;
+    } else if (l < hl) {
+      low = low || w != 0;
+    }
+  }
+  if (top && low) r = (r + t - qmodt) % t;
+  m[j] = (uint32_t)(r * ginv % t);
+}
+
+// In-place bit-reversal permutation of each length-2^logN row.  The thread at i
+// swaps with bitrev(i) when i < bitrev(i), so every pair has one owner.
+__global__ __launch_bounds__(256) void bitrev_kernel(uint32_t* __restrict__ data, int logN, long long total) {
+  for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (long long)gridDim.x * 256) {
+    const long long row = idx >> logN;
+    const uint32_t i = (uint32_t)(idx & ((1LL << logN) - 1));
+    const uint32_t r = __builtin_bitreverse32(i) >> (32 - logN);
+    if (i < r) {
+      uint32_t* d = data + (row << logN);
+      const uint32_t a = d[i], b = d[r];
+      d[i] = b;
+      d[r] = a;
+    }
+  }
+}
+
+hipError_t launch_small_to_limbs(const int8_t* v, uint32_t* out, int N, int L, uint32_t topmask, hipStream_t st) {
+  hipLaunchKernelGGL(small_to_limbs_kernel, dim3((N + 255) / 256, L), dim3(256), 0, st, v, out, N, L, topmask);
+  return hipGetLastError();
+}
+
+hipError_t launch_mask_rows(const uint32_t* in, uint32_t* out, int N, int L, uint32_t topmask, hipStream_t st) {
+  hipLaunchKernelGGL(mask_rows_kernel, dim3((N + 255) / 256, L), dim3(256), 0, st, in, out, N, L, topmask);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_small(const uint32_t* x, const uint32_t* y, const int32_t* e, long long mult, uint32_t* out,
+                            int N, int L, uint32_t topmask, hipStream_t st) {
+  hipLaunchKernelGGL(add_small_kernel, dim3((N + 255) / 256), dim3(256), 0, st, x, y, e, mult, out, N, L, topmask);
+  return hipGetLastError();
+}
+
+hipError_t launch_bgv_decode(const uint32_t* ph, uint32_t* m, int N, int L, int logq, uint32_t t, uint32_t qmodt,
+                             uint32_t ginv, hipStream_t st) {
+  hipLaunchKernelGGL(bgv_decode_kernel, dim3((N + 255) / 256), dim3(256), 0, st, ph, m, N, L, logq, t, qmodt, ginv);
+  return hipGetLastError();
+}
+
+hipError_t launch_bitrev(uint32_t* data, int logN, long long rows, hipStream_t st) {
+  const long long total = rows << logN;
+  const long long blocks = std::min<long long>((total + 255) / 256, 1LL << 16);
+  hipLaunchKernelGGL(bitrev_kernel, dim3((unsigned)blocks), dim3(256), 0, st, data, logN, total);
+  return hipGetLastError();
+}
+
 }  // namespace fhe

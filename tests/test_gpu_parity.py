@@ -80,7 +80,7 @@ def test_ntt_forward_inverse(ctx, logN):
     for p in range(nprimes):
         data[p] = rng.integers(0, ctx.prime_info(p)[0], N, dtype=np.uint64)
     t = dev(data)
-    ctx.ntt(logN, nprimes, t, count=1, inverse=False)
+    ctx.ntt(logN, nprimes, t, count=1, inverse=False, bitrev=True)
     fwd = host(t, (nprimes, N)).copy()
     perm = [_bitrev(i, logN) for i in range(N)]
     for p in primes:
@@ -91,7 +91,7 @@ def test_ntt_forward_inverse(ctx, logN):
         assert got == want
         if logN == 10 and p == 0:
             assert want == ontt.ntt_definition([int(v) for v in data[p]], q, psi)
-    ctx.ntt(logN, nprimes, t, count=1, inverse=True)
+    ctx.ntt(logN, nprimes, t, count=1, inverse=True, bitrev=True)
     assert np.array_equal(host(t, (nprimes, N)), data)
 
 
@@ -147,7 +147,8 @@ def _gpu_he_mult(ctx, evk_limbs, sch, t, logN, logq, logP, x, y, bits, fused=Tru
     return host(o0, (Lo, N)), host(o1, (Lo, N))
 
 
-@pytest.mark.parametrize("sch,t,bits", [(scheme.CKKS, 0, 40), (scheme.BGV, 65537, 32), (scheme.BGV, 65537, 20)])
+@pytest.mark.parametrize("sch,t,bits", [(scheme.CKKS, 0, 40), (scheme.BGV, 65537, 32), (scheme.BGV, 65537, 20),
+                                        (scheme.BGV, 1001, 20)])
 def test_he_mult_small_encrypted(ctx, sch, t, bits):
     """N = 2^10, logq = logP = 200, real keys and encryptions: bit-exact and decrypts."""
     say(f"he_mult small {sch} bits={bits}")
