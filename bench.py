@@ -25,6 +25,37 @@ sys.path.insert(0, ROOT)
 
 LOGN, LOGQ, LOGP, BITS = 16, 1555, 1555, 40
 PEAK_PRODUCTS = 256 * 64 * 2.4e9  # 32x32-bit products per second: 256 CUs x 64 lanes x 2.4 GHz
+PEAK_HBM = 8.0e12                  # bytes per second
+# The library reports each kernel's algorithmic work in the unit of its bound: word
+# products for the lift (integer-ALU bound), HBM bytes for every other kernel.
+ALU_KERNELS = {"lift"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_n16_q1555_cnum4.json")
+
+
+def kernels_source_hash() -> str:
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2607_05920_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter summary,
+    or None when there is none or the kernels changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernels_source_sha256") != kernels_source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return k.get("traffic_bytes_per_dispatch") if k else None
+
+
+def bound_of(kernel: str):
+    if kernel in ALU_KERNELS:
+        return "alu", PEAK_PRODUCTS, "T word-products/s (32x32-bit)", 1e12
+    return "hbm", PEAK_HBM, "GB/s", 1e9
 
 
 def log(msg):
@@ -277,17 +308,23 @@ def main():
 
     dom = max(prof, key=lambda k: prof[k]["ms"])
     d = prof[dom]
+    bound, peak, unit, scale = bound_of(dom)
     achieved = d["work"] / (d["ms"] / 1e3)
     total_kernel_ms = sum(v["ms"] for v in prof.values())
     roofline = {
-        "bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_PRODUCTS / 1e12,
-        "unit": "T word-products/s (32x32-bit)", "frac": achieved / PEAK_PRODUCTS, "traffic": None,
+        "bound": bound, "kernel": dom, "achieved": achieved / scale, "peak": peak / scale, "unit": unit,
+        "frac": achieved / peak, "traffic": measured_traffic(dom),
+        "work_per_launch": d["work"] / max(1, d["launches"]),
         "avg_launch_ms": d["ms"] / max(1, d["launches"]), "launches": d["launches"],
         "share_of_kernel_time": d["ms"] / total_kernel_ms if total_kernel_ms else None,
     }
-    kernels = {k: {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
-                   "T_products_per_s": (v["work"] / (v["ms"] / 1e3) / 1e12) if v["ms"] and v["work"] else None}
-               for k, v in prof.items()}
+    kernels = {}
+    for k, v in prof.items():
+        b, pk, u, sc = bound_of(k)
+        rate = v["work"] / (v["ms"] / 1e3) if v["ms"] and v["work"] else None
+        kernels[k] = {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
+                      "bound": b, "achieved": rate / sc if rate else None, "unit": u,
+                      "frac": rate / pk if rate else None}
 
     extras = {}
     if not args.no_extras:

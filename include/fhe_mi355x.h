@@ -12,8 +12,9 @@
  *
  * Ring products (Section 5.1, pipeline summary) lift limbs onto 30-bit
  * NTT-friendly primes q = 1 (mod 2^17), run negacyclic NTTs (Eq. negacyclic_ntt,
- * Eq. negacyclic_intt), multiply pointwise (Eq. ntt_mul), and rebuild limbs by
- * Garner's mixed-radix conversion (Eq. garner_mrc).  All arithmetic is exact.
+ * Eq. negacyclic_intt), multiply pointwise (Eq. ntt_mul), and rebuild limbs from
+ * the residues (the reconstruction of Section 5.1 and Eq. garner_mrc, computed as
+ * a direct CRT sum with its exact quotient).  All arithmetic is exact.
  *
  * Conventions where the paper is silent (the same readings as the CPU oracle):
  *   - Q_l = 2^logq and the special modulus P = 2^logP; "mod Q_l" keeps logq bits.
@@ -75,9 +76,10 @@ const char* fhe_error_detail(void);
 /* Create a context on HIP device `device` able to hold ciphertexts with
  * logq <= logQ_max and keys with logP <= logP_max.  Builds on the device the
  * tables of Section 5.2 (twiddles psi^j and their inverses, n^-1, the limb
- * weights 2^(32i) mod q_j, the Garner constants q_i^-1 mod q_j and
- * M_i = prod_(k<i) q_k), for as many primes as the largest relinearization
- * product at these limits needs.  *out receives the context (library-owned;
+ * weights 2^(32i) mod q_j, 1/q_j), for as many primes as the largest
+ * relinearization product at these limits needs; the reconstruction constants of
+ * each prime count (the CRT factors (M/q_i)^-1 mod q_i and the limbs of M/q_i) are
+ * built on first use.  *out receives the context (library-owned;
  * release with fhe_ctx_destroy).  Errors: FHE_E_INVAL (bad limits or null out),
  * FHE_E_RANGE (limits need more primes than the table holds), FHE_E_NOMEM,
  * FHE_E_DEVICE. */
@@ -94,12 +96,13 @@ int fhe_ctx_reset_error(fhe_ctx* ctx);
  * on the launch stream around every kernel the context launches (and clears the
  * totals); fhe_ctx_profile(ctx, 0) stops.  fhe_ctx_profile_read waits for the
  * recorded events and returns, for one kernel class, the summed event time (ms),
- * the summed algorithmic work (32x32-bit word products: Garner digits and limb
- * sums, lift limb products, one constant product per NTT butterfly, one per
- * pointwise product) and the number of launches (host outputs).  Kernel classes:
+ * the summed algorithmic work and the number of launches (host outputs).  The
+ * work is 32x32-bit word products for the lift (limb products), the NTT passes
+ * (one constant product per butterfly) and the pointwise products, and HBM bytes
+ * (residues read, limbs written) for the reconstruction.  Kernel classes:
  * 0 lift, 1 forward NTT column pass, 2 forward NTT row pass, 3 inverse NTT row
- * pass, 4 inverse NTT column pass, 5 pointwise, 6 Garner, 7 relinearization
- * compose, 8 rescale.  Errors: FHE_E_INVAL, FHE_E_STATE (not recording). */
+ * pass, 4 inverse NTT column pass, 5 pointwise, 6 reconstruction (CRT),
+ * 7 relinearization compose, 8 rescale.  Errors: FHE_E_INVAL, FHE_E_STATE (not recording). */
 int fhe_ctx_profile(fhe_ctx* ctx, int enable);
 int fhe_ctx_profile_read(fhe_ctx* ctx, int kernel, double* ms, double* work, long long* launches);
 
@@ -115,8 +118,10 @@ int fhe_prime_info(const fhe_ctx* ctx, int idx, uint32_t* q, uint32_t* psi);
 
 /* Number of primes K the library uses for the exact product of two polynomials
  * of degree < N with coefficients in [0, 2^bits_a) and [0, 2^bits_b), summed over
- * `terms` products: the smallest K with prod_(i<K) q_i > 2^(e+1), where
- * e = bits_a + bits_b + logN + ceil(log2(terms)).  (Host output.) */
+ * `terms` products: the smallest K with prod_(i<K) q_i >= 2^(e+17), where
+ * e = bits_a + bits_b + logN + ceil(log2(terms)) bounds the signed exact result,
+ * |X| < 2^e.  The 16 bits beyond 2^(e+1) keep the CRT quotient of X + 2^e exact
+ * when it is evaluated in double precision.  (Host output.) */
 int fhe_primes_needed(const fhe_ctx* ctx, int logN, int bits_a, int bits_b, int terms, int* K);
 
 /* Limb -> RNS projection (Section 5.1 "Limb-to-RNS Conversion"): for each of
@@ -290,7 +295,7 @@ int fhe_decrypt(fhe_ctx* ctx, int scheme, uint32_t t, uint32_t gamma, int logN, 
  * the same cell (key, logq, bits), up to `max_batch`, and launches it as one
  * CipherTensor pipeline (continuous batching; batches on different streams overlap
  * on the device).  Admission is by HBM footprint: the device scratch the server
- * holds (every stream's workspace, rescale staging and Garner digits, sized to the
+ * holds (every stream's workspace and rescale staging, sized to the
  * batches it runs) never exceeds `hbm_budget` bytes.  A batch waits while it would
  * not fit, idle streams give their scratch back when the budget requires it, a
  * batch is cut to the size that fits, and a request that cannot fit even alone

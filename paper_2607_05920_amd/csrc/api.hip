@@ -219,6 +219,23 @@ struct Recorder : EventRecorder {
   }
 };
 
+// Constant tables of the matrix-core lift of L limbs onto K primes.
+struct LiftTab {
+  v4i_t* A = nullptr;      // A fragments [tile][k-block][lane]
+  uint64_t* off = nullptr; // [p] = [C0 2^32]_(q_p) + 2^20 q_p
+  int nkb = 0, ntiles = 0;
+};
+
+// Constant tables of one CRT reconstruction (prime count K, offset exponent e,
+// output limbs Lout).
+struct CrtTab {
+  v4i_t* A = nullptr;        // MFMA A fragments [tile][k-block][lane]
+  uint32_t* d = nullptr;     // [k] = [2^e c_k]_(q_k)
+  uint32_t* mneg = nullptr;  // limbs of (-M) mod 2^(32 Lout), 8 ntiles words
+  uint32_t* eneg = nullptr;  // limbs of (-2^e) mod 2^(32 Lout), 8 ntiles words
+  int ntiles = 0;
+};
+
 struct fhe_ctx {
   int device = 0;
   int logQ_max = 0, logP_max = 0;
@@ -231,16 +248,13 @@ struct fhe_ctx {
   uint2* tw = nullptr;
   uint2* itw = nullptr;
   uint2* nscale[kLogNMax + 1] = {};  // N^-1 per prime
-  uint2* gscale[kLogNMax + 1] = {};  // N^-1 2^32 I_k per prime (Garner-bound transforms)
   uint32_t* liftT = nullptr;
   int TS = 0, Lmax = 0;
-  uint32_t* Gt = nullptr;
-  int GS = 0;
-  uint32_t* Ct = nullptr;
-  int CS = 0, Dmax = 0;
-  int* kstart = nullptr;
-  std::vector<uint32_t> Ik;  // host copy of I_k
-  std::map<int, uint32_t*> ow;       // per offset exponent e
+  double* invq = nullptr;  // [k] = 1 / q_k
+  std::map<int, std::vector<uint32_t>> crt_c;             // per K: c_k = [(M/q_k)^-1]_(q_k)
+  std::map<std::tuple<int, int, int>, CrtTab> crt;        // per (K, e, Lout)
+  std::map<std::pair<int, int>, uint2*> cscale;           // per (logN, K): [N^-1 2^32 c_k]_(q_k), Shoup
+  std::map<std::pair<int, int>, LiftTab> lifts;           // per (L, K)
   std::map<uint32_t, uint32_t*> pw;  // per BGV t: 2^(32 l) mod t
   std::map<std::pair<void*, int>, Workspace> ws;  // (stream, slot)
   std::recursive_mutex mu;
@@ -260,7 +274,7 @@ struct PlanCell {
 struct fhe_plan {
   fhe_ctx* ctx = nullptr;
   std::vector<PlanCell> cells;
-  uint32_t *ws = nullptr, *stage = nullptr, *dig = nullptr;
+  uint32_t *ws = nullptr, *stage = nullptr;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -290,23 +304,143 @@ int set_sticky(fhe_ctx* c, hipError_t e) {
   return st;
 }
 
-// Smallest K with M_K > 2^(e+1), i.e. bitlen(M_K) >= e + 2 (M_K is odd).
+// Smallest K with M_K >= 2^(e + 1 + margin), i.e. bitlen(M_K) >= e + 2 + margin:
+// |X| < 2^e is recovered from its residues, and Y = X + 2^e satisfies Y / M_K <
+// 2^-margin, which keeps the CRT quotient alpha exact in double precision.
 int primes_for_e(const fhe_ctx* c, int e) {
   for (int k = 0; k <= c->K; ++k)
-    if (c->mbits[k] >= e + 2) return k;
+    if (c->mbits[k] >= e + 2 + kCrtMarginBits) return k;
   return -1;
 }
 
-uint32_t* offsets(fhe_ctx* c, int e, hipError_t* err) {
-  auto it = c->ow.find(e);
-  if (it != c->ow.end()) return it->second;
-  std::vector<uint32_t> h(c->Kpad, 0);
-  for (int k = 0; k < c->K; ++k) h[k] = (uint32_t)mulmod64(powmod(2, e, c->q[k]), c->Ik[k], c->q[k]);
-  uint32_t* d = nullptr;
+// c_k = [(M/q_k)^-1]_(q_k) for the first K primes.
+const std::vector<uint32_t>& crt_c(fhe_ctx* c, int K) {
+  auto it = c->crt_c.find(K);
+  if (it != c->crt_c.end()) return it->second;
+  std::vector<uint32_t> v(K);
+  for (int k = 0; k < K; ++k) {
+    uint64_t m = 1;
+    for (int j = 0; j < K; ++j)
+      if (j != k) m = mulmod64(m, c->q[j], c->q[k]);
+    v[k] = (uint32_t)invmod(m, c->q[k]);
+  }
+  return c->crt_c[K] = std::move(v);
+}
+
+// Final inverse-NTT factors [N^-1 2^32 c_k]_(q_k) (Shoup pairs) for transforms whose
+// output goes to a K-prime CRT reconstruction: 2^32 undoes the 2^-32 of the
+// Montgomery pointwise products, c_k is the CRT factor.
+const uint2* crt_scale(fhe_ctx* c, int logN, int K, hipError_t* err) {
+  auto it = c->cscale.find(std::make_pair(logN, K));
+  if (it != c->cscale.end()) return it->second;
+  const std::vector<uint32_t>& ck = crt_c(c, K);
+  std::vector<uint2> h(c->Kpad, make_uint2(0, 0));
+  for (int k = 0; k < K; ++k) {
+    const uint32_t q = c->q[k];
+    const uint64_t f = mulmod64(mulmod64(invmod(1ull << logN, q), (1ull << 32) % q, q), ck[k], q);
+    h[k] = shoup_pair((uint32_t)f, q);
+  }
+  uint2* d = nullptr;
   *err = upload(&d, h);
   if (*err != hipSuccess) return nullptr;
-  c->ow[e] = d;
+  c->cscale[std::make_pair(logN, K)] = d;
   return d;
+}
+
+// x mod 2^(32 n) as n limbs, for x given by its limbs (truncating or zero-padding).
+std::vector<uint32_t> limbs_mod(const std::vector<uint32_t>& x, int n) {
+  std::vector<uint32_t> r(n, 0);
+  for (int i = 0; i < n && i < (int)x.size(); ++i) r[i] = x[i];
+  return r;
+}
+
+// r = r * m mod 2^(32 n) in place.
+void mul_small_trunc(std::vector<uint32_t>& r, uint32_t m) {
+  uint64_t carry = 0;
+  for (auto& w : r) {
+    const uint64_t t = (uint64_t)w * m + carry;
+    w = (uint32_t)t;
+    carry = t >> 32;
+  }
+}
+
+// -x mod 2^(32 n) in place.
+void negate_trunc(std::vector<uint32_t>& r) {
+  uint64_t carry = 1;
+  for (auto& w : r) {
+    const uint64_t t = (uint64_t)(uint32_t)~w + carry;
+    w = (uint32_t)t;
+    carry = t >> 32;
+  }
+}
+
+// Tables of the K-prime CRT reconstruction with offset 2^e into Lout output limbs.
+const CrtTab* crt_table(fhe_ctx* c, int K, int e, int Lout, hipError_t* err) {
+  const auto key = std::make_tuple(K, e, Lout);
+  auto it = c->crt.find(key);
+  if (it != c->crt.end()) return &it->second;
+  const std::vector<uint32_t>& ck = crt_c(c, K);
+  const int nkb = (K + 31) / 32, ntiles = (Lout + 7) / 8, Lp = 8 * ntiles;
+  CrtTab t;
+  t.ntiles = ntiles;
+  std::vector<uint32_t> d(c->Kpad, 0);
+  for (int k = 0; k < K; ++k) d[k] = (uint32_t)mulmod64(powmod(2, e, c->q[k]), ck[k], c->q[k]);
+  // V_k = (M / q_k) mod 2^(32 Lout) in balanced limbs D_kl in [-0x80808080, 0x7F7F7F7F]
+  std::vector<int64_t> D((size_t)K * Lp, 0);
+  for (int k = 0; k < K; ++k) {
+    std::vector<uint32_t> v(Lout, 0);
+    v[0] = 1;
+    for (int j = 0; j < K; ++j)
+      if (j != k) mul_small_trunc(v, c->q[j]);
+    int64_t carry = 0;
+    for (int l = 0; l < Lout; ++l) {
+      const int64_t u = (int64_t)v[l] + carry;
+      carry = u > 0x7F7F7F7FLL ? 1 : 0;
+      D[(size_t)k * Lp + l] = u - (carry << 32);
+    }
+  }
+  // A fragments: lane (r, h) of tile t, k-block kb holds bytes i < 16 of row r
+  // (digit plane b = r / 8 of limb 8 t + r % 8) at k = 32 kb + 16 h + i
+  std::vector<v4i_t> A((size_t)ntiles * nkb * 64);
+  for (int tt = 0; tt < ntiles; ++tt)
+    for (int kb = 0; kb < nkb; ++kb)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int r = lane & 31, hh = lane >> 5, b = r >> 3, limb = 8 * tt + (r & 7);
+        uint32_t w[4] = {0, 0, 0, 0};
+        for (int i = 0; i < 16; ++i) {
+          const int k = 32 * kb + 16 * hh + i;
+          if (k >= K || limb >= Lout) continue;
+          const uint32_t digits = ((uint32_t)(D[(size_t)k * Lp + limb] + 0x80808080LL)) ^ 0x80808080u;
+          w[i >> 2] |= ((digits >> (8 * b)) & 0xFFu) << (8 * (i & 3));
+        }
+        v4i_t f;
+        f[0] = (int)w[0];
+        f[1] = (int)w[1];
+        f[2] = (int)w[2];
+        f[3] = (int)w[3];
+        A[((size_t)tt * nkb + kb) * 64 + lane] = f;
+      }
+  std::vector<uint32_t> mneg(Lout, 0);
+  mneg[0] = 1;
+  for (int j = 0; j < K; ++j) mul_small_trunc(mneg, c->q[j]);
+  negate_trunc(mneg);
+  std::vector<uint32_t> eneg(Lout, 0);
+  if (e < 32 * Lout) {
+    eneg[e >> 5] = 1u << (e & 31);
+    negate_trunc(eneg);
+  }
+  mneg.resize(Lp, 0);
+  eneg.resize(Lp, 0);
+  *err = upload(&t.A, A);
+  if (*err == hipSuccess) *err = upload(&t.d, d);
+  if (*err == hipSuccess) *err = upload(&t.mneg, mneg);
+  if (*err == hipSuccess) *err = upload(&t.eneg, eneg);
+  if (*err != hipSuccess) {
+    for (void* p : {(void*)t.A, (void*)t.d, (void*)t.mneg, (void*)t.eneg})
+      if (p) hipFree(p);
+    return nullptr;
+  }
+  return &(c->crt[key] = t);
 }
 
 uint32_t* pow_table(fhe_ctx* c, uint32_t t, hipError_t* err) {
@@ -360,9 +494,74 @@ NttArgs ntt_args(fhe_ctx* c, uint32_t* data, int logN, int K, int per_group, lon
   return a;
 }
 
+// Tables of the matrix-core lift of L limbs onto K primes (built on first use).
+const LiftTab* lift_table(fhe_ctx* c, int L, int K, hipError_t* err) {
+  const auto key = std::make_pair(L, K);
+  auto it = c->lifts.find(key);
+  if (it != c->lifts.end()) return &it->second;
+  LiftTab t;
+  t.nkb = (L + 7) / 8;
+  t.ntiles = (K + 7) / 8;
+  // T_(i,a),p = [2^(32 i + 8 a + 32)]_(q_p), i < 8 nkb, a < 4
+  std::vector<uint32_t> T((size_t)K * 32 * t.nkb, 0);
+  std::vector<uint64_t> off(c->Kpad, 0);
+  for (int p = 0; p < K; ++p) {
+    const uint32_t q = c->q[p];
+    const uint64_t r32 = (1ull << 32) % q;
+    uint64_t v = r32;
+    for (int i = 0; i < 32 * t.nkb; ++i) {
+      T[(size_t)p * 32 * t.nkb + i] = (uint32_t)v;
+      v = mulmod64(v, 256, q);
+    }
+    // C0 = 0x80808080 sum_(i<L) 2^(32 i), in Montgomery form, plus 2^20 q
+    uint64_t sum = 0, pw = 1;
+    for (int i = 0; i < L; ++i) {
+      sum = (sum + pw) % q;
+      pw = mulmod64(pw, r32, q);
+    }
+    const uint64_t c0 = mulmod64(mulmod64(0x80808080ull % q, sum, q), r32, q);
+    off[p] = c0 + ((uint64_t)q << 20);
+  }
+  std::vector<v4i_t> A((size_t)t.ntiles * t.nkb * 64);
+  for (int tt = 0; tt < t.ntiles; ++tt)
+    for (int kb = 0; kb < t.nkb; ++kb)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int r = lane & 31, hh = lane >> 5, b = r >> 3, p = 8 * tt + (r & 7);
+        uint32_t w[4] = {0, 0, 0, 0};
+        for (int i = 0; i < 16; ++i) {
+          const int li = 8 * kb + 4 * hh + (i >> 2), dg = i & 3;
+          if (li >= L || p >= K) continue;
+          const uint32_t tv = T[(size_t)p * 32 * t.nkb + 4 * li + dg];
+          const uint32_t digits = (tv + 0x80808080u) ^ 0x80808080u;
+          w[i >> 2] |= ((digits >> (8 * b)) & 0xFFu) << (8 * (i & 3));
+        }
+        v4i_t f;
+        f[0] = (int)w[0];
+        f[1] = (int)w[1];
+        f[2] = (int)w[2];
+        f[3] = (int)w[3];
+        A[((size_t)tt * t.nkb + kb) * 64 + lane] = f;
+      }
+  *err = upload(&t.A, A);
+  if (*err == hipSuccess) *err = upload(&t.off, off);
+  if (*err != hipSuccess) {
+    if (t.A) hipFree(t.A);
+    if (t.off) hipFree(t.off);
+    return nullptr;
+  }
+  return &(c->lifts[key] = t);
+}
+
 LiftArgs lift_args(fhe_ctx* c, const uint32_t* limbs, uint32_t* res, long long in_stride,
                    long long out_stride, int N, int L, int K) {
   LiftArgs a{};
+  hipError_t err = hipSuccess;
+  if (const LiftTab* t = lift_table(c, L, K, &err)) {  // else only the VALU lift is available
+    a.A = t->A;
+    a.off = t->off;
+    a.nkb = t->nkb;
+    a.ntiles = t->ntiles;
+  }
   a.limbs = limbs;
   a.res = res;
   a.in_stride = in_stride;
@@ -376,10 +575,16 @@ LiftArgs lift_args(fhe_ctx* c, const uint32_t* limbs, uint32_t* res, long long i
   return a;
 }
 
-GarnerArgs garner_args(fhe_ctx* c, const uint32_t* res, int per_group, long long gstride,
-                       long long pstride, uint32_t* out, long long ostride, int N, int K,
-                       int outbits, const uint32_t* ow) {
-  GarnerArgs a{};
+// CRT reconstruction of npoly polynomials: residues of X (with |X| < 2^e) on K
+// primes -> X mod 2^outbits.  Poly z reads res + (z / per_group) gstride +
+// (z % per_group) pstride and writes out + z ostride.
+hipError_t run_crt(fhe_ctx* c, const uint32_t* res, int per_group, long long gstride, long long pstride,
+                   uint32_t* out, long long ostride, int N, int K, int e, int outbits, int npoly, hipStream_t st) {
+  hipError_t err = hipSuccess;
+  const int Lout = (outbits + 31) / 32;
+  const CrtTab* t = crt_table(c, K, e, Lout, &err);
+  if (!t) return err;
+  CrtArgs a{};
   a.res = res;
   a.per_group = per_group;
   a.gstride = gstride;
@@ -389,25 +594,30 @@ GarnerArgs garner_args(fhe_ctx* c, const uint32_t* res, int per_group, long long
   a.N = N;
   a.K = K;
   a.outbits = outbits;
-  a.Lout = (outbits + 31) / 32;
+  a.Lout = Lout;
+  a.ntiles = t->ntiles;
+  a.A = t->A;
   a.pc = c->pc;
-  a.Gt = c->Gt;
-  a.GS = c->GS;
-  a.Ow = ow;
-  a.Ct = c->Ct;
-  a.CS = c->CS;
-  a.kstart = c->kstart;
-  a.mbits = c->mbits.data();
-  return a;
+  a.d = t->d;
+  a.invq = c->invq;
+  a.mneg = t->mneg;
+  a.eneg = t->eneg;
+  return launch_crt(a, npoly, st);
 }
 
-// Garner launch with its digit scratch (slot 2 of the stream's scratch memory).
-hipError_t run_garner(fhe_ctx* c, void* stream, GarnerArgs a, int npoly) {
-  hipError_t e = hipSuccess;
-  const size_t words = (size_t)npoly * ((a.N + 63) / 64) * garner_wave_words(a.K);
-  a.dig = (uint32_t*)scratch(c, stream, 2, words * 4, &e);
-  if (!a.dig) return e;
-  return launch_garner(a, npoly, (hipStream_t)stream);
+// Creates the lift and CRT tables one pipeline run at (key, logN, logq) uses, so that a run
+// under stream capture allocates and uploads nothing.
+bool tables_prewarm(fhe_ctx* c, const fhe_evk* k, int logN, int logq, hipError_t* err) {
+  const int Kt = primes_for_e(c, 2 * logq + logN + 1), Kr = primes_for_e(c, logN + 2 * logq + k->logP);
+  if (Kt < 0 || Kr < 0) {
+    *err = hipErrorInvalidValue;
+    return false;
+  }
+  const int L = (logq + 31) / 32;
+  return lift_table(c, L, Kt, err) && lift_table(c, L, Kr, err) && crt_scale(c, logN, Kt, err) &&
+         crt_scale(c, logN, Kr, err) &&
+         crt_table(c, Kt, 2 * logq + logN + 1, (logq + 31) / 32, err) &&
+         crt_table(c, Kr, logN + 2 * logq + k->logP, (k->logP + logq + 31) / 32, err);
 }
 
 // Build the relinearization key's NTT form for level logq.
@@ -467,10 +677,10 @@ struct PipeIO {
 };
 
 // Scratch words of one pipeline run (main area, staging of the relinearized
-// ciphertexts before rescale, Garner digit scratch).
+// ciphertexts before rescale).
 struct PipeSize {
   int Kt = 0, Kr = 0, L = 0, LK = 0;
-  long long main_words = 0, stage_words = 0, digit_words = 0;
+  long long main_words = 0, stage_words = 0;
 };
 
 PipeSize pipe_size(const fhe_ctx* c, const fhe_evk* k, int logN, int logq, int cnum) {
@@ -483,8 +693,6 @@ PipeSize pipe_size(const fhe_ctx* c, const fhe_evk* k, int logN, int logq, int c
   if (z.Kt < 0 || z.Kr < 0) return z;
   z.main_words = (long long)cnum * NN * (4LL * z.Kt + 3LL * z.L + z.Kr + 2LL * z.Kr + 2LL * z.LK);
   z.stage_words = 2LL * cnum * z.L * NN;
-  z.digit_words = std::max((long long)cnum * 3 * (NN / 64) * garner_wave_words(z.Kt),
-                           (long long)cnum * 2 * (NN / 64) * garner_wave_words(z.Kr));
   return z;
 }
 
@@ -492,7 +700,7 @@ PipeSize pipe_size(const fhe_ctx* c, const fhe_evk* k, int logN, int logq, int c
 // 2^logq); lift d2, NTT, products with the resident key, iNTT, Garner (k0, k1 mod
 // 2^(logP+logq)); c_i = [d_i + R(k_i)]_(2^logq); then, if bits > 0, the rescale.
 int pipeline(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, const PipeIO& io, int cnum, hipStream_t st,
-             uint32_t* ws, uint32_t* stage, uint32_t* dig, const Tuning& tu) {
+             uint32_t* ws, uint32_t* stage, const Tuning& tu) {
   const int N = 1 << logN;
   const PipeSize z = pipe_size(c, k, logN, logq, cnum);
   if (z.Kt < 0 || z.Kr < 0) return FHE_E_RANGE;
@@ -500,10 +708,11 @@ int pipeline(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, const PipeIO&
   const int logP = k->logP;
   const uint32_t* evk_ntt = k->ntt.at(logq);
   hipError_t e = hipSuccess;
-  const uint32_t* owt = offsets(c, 2 * logq + logN + 1, &e);
-  if (!owt) return set_sticky(c, e);
-  const uint32_t* owr = offsets(c, logN + 2 * logq + logP, &e);
-  if (!owr) return set_sticky(c, e);
+  const int et = 2 * logq + logN + 1, er = logN + 2 * logq + logP;  // |d_i| < 2^et, |k_i| < 2^er
+  const uint2* sct = crt_scale(c, logN, Kt, &e);
+  if (!sct) return set_sticky(c, e);
+  const uint2* scr = crt_scale(c, logN, Kr, &e);
+  if (!scr) return set_sticky(c, e);
   const long long NN = N;
   uint32_t* Rt = ws;                                    // [cnum][4][Kt][N]
   uint32_t* Dl = Rt + (long long)cnum * 4 * Kt * NN;    // [cnum][3][L][N]
@@ -531,16 +740,12 @@ int pipeline(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, const PipeIO&
     pa.pc = c->pc;
     e = launch_tensor_pointwise(pa, cnum, st);
   }
-  // 4. inverse NTT of slots 0..2 (final factor N^-1 2^32 I_k)
+  // 4. inverse NTT of slots 0..2 (final factor N^-1 2^32 c_k)
   if (e == hipSuccess)
-    e = launch_ntt(ntt_args(c, Rt, logN, Kt, 3 * Kt, 4LL * Kt * NN, true, c->gscale[logN]), cnum * 3 * Kt, true,
-                   st, tu);
-  // 5. Garner -> d0, d1, d2 mod 2^logq: Dl[c][i][L][N]
-  if (e == hipSuccess) {
-    GarnerArgs ga = garner_args(c, Rt, 3, 4LL * Kt * NN, (long long)Kt * NN, Dl, polyw, N, Kt, logq, owt);
-    ga.dig = dig;
-    e = launch_garner(ga, cnum * 3, st);
-  }
+    e = launch_ntt(ntt_args(c, Rt, logN, Kt, 3 * Kt, 4LL * Kt * NN, true, sct), cnum * 3 * Kt, true, st, tu);
+  // 5. CRT -> d0, d1, d2 mod 2^logq: Dl[c][i][L][N]
+  if (e == hipSuccess)
+    e = run_crt(c, Rt, 3, 4LL * Kt * NN, (long long)Kt * NN, Dl, polyw, N, Kt, et, logq, cnum * 3, st);
   // 6. lift d2 onto Kr primes; 7. forward NTT
   if (e == hipSuccess)
     e = launch_lift(lift_args(c, Dl + 2 * polyw, Rr, 3 * polyw, (long long)Kr * NN, N, L, Kr), cnum, st, tu);
@@ -559,16 +764,12 @@ int pipeline(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, const PipeIO&
     pa.pc = c->pc;
     e = launch_relin_pointwise(pa, cnum, st);
   }
-  // 9. inverse NTT; 10. Garner -> k0, k1 mod 2^(logP + logq)
+  // 9. inverse NTT; 10. CRT -> k0, k1 mod 2^(logP + logq)
   if (e == hipSuccess)
-    e = launch_ntt(ntt_args(c, Rk, logN, Kr, 2 * Kr, 2LL * Kr * NN, true, c->gscale[logN]), cnum * 2 * Kr, true,
-                   st, tu);
-  if (e == hipSuccess) {
-    GarnerArgs ga = garner_args(c, Rk, 2, 2LL * Kr * NN, (long long)Kr * NN, Kl, (long long)LK * NN, N, Kr,
-                                logP + logq, owr);
-    ga.dig = dig;
-    e = launch_garner(ga, cnum * 2, st);
-  }
+    e = launch_ntt(ntt_args(c, Rk, logN, Kr, 2 * Kr, 2LL * Kr * NN, true, scr), cnum * 2 * Kr, true, st, tu);
+  if (e == hipSuccess)
+    e = run_crt(c, Rk, 2, 2LL * Kr * NN, (long long)Kr * NN, Kl, (long long)LK * NN, N, Kr, er, logP + logq,
+                cnum * 2, st);
   // 11. c_i = [d_i + R(k_i)]_(2^logq), to the outputs or (rescale follows) the staging area
   const uint32_t* pwt = nullptr;
   if (e == hipSuccess && k->scheme == FHE_BGV) pwt = pow_table(c, k->t, &e);
@@ -646,9 +847,7 @@ int mul_relin_locked(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, const
     stage = (uint32_t*)scratch(c, st, 1, (size_t)z.stage_words * 4, &e);
     if (!stage) return set_sticky(c, e);
   }
-  uint32_t* dig = (uint32_t*)scratch(c, st, 2, (size_t)z.digit_words * 4, &e);
-  if (!dig) return set_sticky(c, e);
-  return pipeline(c, k, logN, logq, bits, io, cnum, st, ws, stage, dig, Tuning());
+  return pipeline(c, k, logN, logq, bits, io, cnum, st, ws, stage, Tuning());
 }
 
 int rescale_locked(fhe_ctx* c, int scheme, uint32_t t, int logN, int logq, int bits,
@@ -683,7 +882,7 @@ int plan_run_cells(fhe_plan* pl, hipStream_t st) {
     io.ins = cell.ptrs;
     io.outs = cell.ptrs + 4LL * cell.cnum;
     const int rc = pipeline(pl->ctx, cell.evk, cell.logN, cell.logq, cell.bits, io, cell.cnum, st, pl->ws,
-                            pl->stage, pl->dig, cell.tune);
+                            pl->stage, cell.tune);
     if (rc != FHE_OK) return rc;
   }
   return FHE_OK;
@@ -702,7 +901,7 @@ int plan_autotune(fhe_plan* pl, PlanCell& cell, hipStream_t st) {
     return FHE_OK;
   }
   std::vector<Tuning> cands;
-  for (int lp : {8, 16, 32})
+  for (int lp : {0, 16})
     for (int cf : {1, 0}) {
       if (cf == 0 && (cell.logN % 2 == 0)) continue;  // same split either way
       Tuning t;
@@ -724,10 +923,10 @@ int plan_autotune(fhe_plan* pl, PlanCell& cell, hipStream_t st) {
   int rc = FHE_OK;
   for (const Tuning& t : cands) {
     float ts[3];
-    rc = pipeline(c, cell.evk, cell.logN, cell.logq, cell.bits, io, cell.cnum, st, pl->ws, pl->stage, pl->dig, t);
+    rc = pipeline(c, cell.evk, cell.logN, cell.logq, cell.bits, io, cell.cnum, st, pl->ws, pl->stage, t);
     for (int r = 0; r < 3 && rc == FHE_OK; ++r) {
       hipEventRecord(e0, st);
-      rc = pipeline(c, cell.evk, cell.logN, cell.logq, cell.bits, io, cell.cnum, st, pl->ws, pl->stage, pl->dig,
+      rc = pipeline(c, cell.evk, cell.logN, cell.logq, cell.bits, io, cell.cnum, st, pl->ws, pl->stage,
                     t);
       hipEventRecord(e1, st);
       if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ts[r], e0, e1) != hipSuccess)
@@ -754,7 +953,7 @@ void plan_free(fhe_plan* pl) {
   if (pl->cap) hipStreamDestroy(pl->cap);
   for (PlanCell& cell : pl->cells)
     if (cell.ptrs) hipFree(cell.ptrs);
-  for (void* p : {(void*)pl->ws, (void*)pl->stage, (void*)pl->dig})
+  for (void* p : {(void*)pl->ws, (void*)pl->stage})
     if (p) hipFree(p);
   delete pl;
 }
@@ -779,9 +978,9 @@ struct SrvLater {
   }
 };
 
-// Scratch words one batch needs (main workspace, rescale staging, Garner digits).
+// Scratch words one batch needs (main workspace, rescale staging).
 struct SrvNeed {
-  long long main = 0, stage = 0, dig = 0;
+  long long main = 0, stage = 0;
 };
 
 // One worker stream with its own scratch and pointer staging.
@@ -791,8 +990,8 @@ struct SrvSlot {
   bool busy = false;
   std::vector<SrvReq> reqs;
   uint64_t t_start = 0;
-  uint32_t *ws = nullptr, *stage = nullptr, *dig = nullptr;
-  long long ws_words = 0, stage_words = 0, dig_words = 0;
+  uint32_t *ws = nullptr, *stage = nullptr;
+  long long ws_words = 0, stage_words = 0;
   const uint32_t** hptr = nullptr;  // pinned host staging of the pointer arrays
   uint32_t** dptr = nullptr;        // device pointer arrays (6 max_batch)
 };
@@ -821,27 +1020,24 @@ SrvNeed batch_need(const fhe_ctx* c, const fhe_job& j, int cnum) {
   SrvNeed n;
   n.main = z.main_words;
   n.stage = j.bits > 0 ? z.stage_words : 0;
-  n.dig = z.digit_words;
   return n;
 }
 
-size_t need_bytes(const SrvNeed& n) { return (size_t)(n.main + n.stage + n.dig) * 4; }
+size_t need_bytes(const SrvNeed& n) { return (size_t)(n.main + n.stage) * 4; }
 
-size_t slot_held(const SrvSlot& s) { return (size_t)(s.ws_words + s.stage_words + s.dig_words) * 4; }
+size_t slot_held(const SrvSlot& s) { return (size_t)(s.ws_words + s.stage_words) * 4; }
 
 // Bytes the slot holds once grown for `n`.
 size_t slot_after(const SrvSlot& s, const SrvNeed& n) {
-  return (size_t)(std::max(s.ws_words, n.main) + std::max(s.stage_words, n.stage) +
-                  std::max(s.dig_words, n.dig)) *
-         4;
+  return (size_t)(std::max(s.ws_words, n.main) + std::max(s.stage_words, n.stage)) * 4;
 }
 
 // Frees an idle slot's scratch (its last batch has completed).
 void slot_release(SrvSlot& s) {
   hipStreamSynchronize(s.st);
-  for (uint32_t** p : {&s.ws, &s.stage, &s.dig})
+  for (uint32_t** p : {&s.ws, &s.stage})
     if (*p) hipFree(*p), *p = nullptr;
-  s.ws_words = s.stage_words = s.dig_words = 0;
+  s.ws_words = s.stage_words = 0;
 }
 
 }  // namespace
@@ -877,7 +1073,6 @@ int srv_launch(fhe_server* sv, SrvSlot& sl, std::vector<SrvReq>& reqs, const Srv
   if (rc != FHE_OK) return rc;
   hipError_t e = grow(&sl.ws, &sl.ws_words, need.main, sl.st);
   if (e == hipSuccess) e = grow(&sl.stage, &sl.stage_words, need.stage, sl.st);
-  if (e == hipSuccess) e = grow(&sl.dig, &sl.dig_words, need.dig, sl.st);
   if (e != hipSuccess) return set_sticky(c, e);
   // the previous batch of this slot has completed, so its staging may be rewritten
   for (int m = 0; m < cnum; ++m) {
@@ -894,7 +1089,7 @@ int srv_launch(fhe_server* sv, SrvSlot& sl, std::vector<SrvReq>& reqs, const Srv
   PipeIO io;
   io.ins = sl.dptr;
   io.outs = sl.dptr + 4LL * cnum;
-  rc = pipeline(c, j0.evk, j0.evk->logN, j0.logq, j0.bits, io, cnum, sl.st, sl.ws, sl.stage, sl.dig, Tuning());
+  rc = pipeline(c, j0.evk, j0.evk->logN, j0.logq, j0.bits, io, cnum, sl.st, sl.ws, sl.stage, Tuning());
   if (rc != FHE_OK) return rc;
   return set_sticky(c, hipEventRecord(sl.done, sl.st));
 }
@@ -1037,8 +1232,8 @@ int ring_mul_locked(fhe_ctx* c, int logN, int logq, const uint32_t* a, const uin
   const int K = primes_for_e(c, eb);
   if (K < 0) return FHE_E_RANGE;
   hipError_t e = hipSuccess;
-  const uint32_t* ow = offsets(c, eb, &e);
-  if (!ow) return set_sticky(c, e);
+  const uint2* sc = crt_scale(c, logN, K, &e);
+  if (!sc) return set_sticky(c, e);
   const long long KN = (long long)K * N;
   uint32_t* R = (uint32_t*)scratch(c, stream, 0, (size_t)2 * cnum * KN * 4, &e);
   if (!R) return set_sticky(c, e);
@@ -1057,9 +1252,8 @@ int ring_mul_locked(fhe_ctx* c, int logN, int logq, const uint32_t* a, const uin
     pa.pc = c->pc;
     e = launch_ring_pointwise(pa, cnum, st);
   }
-  if (e == hipSuccess) e = launch_ntt(ntt_args(c, Ra, logN, K, K, KN, true, c->gscale[logN]), cnum * K, true, st);
-  if (e == hipSuccess)
-    e = run_garner(c, stream, garner_args(c, Ra, 1, KN, 0, out, (long long)L * N, N, K, logq, ow), cnum);
+  if (e == hipSuccess) e = launch_ntt(ntt_args(c, Ra, logN, K, K, KN, true, sc), cnum * K, true, st);
+  if (e == hipSuccess) e = run_crt(c, Ra, 1, KN, 0, out, (long long)L * N, N, K, eb, logq, cnum, st);
   return set_sticky(c, e);
 }
 
@@ -1103,8 +1297,8 @@ int fhe_ctx_create(int device, int logQ_max, int logP_max, fhe_ctx** out) {
   c->logQ_max = logQ_max;
   c->logP_max = logP_max;
   // primes q = 1 mod 2^17 below 2^30, largest first, until the largest relinearization
-  // product (logN 16, logq = logQ_max, logP = logP_max) is covered.
-  const int e_max = kLogNMax + 2 * logQ_max + logP_max;
+  // product (logN 16, logq = logQ_max, logP = logP_max) is covered with the CRT margin.
+  const int e_max = kLogNMax + 2 * logQ_max + logP_max + kCrtMarginBits;
   Big M;
   c->mbits.push_back(M.bitlen());
   for (uint32_t cand = (1u << 30) - (1u << 17) + 1; cand > (1u << 29); cand -= (1u << 17)) {
@@ -1120,11 +1314,11 @@ int fhe_ctx_create(int device, int logQ_max, int logP_max, fhe_ctx** out) {
   }
   const int K = (int)c->q.size();
   c->K = K;
-  if (K + kGarnerBlock + kLiftPrimes > kGarnerGS) {
+  if (K > kCrtMaxPrimes) {
     delete c;
     return FHE_E_RANGE;
   }
-  c->Kpad = K + kGarnerBlock + kLiftPrimes;
+  c->Kpad = K + 16 + kLiftPrimes;  // blocked kernels read per-prime constants past K
   const int Kpad = c->Kpad;
   // psi: g^((q-1)/2^17) for the smallest g with order exactly 2^17
   for (int k = 0; k < K; ++k) {
@@ -1148,72 +1342,8 @@ int fhe_ctx_create(int device, int logQ_max, int logP_max, fhe_ctx** out) {
     pc[k].c32 = (uint32_t)((1ull << 32) % q);
     pc[k].two_q = 2 * q;
   }
-  // I_k = [M_k^-1]_(q_k); mk[j][k] = [M_j]_(q_k)
-  c->Ik.assign(K, 1);
-  std::vector<uint32_t> Mmod(K, 1);  // running [M_j]_(q_k) for the current j
-  c->GS = kGarnerGS;
-  std::vector<uint32_t> Gt((size_t)K * c->GS, 0);
-  for (int j = 0; j < K; ++j) {
-    for (int k = j + 1; k < K; ++k) {
-      // Mmod[k] currently holds [M_j]_(q_k)
-      Gt[(size_t)j * c->GS + k] = Mmod[k];
-    }
-    for (int k = 0; k < K; ++k) Mmod[k] = (uint32_t)mulmod64(Mmod[k], c->q[j], c->q[k]);
-  }
-  {
-    // I_k from [M_k]_(q_k): recompute M_k mod q_k
-    for (int k = 0; k < K; ++k) {
-      uint64_t m = 1;
-      for (int i = 0; i < k; ++i) m = mulmod64(m, c->q[i], c->q[k]);
-      c->Ik[k] = (uint32_t)invmod(m, c->q[k]);
-    }
-    for (int j = 0; j < K; ++j)
-      for (int k = j + 1; k < K; ++k) {
-        uint64_t v = mulmod64(Gt[(size_t)j * c->GS + k], c->Ik[k], c->q[k]);
-        Gt[(size_t)j * c->GS + k] = (uint32_t)mulmod64(v, (1ull << 32) % c->q[k], c->q[k]);
-      }
-  }
-  // column digits of M_k (radix 2^26) and first contributing k per column
-  const int outbits_max = logP_max + logQ_max;
-  c->Dmax = (outbits_max + kHornerDigitBits - 1) / kHornerDigitBits;
-  std::vector<uint32_t> Csq((size_t)Kpad * (c->Dmax + kHornerBlock), 0);
-  const int CW = c->Dmax + kHornerBlock;
-  {
-    Big Mk;
-    for (int k = 0; k < K; ++k) {
-      for (int m = 0; m < c->Dmax; ++m) Csq[(size_t)k * CW + m] = Mk.bits_at(kHornerDigitBits * m, kHornerDigitBits);
-      Mk.mul_small(c->q[k]);
-    }
-  }
-  // Both Garner tables are stored in the order the kernel consumes them, one 64-byte
-  // row of 16 constants after another, so scalar-cache lines are read sequentially
-  // and used whole.  Digit block b (digits 16b .. 16b+15): rows j = 0 .. 16b+15 of
-  // the 16 columns k = 16b .. 16b+15, segment at word 256 b (b + 1) / 2.  Column block
-  // c (radix-2^26 columns 16c .. 16c+15): rows k = 0 .. Kpad-1, segment at word
-  // c Kpad 16.
-  const int NB = (K + kGarnerBlock - 1) / kGarnerBlock;
-  std::vector<uint32_t> Gb((size_t)256 * NB * (NB + 1) / 2, 0);
-  for (int b = 0; b < NB; ++b) {
-    const size_t off = (size_t)256 * b * (b + 1) / 2;
-    for (int j = 0; j < 16 * b + 16; ++j)
-      for (int u = 0; u < 16; ++u) {
-        const int k = 16 * b + u;
-        if (j < K && k < K && j < k) Gb[off + (size_t)16 * j + u] = Gt[(size_t)j * c->GS + k];
-      }
-  }
-  const int NC = (c->Dmax + kHornerBlock - 1) / kHornerBlock;
-  std::vector<uint32_t> Cb((size_t)NC * Kpad * 16, 0);
-  for (int cb = 0; cb < NC; ++cb)
-    for (int k = 0; k < Kpad; ++k)
-      for (int m = 0; m < 16; ++m) Cb[((size_t)cb * Kpad + k) * 16 + m] = Csq[(size_t)k * CW + 16 * cb + m];
-  c->CS = Kpad * 16;  // words per column-block segment
-  std::vector<int> kstart(c->Dmax + kHornerBlock, K);
-  for (int m = 0; m < (int)kstart.size(); ++m)
-    for (int k = 0; k < K; ++k)
-      if (c->mbits[k] > kHornerDigitBits * m) {
-        kstart[m] = k;
-        break;
-      }
+  std::vector<double> iq(Kpad, 0.0);
+  for (int k = 0; k < K; ++k) iq[k] = 1.0 / (double)c->q[k];
   // lift constants 2^(28 i) 2^32 mod q_p (Montgomery form)
   c->Lmax = (std::max(logQ_max, logP_max + logQ_max) + 31) / 32;
   c->TS = 8 * ((c->Lmax + 6) / 7);
@@ -1248,28 +1378,17 @@ int fhe_ctx_create(int device, int logQ_max, int logP_max, fhe_ctx** out) {
       }
     }
   }
-  // final inverse factors per logN
-  std::vector<std::vector<uint2>> ns(kLogNMax + 1), gs(kLogNMax + 1);
+  // final inverse factors N^-1 per logN (standalone transforms)
+  std::vector<std::vector<uint2>> ns(kLogNMax + 1);
   for (int lg = FHE_LOGN_MIN; lg <= kLogNMax; ++lg) {
     ns[lg].assign(Kpad, make_uint2(0, 0));
-    gs[lg].assign(Kpad, make_uint2(0, 0));
-    for (int p = 0; p < K; ++p) {
-      const uint32_t q = c->q[p];
-      const uint64_t ni = invmod(1ull << lg, q);
-      ns[lg][p] = shoup_pair((uint32_t)ni, q);
-      const uint64_t g = mulmod64(mulmod64(ni, (1ull << 32) % q, q), c->Ik[p], q);
-      gs[lg][p] = shoup_pair((uint32_t)g, q);
-    }
+    for (int p = 0; p < K; ++p) ns[lg][p] = shoup_pair((uint32_t)invmod(1ull << lg, c->q[p]), c->q[p]);
   }
   // upload
   if ((e = upload(&c->pc, pc)) == hipSuccess && (e = upload(&c->tw, tw)) == hipSuccess &&
       (e = upload(&c->itw, itw)) == hipSuccess && (e = upload(&c->liftT, T)) == hipSuccess &&
-      (e = upload(&c->Gt, Gb)) == hipSuccess && (e = upload(&c->Ct, Cb)) == hipSuccess &&
-      (e = upload(&c->kstart, kstart)) == hipSuccess) {
-    for (int lg = FHE_LOGN_MIN; lg <= kLogNMax && e == hipSuccess; ++lg) {
-      e = upload(&c->nscale[lg], ns[lg]);
-      if (e == hipSuccess) e = upload(&c->gscale[lg], gs[lg]);
-    }
+      (e = upload(&c->invq, iq)) == hipSuccess) {
+    for (int lg = FHE_LOGN_MIN; lg <= kLogNMax && e == hipSuccess; ++lg) e = upload(&c->nscale[lg], ns[lg]);
   }
   if (e != hipSuccess) {
     const int st = e == hipErrorOutOfMemory ? FHE_E_NOMEM : FHE_E_DEVICE;
@@ -1284,14 +1403,17 @@ void fhe_ctx_destroy(fhe_ctx* c) {
   if (!c) return;
   hipSetDevice(c->device);
   hipDeviceSynchronize();
-  for (void* p : {(void*)c->pc, (void*)c->tw, (void*)c->itw, (void*)c->liftT, (void*)c->Gt, (void*)c->Ct,
-                  (void*)c->kstart})
+  for (void* p : {(void*)c->pc, (void*)c->tw, (void*)c->itw, (void*)c->liftT, (void*)c->invq})
     if (p) hipFree(p);
-  for (int lg = 0; lg <= kLogNMax; ++lg) {
+  for (int lg = 0; lg <= kLogNMax; ++lg)
     if (c->nscale[lg]) hipFree(c->nscale[lg]);
-    if (c->gscale[lg]) hipFree(c->gscale[lg]);
-  }
-  for (auto& kv : c->ow) hipFree(kv.second);
+  for (auto& kv : c->cscale) hipFree(kv.second);
+  for (auto& kv : c->lifts)
+    for (void* p : {(void*)kv.second.A, (void*)kv.second.off})
+      if (p) hipFree(p);
+  for (auto& kv : c->crt)
+    for (void* p : {(void*)kv.second.A, (void*)kv.second.d, (void*)kv.second.mneg, (void*)kv.second.eneg})
+      if (p) hipFree(p);
   for (auto& kv : c->pw) hipFree(kv.second);
   for (auto& kv : c->ws)
     if (kv.second.ptr) hipFree(kv.second.ptr);
@@ -1609,7 +1731,7 @@ int fhe_batch_plan(fhe_ctx* c, const fhe_job* jobs, int njobs, int flags, void* 
     members[ci].push_back(i);
   }
   int rc = FHE_OK;
-  long long mw = 0, sw = 0, dw = 0;
+  long long mw = 0, sw = 0;
   for (size_t ci = 0; ci < pl->cells.size() && rc == FHE_OK; ++ci) {
     PlanCell& cell = pl->cells[ci];
     cell.cnum = (int)members[ci].size();
@@ -1618,8 +1740,7 @@ int fhe_batch_plan(fhe_ctx* c, const fhe_job* jobs, int njobs, int flags, void* 
     {
       // tables the pipeline would otherwise upload lazily (not allowed under capture)
       hipError_t e = hipSuccess;
-      if (!offsets(c, 2 * cell.logq + cell.logN + 1, &e) ||
-          !offsets(c, cell.logN + 2 * cell.logq + cell.evk->logP, &e) ||
+      if (!tables_prewarm(c, cell.evk, cell.logN, cell.logq, &e) ||
           (cell.evk->scheme == FHE_BGV && !pow_table(c, cell.evk->t, &e))) {
         rc = set_sticky(c, e);
         break;
@@ -1632,7 +1753,6 @@ int fhe_batch_plan(fhe_ctx* c, const fhe_job* jobs, int njobs, int flags, void* 
     }
     mw = std::max(mw, z.main_words);
     sw = std::max(sw, z.stage_words);
-    dw = std::max(dw, z.digit_words);
     std::vector<const uint32_t*> h(6 * (size_t)cell.cnum);
     for (int m = 0; m < cell.cnum; ++m) {
       const fhe_job& j = jobs[members[ci][m]];
@@ -1650,7 +1770,6 @@ int fhe_batch_plan(fhe_ctx* c, const fhe_job* jobs, int njobs, int flags, void* 
   if (rc == FHE_OK) {
     hipError_t e = hipMalloc((void**)&pl->ws, (size_t)std::max(mw, 1LL) * 4);
     if (e == hipSuccess) e = hipMalloc((void**)&pl->stage, (size_t)std::max(sw, 1LL) * 4);
-    if (e == hipSuccess) e = hipMalloc((void**)&pl->dig, (size_t)std::max(dw, 1LL) * 4);
     if (e != hipSuccess) rc = set_sticky(c, e);
   }
   if (rc == FHE_OK && (flags & FHE_PLAN_AUTOTUNE)) {
@@ -1802,7 +1921,7 @@ void fhe_server_destroy(fhe_server* sv) {
   hipSetDevice(sv->ctx->device);
   for (SrvSlot& sl : sv->slots) {
     if (sl.st) hipStreamSynchronize(sl.st);
-    for (void* p : {(void*)sl.ws, (void*)sl.stage, (void*)sl.dig, (void*)sl.dptr})
+    for (void* p : {(void*)sl.ws, (void*)sl.stage, (void*)sl.dptr})
       if (p) hipFree(p);
     if (sl.hptr) hipHostFree(sl.hptr);
     if (sl.done) hipEventDestroy(sl.done);

@@ -8,14 +8,14 @@
 
 namespace fhe {
 
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+
 constexpr int kLogNMax = 16;
 constexpr int kNMax = 1 << kLogNMax;
 constexpr int kLiftDigitBits = 28;    // lift input digits: 8 digits = 7 limbs
-constexpr int kHornerDigitBits = 26;  // Garner output radix
-constexpr int kGarnerBlock = 16;      // digits finalized per block (accumulators)
-constexpr int kHornerBlock = 16;      // output columns per block
 constexpr int kLiftPrimes = 32;       // largest primes-per-thread choice of the lift
-constexpr int kGarnerGS = 256;        // row stride of the host's square digit table (K <= 224)
+constexpr int kCrtMarginBits = 16;    // prime product >= 2^(e + 1 + margin): exact alpha
+constexpr int kCrtMaxPrimes = 256;    // k-blocks of 32 held in registers by the CRT kernel (<= 8)
 
 // Negacyclic NTT over a set of transforms.  Transform (group g, row r) lives at
 // data + g * group_stride + r * N and uses prime r % K; per_group (rows per group)
@@ -39,9 +39,14 @@ struct LiftArgs {
   long long in_stride = 0, out_stride = 0;
   int N = 0, L = 0, K = 0;
   int npoly = 0;          // set by launch_lift
-  const uint32_t* T = nullptr; // [prime][TS]: 2^(28 i) 2^32 mod q
+  const uint32_t* T = nullptr; // [prime][TS]: 2^(28 i) 2^32 mod q (VALU lift)
   int TS = 0;
   const PrimeC* pc = nullptr;
+  // matrix-core lift: A fragments [tile of 8 primes][k-block of 8 limbs][lane] and
+  // per-prime offsets [C0 2^32]_(q_p) + 2^20 q_p (null: only the VALU lift)
+  const v4i_t* A = nullptr;
+  const uint64_t* off = nullptr;
+  int nkb = 0, ntiles = 0;
 };
 
 struct PointwiseArgs {
@@ -53,27 +58,24 @@ struct PointwiseArgs {
   const PrimeC* pc = nullptr;
 };
 
-struct GarnerArgs {
-  const uint32_t* res = nullptr; // poly z: res + (z / per_group) * gstride + (z % per_group) * pstride
+// CRT reconstruction of `npoly` polynomials from canonical residues (the inverse
+// NTT's output with the CRT factor c_k folded in).
+struct CrtArgs {
+  const uint32_t* res = nullptr; // poly z: res + (z / per_group) * gstride + (z % per_group) * pstride, [K][N]
   int per_group = 0;
   long long gstride = 0, pstride = 0;
   uint32_t* out = nullptr;  // poly z: out + z * ostride, uint32[Lout][N]
   long long ostride = 0;
   int N = 0, K = 0, outbits = 0, Lout = 0;
+  int ntiles = 0;           // tiles of 8 output limbs
+  const v4i_t* A = nullptr; // [tile][k-block][lane]: the 16 MFMA A bytes of each lane
   const PrimeC* pc = nullptr;
-  const uint32_t* Gt = nullptr; // digit block b: 16-word rows j of [M_j I_k 2^32]_(q_k), k = 16b..16b+15,
-  int GS = 0;          //   at word 256 b (b + 1) / 2 (GS unused)
-  const uint32_t* Ow = nullptr; // [k] = [2^e I_k]_(q_k)
-  const uint32_t* Ct = nullptr;  // column block c: 16-word rows k of radix-2^26 digits 16c.. of M_k,
-  int CS = 0;              //   at word c CS
-  const int* kstart = nullptr; // [m] = min k with M_k >= 2^(26 m)
-  const int* mbits = nullptr; // host: bit length of M_k (work accounting only)
-  uint32_t* dig = nullptr; // digit scratch: wave w's region at dig + w * garner_wave_words(K)
+  const uint32_t* d = nullptr;    // [k] = [2^e c_k]_(q_k)
+  const double* invq = nullptr;   // [k] = 1 / q_k
+  const uint32_t* mneg = nullptr; // [l < 8 ntiles] limbs of (-M) mod 2^(32 Lout), zero beyond Lout
+  const uint32_t* eneg = nullptr; // [l < 8 ntiles] limbs of (-2^e) mod 2^(32 Lout), zero beyond Lout
+  int npoly = 0;                  // set by launch_crt
 };
-
-// Words of digit scratch per wave of 64 coefficients: the digits padded to the
-// 16-digit block plus one pair read ahead.
-__host__ __device__ inline long long garner_wave_words(int K) { return (long long)((K + 15) / 16 * 16 + 2) * 64; }
 
 struct ComposeArgs {
   const uint32_t* k = nullptr; // poly z (= 2 c + i): k + z * kstride, uint32[LK][N]
@@ -130,7 +132,7 @@ long long kernel_launch_count();      // kernels launched by this host thread so
 // Launch parameters chosen by the autotuner (defaults: 16 primes per lift thread,
 // NTT column pass of ceil(logN / 2) stages).
 struct Tuning {
-  int lift_primes = 16;  // 8, 16 or 32
+  int lift_primes = 0;  // 0: matrix-core lift; 8, 16 or 32: VALU lift with that many primes per thread
   int ntt_cols_first = 1;  // 1: column pass takes ceil(logN/2) stages; 0: floor
 };
 
@@ -140,7 +142,7 @@ hipError_t launch_lift(const LiftArgs& a, int npoly, hipStream_t s, const Tuning
 hipError_t launch_tensor_pointwise(const PointwiseArgs& a, int cnum, hipStream_t s);
 hipError_t launch_relin_pointwise(const PointwiseArgs& a, int cnum, hipStream_t s);
 hipError_t launch_ring_pointwise(const PointwiseArgs& a, int cnum, hipStream_t s);
-hipError_t launch_garner(const GarnerArgs& a, int npoly, hipStream_t s);
+hipError_t launch_crt(CrtArgs a, int npoly, hipStream_t s);
 hipError_t launch_compose(const ComposeArgs& a, int cnum, hipStream_t s);
 hipError_t launch_rescale(const RescaleArgs& a, int cnum, hipStream_t s);
 hipError_t launch_small_to_limbs(const int8_t* v, uint32_t* out, int N, int L, uint32_t topmask, hipStream_t s);

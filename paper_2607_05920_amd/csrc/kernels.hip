@@ -1,6 +1,7 @@
 // gfx950 kernels for the non-RNS HE-mult pipeline:
 //   lift (limbs -> residues), negacyclic NTT / iNTT, pointwise products,
-//   Garner reconstruction (residues -> limbs), relinearization compose, rescale.
+//   CRT reconstruction (residues -> limbs, on the i8 matrix cores), relinearization
+//   compose, rescale.
 #include <algorithm>
 #include <utility>
 
@@ -8,13 +9,16 @@
 
 namespace fhe {
 
+typedef v4i_t v4i;
+typedef int v16i __attribute__((ext_vector_type(16)));
+
 static thread_local EventRecorder* g_rec = nullptr;
 static thread_local long long g_launches = 0;
 void set_recorder(EventRecorder* r) { g_rec = r; }
 long long kernel_launch_count() { return g_launches; }
 
 // Brackets one kernel launch with the recorder's events; `work` is the kernel's
-// algorithmic 32x32-bit word-product count (0 when not tracked).
+// algorithmic work: 32x32-bit word products for the lift, HBM bytes otherwise.
 struct Bracket {
   int kid;
   hipStream_t s;
@@ -214,8 +218,9 @@ static hipError_t ntt_pass(const NttArgs& a, int ntr, hipStream_t st) {
   const int kx = (a.K + 7) / 8;  // primes per XCD (the largest share)
   dim3 grid(8 * kx * (ntr / a.K) * nwg);
   // algorithmic work: (N / 2) S butterflies per transform, one constant product each
+  // algorithmic HBM bytes: every element of every transform read and written once
   Bracket br(INV ? (ROWS ? KID_NTT_INV_ROWS : KID_NTT_INV_COLS) : (ROWS ? KID_NTT_FWD_ROWS : KID_NTT_FWD_COLS), st,
-             (double)ntr * (double)((1 << a.logN) / 2) * S);
+             8.0 * ntr * (double)(1 << a.logN));
   hipLaunchKernelGGL((ntt_pass_kernel<S, INV, ROWS>), grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
@@ -318,12 +323,86 @@ static void lift_launch(const LiftArgs& b, int npoly, hipStream_t st) {
   hipLaunchKernelGGL((lift_kernel<PB>), grid, dim3(256), 0, st, b);
 }
 
+// The same projection on the i8 matrix cores.  A limb's four bytes minus 128 are
+// signed digits s_(i,a), so A = sum_(i,a) s_(i,a) 2^(32 i + 8 a) + C0 with the
+// constant C0 = 0x80808080 sum_(i<L) 2^(32 i): a limb word XOR 0x80808080 is its
+// four digits as int8 bytes.  The digit index runs along the contraction, against
+// the constants T_(i,a),p = [2^(32 i + 8 a) 2^32]_(q_p) split into four balanced
+// byte planes b (rows of the tile: row = 8 b + p', prime 8 t + p').  The VALU adds
+// the planes (sum_b 2^(8 b) C_b, |.| < 2^49), the per-prime constant
+// [C0 2^32]_(q_p) + 2^20 q_p (makes it positive), and Montgomery-reduces.
+// One wave per 32 coefficients; lane (c, h) supplies limbs 8 kb + 4 h + r (r < 4)
+// of coefficient c as B register r of k-block kb.
+template <int MAXKB>
+__global__ __launch_bounds__(256) void lift_mfma_kernel(LiftArgs a) {
+  const int lane = threadIdx.x & 63, c = lane & 31, h = lane >> 5;
+  const long long unit = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int groups = a.N >> 5;
+  if (unit >= (long long)a.npoly * groups) return;
+  const int z = (int)(unit / groups);
+  const int j = (int)(unit % groups) * 32 + c;
+  const uint32_t* src = (a.in_ptrs ? a.in_ptrs[z] : a.limbs + (long long)z * a.in_stride) + j;
+  v4i B[MAXKB];
+#pragma unroll
+  for (int kb = 0; kb < MAXKB; ++kb) {
+    if (kb < a.nkb) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int li = 8 * kb + 4 * h + r;
+        B[kb][r] = (int)((li < a.L ? src[(long long)li * a.N] : 0x80808080u) ^ 0x80808080u);
+      }
+    }
+  }
+  uint32_t* dst = a.res + (long long)z * a.out_stride + j;
+  for (int t = 0; t < a.ntiles; ++t) {
+    v16i acc = {};
+    const v4i* Ap = a.A + (long long)t * a.nkb * 64 + lane;
+#pragma unroll
+    for (int kb = 0; kb < MAXKB; ++kb)
+      if (kb < a.nkb) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(Ap[kb * 64], B[kb], acc, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int p = 8 * t + 4 * h + i;
+      if (p < a.K) {
+        const int64_t v = (int64_t)acc[i] + (int64_t)acc[4 + i] * 256 + (int64_t)acc[8 + i] * 65536 +
+                          (int64_t)acc[12 + i] * 16777216;
+        const PrimeC pc = a.pc[p];
+        const uint64_t u = (uint64_t)(v + (int64_t)a.off[p]);
+        dst[(long long)p * a.N] = csub(redc_lazy(u, pc.q, pc.qneg), pc.q);
+      }
+    }
+  }
+}
+
+template <int MAXKB>
+static void lift_mfma_launch(const LiftArgs& b, hipStream_t st) {
+  const long long units = (long long)b.npoly * (b.N >> 5);
+  hipLaunchKernelGGL((lift_mfma_kernel<MAXKB>), dim3((unsigned)((units + 3) / 4)), dim3(256), 0, st, b);
+}
+
 hipError_t launch_lift(const LiftArgs& a, int npoly, hipStream_t st, const Tuning& t) {
   if (npoly <= 0) return hipSuccess;
   LiftArgs b = a;
   b.npoly = npoly;
   // algorithmic work: L limb-constant products per (coefficient, prime)
   Bracket br(KID_LIFT, st, (double)npoly * a.N * a.K * a.L);
+  if (t.lift_primes == 0 && a.A) {
+    if (b.nkb <= 1)
+      lift_mfma_launch<1>(b, st);
+    else if (b.nkb <= 2)
+      lift_mfma_launch<2>(b, st);
+    else if (b.nkb <= 4)
+      lift_mfma_launch<4>(b, st);
+    else if (b.nkb <= 8)
+      lift_mfma_launch<8>(b, st);
+    else if (b.nkb <= 16)
+      lift_mfma_launch<16>(b, st);
+    else if (b.nkb <= 32)
+      lift_mfma_launch<32>(b, st);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   switch (t.lift_primes) {
     case 8: lift_launch<8>(b, npoly, st); break;
     case 32: lift_launch<32>(b, npoly, st); break;
@@ -385,262 +464,202 @@ __global__ __launch_bounds__(256) void ring_pointwise_kernel(PointwiseArgs a) {
 
 hipError_t launch_tensor_pointwise(const PointwiseArgs& a, int cnum, hipStream_t st) {
   dim3 grid((a.N + 255) / 256, a.K, cnum);
-  Bracket br(KID_POINTWISE, st, 4.0 * cnum * a.K * a.N);
+  Bracket br(KID_POINTWISE, st, 28.0 * cnum * a.K * a.N);  // bytes: 4 residue rows in, 3 out
   hipLaunchKernelGGL(tensor_pointwise_kernel, grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_relin_pointwise(const PointwiseArgs& a, int cnum, hipStream_t st) {
   dim3 grid((a.N + 255) / 256, a.K, cnum);
-  Bracket br(KID_POINTWISE, st, 2.0 * cnum * a.K * a.N);
+  Bracket br(KID_POINTWISE, st, 20.0 * cnum * a.K * a.N);  // bytes: d2 and the key's 2 rows in, 2 out
   hipLaunchKernelGGL(relin_pointwise_kernel, grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_ring_pointwise(const PointwiseArgs& a, int cnum, hipStream_t st) {
   dim3 grid((a.N + 255) / 256, a.K, cnum);
-  Bracket br(KID_POINTWISE, st, 1.0 * cnum * a.K * a.N);
+  Bracket br(KID_POINTWISE, st, 12.0 * cnum * a.K * a.N);  // bytes: 2 rows in, 1 out
   hipLaunchKernelGGL(ring_pointwise_kernel, grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
-// ============================================================================ Garner
+// ============================================================================ CRT reconstruction
+// Residues -> limbs (the reconstruction step of Section 5.1 / Eq. garner_mrc, here
+// in its direct CRT form).  With M = q_0 ... q_(K-1), c_k = [(M/q_k)^-1]_(q_k) and
+// the inverse NTT's final factor including c_k, a transform output x_k
+// gives y_k = [x_k + d_k]_(q_k), d_k = [2^e c_k]_(q_k), the CRT coordinates of
+// Y = X + 2^e in [0, 2^(e+1)) (X the signed exact product, |X| < 2^e).  Then
+//   Y = sum_k y_k (M/q_k) - alpha M,   alpha = floor(sum_k y_k / q_k),
+// and the output is X mod 2^outbits = (Y - 2^e) mod 2^outbits.  The prime count
+// leaves Y / M < 2^-16, so alpha is the floor of a sum of fractions evaluated in
+// double precision (error < 2^-37, far inside the margin).
 //
-// RNS -> limbs (Section 5.1, "RNS-to-Limb Reconstruction"; Section 2.5,
-// Eq. garner_mrc).  The integer recovered is Y = X + 2^e, where X is the signed
-// exact coefficient and 2^e exceeds |X|; Y lies in [0, M), so no sign test is
-// needed, and Y = X mod 2^outbits because e >= outbits.
+// The column sums sum_k y_k V_kl, V_kl = limb l of (M/q_k) mod 2^(32 Lout), are a
+// dense integer contraction [coefficients x K] x [K x Lout] and run on the i8
+// matrix cores: y_k and V_kl are split into 4 balanced base-256 digits each
+// (digits in [-128, 127], limbs of V taken in [-0x80808080, 0x7F7F7F7F]), the 16
+// digit-plane products accumulate exactly in int32 (|sum| <= K 2^14), and the VALU
+// recombines sum_(a,b) 2^(8(a+b)) C_ab per limb, adds alpha [-M] + [-2^e], and
+// propagates the carries.
 //
-// Mixed-radix digits: with M_k = prod_(i<k) q_i and I_k = [M_k^-1]_(q_k),
-//   v_k = [ x_k I_k + [2^e I_k] - sum_(j<k) v_j [M_j I_k] ]_(q_k),
-// the same digits as Garner's nested recurrence.  The factor I_k of x_k is
-// applied by the inverse NTT's final multiply.  The sum is a dot product of
-// 30-bit values: lazily accumulated in 64 bits (folded every 11 terms) against
-// constants in Montgomery form, reduced once per digit.
-//
-// One wave handles 64 coefficients (one per lane).  Digits are kept in LDS
-// ([k][lane]); digits are finalized in blocks of 16: the block's 16 sums first
-// take every earlier digit (one LDS read feeds 16 multiply-adds), then the block
-// is finished sequentially in registers.
-//
-// Limbs: Y = sum_k v_k M_k, taken mod 2^(26 D) as column sums over radix-2^26
-// digits of M_k (each product < 2^56, so a column of up to 255 terms fits 64 bits),
-// then carried and re-packed into 32-bit limbs.
+// One wave per 32 coefficients.  MFMA v_mfma_i32_32x32x32_i8: lane (c, h) = (lane
+// mod 32, lane / 32) supplies B bytes k = 32 kb + 16 h + i (i < 16) of coefficient
+// column c, and A bytes of row c for the same k; its accumulator holds rows
+// 8 j + 4 h + i.  Rows of a tile are (digit plane b of V, limb 8 t + l'), row =
+// 8 b + l', so lane half h ends with all four planes of limbs 8 t + 4 h + i.
 
-// Tables are read through the constant address space so the compiler may treat
-// them as invariant and keep wave-uniform loads scalar.
-typedef __attribute__((address_space(4))) const uint32_t cu32;
-typedef __attribute__((address_space(4))) const PrimeC cprime;
 
-#define FHE_FENCE() __builtin_amdgcn_sched_barrier(0)
-
-__device__ __forceinline__ PrimeC load_prime(cprime* p) {
-  PrimeC r;
-  r.q = p->q;
-  r.qneg = p->qneg;
-  r.c32 = p->c32;
-  r.two_q = p->two_q;
-  return r;
+// 4 x 32-bit words -> their byte plane a (a < 4) as 4 packed bytes, for all planes.
+__device__ __forceinline__ void byte_planes(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, uint32_t& p0,
+                                            uint32_t& p1, uint32_t& p2, uint32_t& p3) {
+  // v_perm_b32: result byte i = byte sel_i of {src0 (bytes 4..7), src1 (bytes 0..3)}
+  const uint32_t lo01 = __builtin_amdgcn_perm(w1, w0, 0x05010400u);  // w0.0 w1.0 w0.1 w1.1
+  const uint32_t hi01 = __builtin_amdgcn_perm(w1, w0, 0x07030602u);  // w0.2 w1.2 w0.3 w1.3
+  const uint32_t lo23 = __builtin_amdgcn_perm(w3, w2, 0x05010400u);
+  const uint32_t hi23 = __builtin_amdgcn_perm(w3, w2, 0x07030602u);
+  p0 = __builtin_amdgcn_perm(lo23, lo01, 0x05040100u);  // w0.0 w1.0 w2.0 w3.0
+  p1 = __builtin_amdgcn_perm(lo23, lo01, 0x07060302u);
+  p2 = __builtin_amdgcn_perm(hi23, hi01, 0x05040100u);
+  p3 = __builtin_amdgcn_perm(hi23, hi01, 0x07060302u);
 }
 
-struct Row16 {
-  uint32_t c[16];
-};
-
-__device__ __forceinline__ Row16 load_row(cu32* p) {
-  Row16 r;
+// Adds a signed carry to 4 unsigned limbs; returns the carry out of the top limb.
+__device__ __forceinline__ int64_t add_carry4(uint32_t (&o)[4], int64_t cin) {
 #pragma unroll
-  for (int u = 0; u < 16; ++u) r.c[u] = p[u];
-  return r;
-}
-
-// Digits of the wave's 64 coefficients, two per lane word pair: digit k of lane l
-// at vd[(k / 2) * 128 + 2 l + (k % 2)], so one ds_read_b64 returns digits 2p, 2p+1.
-__device__ __forceinline__ uint2 load_pair(const uint32_t* vd, int pair, int lane) {
-  return *(const uint2*)(vd + pair * 128 + 2 * lane);
-}
-
-// Copies a wave-uniform value into a vector register (keeps it out of the scalar
-// register budget, which the pipelined constant rows need).
-__device__ __forceinline__ uint32_t to_vgpr(uint32_t x) {
-  uint32_t r;
-  asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
-  return r;
-}
-
-// acc[u] += sum over digits k in [2 p0, 2 p1) of v_k T[k][u], T's 16-word rows stored
-// contiguously from `t`.  Rows are consumed in turn from two scalar buffers: the
-// first product of a row waits for it, the next row (the following 64 bytes) is
-// requested right after, and the row's other 15 products cover that latency.
-// (Scalar loads complete out of order, so a wait placed after the request would
-// also wait for it.)  Digit pairs come from LDS one pair per two rows.  With FOLD every
-// accumulator is folded (hi 2^32 + lo -> hi c32[u] + lo) after every 10 products,
-// so it stays below 2^64; the last action is then a fold.
-template <bool FOLD>
-__device__ __forceinline__ void mac_rows(uint64_t (&acc)[16], const uint32_t* vd, int lane, cu32* t, int p0,
-                                         int p1, const uint32_t (&c32)[16]) {
-  if (p1 <= p0) return;
-  const int k1 = 2 * p1;
-  int k = 2 * p0;
-  cu32* tp = t + 16 * k;
-  const uint32_t* vp = vd + p0 * 128 + 2 * lane;
-  Row16 ra = load_row(tp), rb;
-  uint2 d = *(const uint2*)vp;
-  for (; k + 10 <= k1; k += 10, tp += 160, vp += 640) {
-    // pair read after the last row of this iteration: the next one, or (at the end)
-    // the last pair again, so that no pair beyond p1 is read
-    const int last = (k + 10 < k1) ? 5 : 4;
-#pragma unroll
-    for (int q = 0; q < 10; ++q) {
-      const uint32_t x = (q % 2 == 0) ? d.x : d.y;
-      Row16& cur = (q % 2 == 0) ? ra : rb;
-      Row16& nxt = (q % 2 == 0) ? rb : ra;
-      acc[0] = mad64(x, cur.c[0], acc[0]);
-      FHE_FENCE();
-      nxt = load_row(tp + 16 * (q + 1));  // the row after the last one reads padding
-      FHE_FENCE();
-#pragma unroll
-      for (int u = 1; u < 16; ++u) acc[u] = mad64(x, cur.c[u], acc[u]);
-      if (q % 2 == 1) d = *(const uint2*)(vp + ((q < 9 ? (q + 1) / 2 : last)) * 128);
-      FHE_FENCE();
-    }
-    if (FOLD) {
-#pragma unroll
-      for (int u = 0; u < 16; ++u) acc[u] = fold64(acc[u], c32[u]);
-    }
+  for (int i = 0; i < 4; ++i) {
+    const int64_t t = (int64_t)o[i] + cin;
+    o[i] = (uint32_t)t;
+    cin = t >> 32;
   }
-  // remainder: fewer than 10 rows (an even number)
-  for (; k < k1; k += 2, tp += 32, vp += 128) {
-    const uint2 dd = *(const uint2*)vp;
-    const Row16 r0 = load_row(tp), r1 = load_row(tp + 16);
-#pragma unroll
-    for (int u = 0; u < 16; ++u) acc[u] = mad64(dd.x, r0.c[u], acc[u]);
-#pragma unroll
-    for (int u = 0; u < 16; ++u) acc[u] = mad64(dd.y, r1.c[u], acc[u]);
-  }
-  if (FOLD) {
-#pragma unroll
-    for (int u = 0; u < 16; ++u) acc[u] = fold64(acc[u], c32[u]);
-  }
+  return cin;
 }
 
-__global__ __launch_bounds__(64) void garner_kernel(GarnerArgs a) {
-  // This wave's digits, in a private scratch region (pair layout of load_pair).  Each
-  // digit is written once, after which this wave alone reads it; stores complete
-  // (s_waitcnt) before any read of the same block, and no line of a block is read
-  // before the block is written, so no stale line can sit in the vector L1.
-  uint32_t* vd = a.dig + (long long)(blockIdx.y * gridDim.x + blockIdx.x) * garner_wave_words(a.K);
-  constexpr int B = kGarnerBlock;   // 16: digits finalized per block
-  const int lane = threadIdx.x;
-  const int jc = blockIdx.x * 64 + lane;
-  const int z = blockIdx.y;
-  const bool active = jc < a.N;
-  const int jcc = active ? jc : 0;
-  const uint32_t* in = a.res + (long long)(z / a.per_group) * a.gstride +
-                       (long long)(z % a.per_group) * a.pstride + jcc;
-  const int K = a.K;
-  cu32* Gt = (cu32*)a.Gt;
-  cu32* Ow = (cu32*)a.Ow;
-  cprime* pcs = (cprime*)a.pc;
+template <int NKB>
+__global__ __launch_bounds__(256) void crt_kernel(CrtArgs a) {
+  __shared__ uint32_t s_q[32 * NKB], s_d[32 * NKB];
+  __shared__ double s_iq[32 * NKB];
+  for (int k = threadIdx.x; k < 32 * NKB; k += 256) {
+    const bool in = k < a.K;
+    s_q[k] = in ? a.pc[k].q : 1u;
+    s_d[k] = in ? a.d[k] : 0u;
+    s_iq[k] = in ? a.invq[k] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, c = lane & 31, h = lane >> 5;
+  const long long unit = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int groups = a.N >> 5;
+  if (unit >= (long long)a.npoly * groups) return;
+  const int z = (int)(unit / groups);
+  const int j = (int)(unit % groups) * 32 + c;
+  const uint32_t* x = a.res + (long long)(z / a.per_group) * a.gstride + (long long)(z % a.per_group) * a.pstride + j;
 
-  for (int kb = 0; kb < K; kb += B) {
-    // residues of this block (rows past K are valid memory; those digits are zeroed)
-    uint32_t xin[B];
+  // phase 1: y_k, the partial sum of y_k / q_k, and the four digit planes per k-block
+  v4i B[NKB][4];
+  double frac = 0.0;
 #pragma unroll
-    for (int u = 0; u < B; ++u) xin[u] = in[(long long)min(kb + u, K - 1) * a.N];
-    uint32_t c32[B];
+  for (int kb = 0; kb < NKB; ++kb) {
+    uint32_t s[16];
 #pragma unroll
-    for (int u = 0; u < B; ++u) c32[u] = to_vgpr(pcs[kb + u].c32);
-    uint64_t acc[B];
-#pragma unroll
-    for (int u = 0; u < B; ++u) acc[u] = 0;
-    // all earlier digits, pairs 0 .. kb/2 - 1 (accumulators folded at least every 10 products)
-    cu32* gb = Gt + 256 * (kb / B) * (kb / B + 1) / 2;  // this digit block's rows
-    mac_rows<true>(acc, vd, lane, gb, 0, kb >> 1, c32);
-    // this block's digits in order (branch-free; digits k >= K are zero)
-#pragma unroll
-    for (int u = 0; u < B; ++u) {
-      const int k = kb + u;
-      const PrimeC pk = load_prime(pcs + k);
-      const uint32_t sred = reduce64_mont(acc[u], pk);
-      const uint32_t xk = add_mod(xin[u], Ow[k], pk.q);
-      const uint32_t vk = k < K ? sub_mod(xk, sred, pk.q) : 0u;
-      vd[(k >> 1) * 128 + 2 * lane + (k & 1)] = vk;
-      cu32* g = gb + 16 * k;
-#pragma unroll
-      for (int w = u + 1; w < B; ++w) acc[w] = mad64(vk, g[w], acc[w]);
-      if (u == 10) {  // the in-block sums hold at most 11 products before this fold
-#pragma unroll
-        for (int w = 11; w < B; ++w) acc[w] = fold64(acc[w], c32[w]);
+    for (int i = 0; i < 16; ++i) {
+      const int k = 32 * kb + 16 * h + i;
+      uint32_t y = 0;
+      if (k < a.K) {
+        const uint32_t q = s_q[k];
+        y = x[(long long)k * a.N] + s_d[k];
+        y = min(y, y - q);
+        frac = __builtin_fma((double)y, s_iq[k], frac);
       }
+      s[i] = (y + 0x80808080u) ^ 0x80808080u;  // balanced base-256 digits, as int8 bytes
     }
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this block's digit stores are done
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      uint32_t p0, p1, p2, p3;
+      byte_planes(s[4 * r], s[4 * r + 1], s[4 * r + 2], s[4 * r + 3], p0, p1, p2, p3);
+      B[kb][0][r] = (int)p0;
+      B[kb][1][r] = (int)p1;
+      B[kb][2][r] = (int)p2;
+      B[kb][3][r] = (int)p3;
+    }
   }
+  frac += __shfl_xor(frac, 32);
+  const uint32_t alpha = (uint32_t)(frac + 0x1p-20);
 
-  // Column sums over radix-2^26 digits of M_k, carried and packed into limbs.
-  const int D = (a.outbits + kHornerDigitBits - 1) / kHornerDigitBits;
-  const int npair = (K + 1) >> 1;  // a digit K (K odd) is stored as zero
-  uint32_t* out = a.out + (long long)z * a.ostride + jcc;
-  cu32* Ct = (cu32*)a.Ct;
-  uint64_t carry = 0, bitbuf = 0;
-  int nbits = 0, li = 0;
+  // phase 2: per tile of 8 limbs, the digit-plane products, recombination, carries
+  uint32_t* o = a.out + (long long)z * a.ostride + j;
   const int topbits = a.outbits - 32 * (a.Lout - 1);
-  const uint32_t topmask = topbits >= 32 ? 0xFFFFFFFFu : ((1u << topbits) - 1u);
-  constexpr int BC = kHornerBlock;
-  static_assert(BC == 16, "a column block is one constant row");
-  const uint32_t nofold[16] = {};
-  for (int m0 = 0; m0 < D; m0 += BC) {
-    uint64_t col[BC];
+  int64_t cin = 0;  // carry into the tile (valid in lane half 0)
+  for (int t = 0; t < a.ntiles; ++t) {
+    v16i acc0 = {}, acc1 = {}, acc2 = {}, acc3 = {};
+    const v4i* Ap = a.A + ((long long)t * NKB) * 64 + lane;
 #pragma unroll
-    for (int m = 0; m < BC; ++m) col[m] = 0;
-    // digits k < kstart[m0] have no radix-2^26 digit at or above m0
-    const int ps = ((__attribute__((address_space(4))) const int*)a.kstart)[m0] >> 1;
-    mac_rows<false>(col, vd, lane, Ct + (long long)(m0 / BC) * a.CS, ps, npair, nofold);
+    for (int kb = 0; kb < NKB; ++kb) {
+      const v4i A = Ap[kb * 64];
+      acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B[kb][0], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B[kb][1], acc1, 0, 0, 0);
+      acc2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B[kb][2], acc2, 0, 0, 0);
+      acc3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B[kb][3], acc3, 0, 0, 0);
+    }
+    uint32_t ol[4];
+    int64_t carry = 0;
 #pragma unroll
-    for (int m = 0; m < BC; ++m) {
-      if (m0 + m < D) {
-        const uint64_t t = col[m] + carry;
-        carry = t >> kHornerDigitBits;
-        bitbuf |= (t & ((1u << kHornerDigitBits) - 1u)) << nbits;
-        nbits += kHornerDigitBits;
-        if (nbits >= 32) {
-          if (li < a.Lout && active) {
-            uint32_t wv = (uint32_t)bitbuf;
-            if (li == a.Lout - 1) wv &= topmask;
-            out[(long long)li * a.N] = wv;
-          }
-          ++li;
-          bitbuf >>= 32;
-          nbits -= 32;
-        }
+    for (int i = 0; i < 4; ++i) {
+      const int limb = 8 * t + 4 * h + i;
+      // C_ab = acc_a[4 b + i]: y plane a times V plane b
+      const int64_t s0 = acc0[i];
+      const int64_t s1 = (int64_t)acc0[4 + i] + acc1[i];
+      const int64_t s2 = (int64_t)acc0[8 + i] + acc1[4 + i] + acc2[i];
+      const int64_t s3 = (int64_t)acc0[12 + i] + acc1[8 + i] + acc2[4 + i] + acc3[i];
+      const int64_t s4 = (int64_t)acc1[12 + i] + acc2[8 + i] + acc3[4 + i];
+      const int64_t s5 = (int64_t)acc2[12 + i] + acc3[8 + i];
+      const int64_t s6 = acc3[12 + i];
+      const int64_t lo = s0 + s1 * 256 + s2 * 65536 + s3 * 16777216 + (int64_t)((uint64_t)alpha * a.mneg[limb]) +
+                         (int64_t)a.eneg[limb];
+      const int64_t hi = s4 + s5 * 256 + s6 * 65536;
+      const int64_t tt = lo + carry;
+      ol[i] = (uint32_t)tt;
+      carry = (tt >> 32) + hi;
+    }
+    // carry across the lane halves: half 0 takes the carry into the tile, passes its
+    // carry out to half 1, whose carry out enters the next tile
+    carry += add_carry4(ol, h == 0 ? cin : 0);
+    const int64_t mid = __shfl_xor(carry, 32);
+    carry += add_carry4(ol, h == 1 ? mid : 0);
+    cin = __shfl_xor(carry, 32);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int limb = 8 * t + 4 * h + i;
+      if (limb < a.Lout) {
+        uint32_t w = ol[i];
+        if (limb == a.Lout - 1 && topbits < 32) w &= (1u << topbits) - 1u;
+        o[(long long)limb * a.N] = w;
       }
     }
   }
-  if (li < a.Lout && active) {
-    uint32_t wv = (uint32_t)bitbuf;
-    if (li == a.Lout - 1) wv &= topmask;
-    out[(long long)li * a.N] = wv;
+}
+
+template <int NKB>
+static void crt_launch(const CrtArgs& a, hipStream_t st) {
+  const long long units = (long long)a.npoly * (a.N >> 5);
+  hipLaunchKernelGGL(crt_kernel<NKB>, dim3((unsigned)((units + 3) / 4)), dim3(256), 0, st, a);
+}
+
+hipError_t launch_crt(CrtArgs a, int npoly, hipStream_t st) {
+  a.npoly = npoly;
+  if (npoly == 0) return hipSuccess;
+  const int nkb = (a.K + 31) / 32;
+  // algorithmic HBM bytes: K residues read and Lout limbs written per coefficient
+  Bracket br(KID_GARNER, st, 4.0 * npoly * a.N * (double)(a.K + a.Lout));
+  switch (nkb) {
+    case 1: crt_launch<1>(a, st); break;
+    case 2: crt_launch<2>(a, st); break;
+    case 3: crt_launch<3>(a, st); break;
+    case 4: crt_launch<4>(a, st); break;
+    case 5: crt_launch<5>(a, st); break;
+    case 6: crt_launch<6>(a, st); break;
+    case 7: crt_launch<7>(a, st); break;
+    case 8: crt_launch<8>(a, st); break;
+    default: return hipErrorInvalidValue;
   }
-}
-
-// Word products Garner's method needs per coefficient: K(K-1)/2 for the
-// mixed-radix digits, plus one per limb of each M_k (up to Lout limbs) for the
-// limb-form sum.  mbits[k] is the bit length of M_k.
-static double garner_products(int K, int Lout, const int* mbits) {
-  double w = 0.5 * K * (K - 1);
-  for (int k = 0; k < K; ++k) w += std::min(Lout, (mbits[k] + 31) / 32);
-  return w;
-}
-
-hipError_t launch_garner(const GarnerArgs& a, int npoly, hipStream_t st) {
-  if (npoly <= 0) return hipSuccess;
-  dim3 grid((a.N + 63) / 64, npoly);
-  // digits padded to the 16-digit block (the last block writes through k < K + 16),
-  // plus one pair read ahead by the last prefetch
-  const size_t lds = (size_t)((a.K + kGarnerBlock - 1) / kGarnerBlock * kGarnerBlock + 2) * 64 * sizeof(uint32_t);
-  Bracket br(KID_GARNER, st, (double)npoly * a.N * garner_products(a.K, a.Lout, a.mbits));
-  (void)lds;
-  hipLaunchKernelGGL(garner_kernel, grid, dim3(64), 0, st, a);
   return hipGetLastError();
 }
 
@@ -730,14 +749,15 @@ __global__ __launch_bounds__(256) void rescale_kernel(RescaleArgs a) {
 
 hipError_t launch_compose(const ComposeArgs& a, int cnum, hipStream_t st) {
   dim3 grid((a.N + 255) / 256, 2 * cnum);
-  Bracket br(KID_COMPOSE, st, 0.0);
+  Bracket br(KID_COMPOSE, st, 8.0 * cnum * a.N * (double)(a.LK + 2 * a.L));  // bytes: k_i, d_i in, c_i out
   hipLaunchKernelGGL(compose_kernel, grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_rescale(const RescaleArgs& a, int cnum, hipStream_t st) {
   dim3 grid((a.N + 255) / 256, 2 * cnum);
-  Bracket br(KID_RESCALE, st, 0.0);
+  // bytes: L limbs in, L - bits/32 limbs out, per polynomial
+  Bracket br(KID_RESCALE, st, 8.0 * cnum * a.N * (double)(((a.logq + 31) >> 5) + ((a.logq - a.bits + 31) >> 5)));
   hipLaunchKernelGGL(rescale_kernel, grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }

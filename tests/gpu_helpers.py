@@ -49,3 +49,17 @@ def keys(rk, logN, logQ, logP, sch, t, h):
     a2 = ints(synth.uniform_limbs(rk, logQ + logP, N))
     evk = scheme.keygen_relin(s, a2, synth.dg(rk, N, 3.2), logQ, logP, sch, t)
     return s, pk, evk, limbs_of(evk.b, logQ + logP), limbs_of(evk.a, logQ + logP)
+
+
+def check(got, want, what: str = "values"):
+    """Element-by-element equality of two sequences, failing with the count and the
+    first mismatching positions (a plain `assert list == list` on 10^4 big integers
+    makes pytest build a quadratic diff that runs for minutes)."""
+    got, want = list(got), list(want)
+    if got == want:
+        return
+    if len(got) != len(want):
+        raise AssertionError(f"{what}: length {len(got)} != {len(want)}")
+    bad = [i for i, (a, b) in enumerate(zip(got, want)) if a != b]
+    first = ", ".join(f"[{i}] {str(got[i])[:24]} != {str(want[i])[:24]}" for i in bad[:4])
+    raise AssertionError(f"{what}: {len(bad)} of {len(want)} differ; first: {first}")

@@ -6,7 +6,7 @@ import pytest
 import paper_2607_05920_amd as fhe
 import synth
 from oracle import scheme
-from tests.gpu_helpers import dev, host, ints, oracle_ct, say
+from tests.gpu_helpers import check, dev, host, ints, oracle_ct, say
 
 pytestmark = pytest.mark.gpu
 
@@ -95,6 +95,6 @@ def test_batch_sampled_jobs_match_oracle(setup):
         want = scheme.mult_rescale(oracle_ct(*x, logN, logq, scheme.CKKS, 0), oracle_ct(*y, logN, logq, scheme.CKKS, 0),
                                    evk, 40)
         Lo = synth.nlimbs(logq - 40)
-        assert ints(host(jobs[i][7], (Lo, N))) == want.c0
-        assert ints(host(jobs[i][8], (Lo, N))) == want.c1
+        check(ints(host(jobs[i][7], (Lo, N))), want.c0, f"job {i} c0")
+        check(ints(host(jobs[i][8], (Lo, N))), want.c1, f"job {i} c1")
     plan.close()

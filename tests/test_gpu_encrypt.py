@@ -9,7 +9,7 @@ import paper_2607_05920_amd as fhe
 import synth
 from oracle import ntt as ontt
 from oracle import ring, scheme
-from tests.gpu_helpers import dev, host, ints, keys, limbs_of, say
+from tests.gpu_helpers import check, dev, host, ints, keys, limbs_of, say
 
 pytestmark = pytest.mark.gpu
 
@@ -57,21 +57,22 @@ def test_encrypt_decrypt_bit_exact(ctx, sch, t, logN, logQ, logq):
                 dev(limbs_of([x % Q for x in m], logq)), _small(v, np.int8), _small(e0, np.int32),
                 _small(e1, np.int32), c0, c1)
     torch.cuda.synchronize()
-    assert ints(host(c0, (L, N))) == want.c0 and ints(host(c1, (L, N))) == want.c1
+    check(ints(host(c0, (L, N))), want.c0, "c0")
+    check(ints(host(c1, (L, N))), want.c1, "c1")
     if sch == scheme.CKKS:
         ph = torch.empty(L * N, dtype=torch.int32, device="cuda")
         ctx.decrypt(fhe.CKKS, 0, 1, logN, logq, c0, c1, _small(s, np.int8), ph)
         torch.cuda.synchronize()
-        assert ints(host(ph, (L, N))) == scheme.phase(want, s)
+        check(ints(host(ph, (L, N))), scheme.phase(want, s), "phase")
     else:
         gamma = pow(2, -20, t)   # any invertible factor: decoding multiplies by its inverse
         out = torch.empty(N, dtype=torch.int32, device="cuda")
         ctx.decrypt(fhe.BGV, t, gamma, logN, logq, c0, c1, _small(s, np.int8), out)
         torch.cuda.synchronize()
-        assert fhe.to_host(out).tolist() == scheme.bgv_decode(scheme.decrypt(want, s), t, gamma)
+        check(fhe.to_host(out).tolist(), scheme.bgv_decode(scheme.decrypt(want, s), t, gamma), "message")
         ctx.decrypt(fhe.BGV, t, 1, logN, logq, c0, c1, _small(s, np.int8), out)
         torch.cuda.synchronize()
-        assert fhe.to_host(out).tolist() == m
+        check(fhe.to_host(out).tolist(), m, "message (gamma 1)")
 
 
 @pytest.mark.parametrize("sch,t,bits", [(scheme.CKKS, 0, 40), (scheme.BGV, 65537, 32)])
@@ -115,7 +116,7 @@ def test_round_trip_through_the_library(ctx, sch, t, bits):
         out = torch.empty(N, dtype=torch.int32, device="cuda")
         ctx.decrypt(fhe.BGV, t, pow(2, -bits, t), logN, logq - bits, o0, o1, sd, out)
         torch.cuda.synchronize()
-        assert fhe.to_host(out).tolist() == ring.ring_mul(mi[0], mi[1], t)
+        check(fhe.to_host(out).tolist(), ring.ring_mul(mi[0], mi[1], t), "m1 m2")
     evk.close()
 
 
@@ -137,7 +138,7 @@ def test_ntt_natural_order_prime_offset(ctx, logN, prime0, nprimes, count):
         for p in range(nprimes):
             q, psi_max = ctx.prime_info(prime0 + p)
             psi = pow(psi_max, (1 << 16) // N, q)
-            assert [int(x) for x in fwd[c, p]] == ontt.ntt_fast([int(x) for x in data[c, p]], q, psi)
+            check([int(x) for x in fwd[c, p]], ontt.ntt_fast([int(x) for x in data[c, p]], q, psi), f"ntt {c} {p}")
     ctx.ntt(logN, nprimes, t, count=count, inverse=True, prime0=prime0)
     torch.cuda.synchronize()
     assert np.array_equal(host(t, (count, nprimes, N)), data)

@@ -11,7 +11,7 @@ import paper_2607_05920_amd as fhe
 import synth
 from oracle import ntt as ontt
 from oracle import ring, scheme
-from tests.gpu_helpers import dev, host, ints, keys, limbs_of, oracle_ct, random_ct, say
+from tests.gpu_helpers import check, dev, host, ints, keys, limbs_of, oracle_ct, random_ct, say
 
 pytestmark = pytest.mark.gpu
 
@@ -35,14 +35,15 @@ def test_prime_table(ctx):
         assert q < prev and q > 1 << 29 and q % (1 << 17) == 1 and ontt.is_prime(q)
         assert pow(psi, 1 << 16, q) == q - 1
         prev = q
-    # K rule: smallest K with prod q_i > 2^(e+1)
+    # K rule: smallest K with prod q_i >= 2^(e + 1 + 16) (|X| < 2^e recovered, and the
+    # CRT quotient of X + 2^e kept exact by a 16-bit margin)
     for logN, a, b, terms in ((10, 120, 120, 1), (14, 438, 438, 2), (16, 1555, 3110, 1)):
         K = ctx.primes_needed(logN, a, b, terms)
         e = a + b + logN + (terms - 1).bit_length()
         M = 1
         for i in range(K):
             M *= ctx.prime_info(i)[0]
-        assert M > 1 << (e + 1) and M // ctx.prime_info(K - 1)[0] <= 1 << (e + 1)
+        assert M >= 1 << (e + 17) and M // ctx.prime_info(K - 1)[0] < 1 << (e + 17)
 
 
 @pytest.mark.parametrize("logN,bits,nprimes", [(10, 120, 9), (12, 1555, 40), (16, 438, 20), (16, 3110, 17)])
@@ -88,9 +89,9 @@ def test_ntt_forward_inverse(ctx, logN):
         psi = pow(psi_max, (1 << 16) // N, q)
         want = ontt.ntt_fast([int(v) for v in data[p]], q, psi)
         got = [int(fwd[p, perm[i]]) for i in range(N)]
-        assert got == want
+        check(got, want, f"ntt prime {p}")
         if logN == 10 and p == 0:
-            assert want == ontt.ntt_definition([int(v) for v in data[p]], q, psi)
+            check(want, ontt.ntt_definition([int(v) for v in data[p]], q, psi), "ntt definition")
     ctx.ntt(logN, nprimes, t, count=1, inverse=True, bitrev=True)
     assert np.array_equal(host(t, (nprimes, N)), data)
 
@@ -107,7 +108,7 @@ def test_ring_mul_cfg1_bit_exact(ctx):
     out = torch.empty(4 * N, dtype=torch.int32, device="cuda")
     ctx.ring_mul(logN, logq, dev(a), dev(b), out)
     want = ring.negacyclic_schoolbook(ints(a), ints(b), 1 << logq)
-    assert ints(host(out, (4, N))) == want
+    check(ints(host(out, (4, N))), want, "ring_mul cfg1")
 
 
 @pytest.mark.parametrize("logN,logq,cnum", [(10, 1, 1), (10, 33, 2), (11, 97, 3), (13, 250, 2)])
@@ -123,7 +124,7 @@ def test_ring_mul_ragged_batched_in_place(ctx, logN, logq, cnum):
     got = host(ta, (cnum, L, N))
     for c in range(cnum):
         want = ring.ring_mul(ints(a[c]), ints(b[c]), 1 << logq)
-        assert ints(got[c]) == want
+        check(ints(got[c]), want, f"ring_mul {c}")
 
 
 def _gpu_he_mult(ctx, evk_limbs, sch, t, logN, logq, logP, x, y, bits, fused=True):
@@ -168,10 +169,11 @@ def test_he_mult_small_encrypted(ctx, sch, t, bits):
     y = (limbs_of(cy.c0, logq), limbs_of(cy.c1, logq))
     g0, g1 = _gpu_he_mult(ctx, (eb, ea), sch, t, logN, logq, logP, x, y, bits)
     want = scheme.mult_rescale(cx, cy, evk, bits)
-    assert ints(g0) == want.c0 and ints(g1) == want.c1
+    check(ints(g0), want.c0, "c0")
+    check(ints(g1), want.c1, "c1")
     out = scheme.Ciphertext(ints(g0), ints(g1), logN, logq - bits, want.logp, sch, t, want.gamma)
     if sch == scheme.BGV:
-        assert scheme.bgv_decode(scheme.decrypt(out, s), t, out.gamma) == ring.negacyclic_schoolbook(m1, m2, t)
+        check(scheme.bgv_decode(scheme.decrypt(out, s), t, out.gamma), ring.negacyclic_schoolbook(m1, m2, t), "m1 m2")
     else:
         z = scheme.ckks_decode(scheme.decrypt(out, s), N // 2, out.logp)
         assert np.max(np.abs(z - z1 * z2)) <= 2.0 ** -20
@@ -198,10 +200,11 @@ def test_he_mult_cfg2_encrypted(ctx, sch, t, bits):
     y = (limbs_of(cy.c0, logq), limbs_of(cy.c1, logq))
     g0, g1 = _gpu_he_mult(ctx, (eb, ea), sch, t, logN, logq, logP, x, y, bits)
     want = scheme.mult_rescale(cx, cy, evk, bits)
-    assert ints(g0) == want.c0 and ints(g1) == want.c1
+    check(ints(g0), want.c0, "c0")
+    check(ints(g1), want.c1, "c1")
     out = scheme.Ciphertext(ints(g0), ints(g1), logN, logq - bits, want.logp, sch, t, want.gamma)
     if sch == scheme.BGV:
-        assert scheme.bgv_decode(scheme.decrypt(out, s), t, out.gamma) == ring.negacyclic_kronecker(m1, m2, t)
+        check(scheme.bgv_decode(scheme.decrypt(out, s), t, out.gamma), ring.negacyclic_kronecker(m1, m2, t), "m1 m2")
     else:
         z = scheme.ckks_decode(scheme.decrypt(out, s), N // 2, out.logp)
         assert np.max(np.abs(z - z1 * z2)) <= 2.0 ** -20
@@ -231,7 +234,8 @@ def test_he_mult_cfg3_sampled(ctx, sch, t, bits):
     Lo = synth.nlimbs(logq - bits)
     got0 = [sum(int(g0[l, i]) << (32 * l) for l in range(Lo)) for i in idx]
     got1 = [sum(int(g1[l, i]) << (32 * l) for l in range(Lo)) for i in idx]
-    assert got0 == w0 and got1 == w1
+    check(got0, w0, "sampled c0")
+    check(got1, w1, "sampled c1")
 
 
 @pytest.mark.parametrize("sch,t,bits", [(scheme.CKKS, 0, 1), (scheme.CKKS, 0, 32), (scheme.CKKS, 0, 73),
@@ -253,12 +257,13 @@ def test_rescale(ctx, sch, t, bits):
     for c in range(cnum):
         ct = scheme.Ciphertext(ints(c0[c]), ints(c1[c]), logN, logq, 60, sch, t, 1)
         want = scheme.rescale(ct, bits)
-        assert ints(g0[c]) == want.c0 and ints(g1[c]) == want.c1
+        check(ints(g0[c]), want.c0, f"c0 [{c}]")
+        check(ints(g1[c]), want.c1, f"c1 [{c}]")
     # in place, one ciphertext
     t0, t1 = dev(c0[0]), dev(c1[0])
     ctx.rescale(lsch, t, logN, logq, bits, t0, t1, t0, t1)
     ct = scheme.Ciphertext(ints(c0[0]), ints(c1[0]), logN, logq, 60, sch, t, 1)
-    assert ints(host(t0, (-1, N))[:Lo]) == scheme.rescale(ct, bits).c0
+    check(ints(host(t0, (-1, N))[:Lo]), scheme.rescale(ct, bits).c0, "in-place rescale")
 
 
 def test_zero_and_batched_he_mult(ctx):
@@ -291,7 +296,8 @@ def test_zero_and_batched_he_mult(ctx):
     # against the oracle for the first one
     ox, oy = oracle_ct(*xs[0], logN, logq, scheme.CKKS, 0), oracle_ct(*ys[0], logN, logq, scheme.CKKS, 0)
     want = scheme.mult(ox, oy, scheme.EvalKey(ints(eb), ints(ea), logN, logq, logP))
-    assert ints(b0[0]) == want.c0 and ints(b1[0]) == want.c1
+    check(ints(b0[0]), want.c0, "c0")
+    check(ints(b1[0]), want.c1, "c1")
     ek.close()
 
 

@@ -108,8 +108,8 @@ def test_admission_tight_budget_and_rejection(world):
     ctx, reqs, alone = world
     say("serve budget")
     _clear(reqs)
-    # a logN=14, logq=438 request holds about 32 MB of scratch: at most two fit in 80 MB
-    done = serve(ctx, reqs, budget=80 << 20, nstreams=4, max_batch=8)
+    # a logN=14, logq=438 request holds about 25 MB of scratch: at most two fit in 60 MB
+    done = serve(ctx, reqs, budget=60 << 20, nstreams=4, max_batch=8)
     assert len(done) == len(reqs) and all(d.status == 0 for d in done)
     big = {i + 1 for i, r in enumerate(reqs) if r[0].logN == 14 and r[1] == 438}
     assert big and max(d.batch for d in done if d.ticket in big) <= 2
