@@ -241,6 +241,7 @@ struct fhe_ctx {
   int logQ_max = 0, logP_max = 0;
   int K = 0;     // primes in the table
   int Kpad = 0;  // K + padding read by blocked kernels
+  int lds_max = 0, cus = 0;  // LDS bytes per workgroup and compute units of the device
   std::vector<uint32_t> q, psi;
   std::vector<int> mbits;  // mbits[k] = bit length of M_k = prod_(i<k) q_i, k <= K
   // device tables
@@ -250,7 +251,7 @@ struct fhe_ctx {
   uint2* nscale[kLogNMax + 1] = {};  // N^-1 per prime
   uint32_t* liftT = nullptr;
   int TS = 0, Lmax = 0;
-  double* invq = nullptr;  // [k] = 1 / q_k
+  uint32_t* rq = nullptr;  // [k] = floor(2^56 / q_k)
   std::map<int, std::vector<uint32_t>> crt_c;             // per K: c_k = [(M/q_k)^-1]_(q_k)
   std::map<std::tuple<int, int, int>, CrtTab> crt;        // per (K, e, Lout)
   std::map<std::pair<int, int>, uint2*> cscale;           // per (logN, K): [N^-1 2^32 c_k]_(q_k), Shoup
@@ -379,6 +380,10 @@ const CrtTab* crt_table(fhe_ctx* c, int K, int e, int Lout, hipError_t* err) {
   const auto key = std::make_tuple(K, e, Lout);
   auto it = c->crt.find(key);
   if (it != c->crt.end()) return &it->second;
+  if (8 * ((Lout + 7) / 8) > kCrtMaxLimbs || K > kCrtMaxPrimes) {
+    *err = hipErrorInvalidValue;
+    return nullptr;
+  }
   const std::vector<uint32_t>& ck = crt_c(c, K);
   const int nkb = (K + 31) / 32, ntiles = (Lout + 7) / 8, Lp = 8 * ntiles;
   CrtTab t;
@@ -501,6 +506,11 @@ const LiftTab* lift_table(fhe_ctx* c, int L, int K, hipError_t* err) {
   if (it != c->lifts.end()) return &it->second;
   LiftTab t;
   t.nkb = (L + 7) / 8;
+  if (t.nkb > 16) t.nkb = 32;  // the kernel is instantiated for 1..16 and 32 k-blocks (zero-padded)
+  if (L > 256) {
+    *err = hipErrorInvalidValue;
+    return nullptr;
+  }
   t.ntiles = (K + 7) / 8;
   // T_(i,a),p = [2^(32 i + 8 a + 32)]_(q_p), i < 8 nkb, a < 4
   std::vector<uint32_t> T((size_t)K * 32 * t.nkb, 0);
@@ -562,6 +572,8 @@ LiftArgs lift_args(fhe_ctx* c, const uint32_t* limbs, uint32_t* res, long long i
     a.nkb = t->nkb;
     a.ntiles = t->ntiles;
   }
+  a.lds_max = c->lds_max;
+  a.cus = c->cus;
   a.limbs = limbs;
   a.res = res;
   a.in_stride = in_stride;
@@ -599,9 +611,11 @@ hipError_t run_crt(fhe_ctx* c, const uint32_t* res, int per_group, long long gst
   a.A = t->A;
   a.pc = c->pc;
   a.d = t->d;
-  a.invq = c->invq;
+  a.rq = c->rq;
   a.mneg = t->mneg;
   a.eneg = t->eneg;
+  a.lds_max = c->lds_max;
+  a.cus = c->cus;
   return launch_crt(a, npoly, st);
 }
 
@@ -1294,6 +1308,11 @@ int fhe_ctx_create(int device, int logQ_max, int logP_max, fhe_ctx** out) {
   fhe_ctx* c = new (std::nothrow) fhe_ctx();
   if (!c) return FHE_E_NOMEM;
   c->device = device;
+  if (hipDeviceGetAttribute(&c->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess ||
+      hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+    delete c;
+    return FHE_E_DEVICE;
+  }
   c->logQ_max = logQ_max;
   c->logP_max = logP_max;
   // primes q = 1 mod 2^17 below 2^30, largest first, until the largest relinearization
@@ -1342,8 +1361,8 @@ int fhe_ctx_create(int device, int logQ_max, int logP_max, fhe_ctx** out) {
     pc[k].c32 = (uint32_t)((1ull << 32) % q);
     pc[k].two_q = 2 * q;
   }
-  std::vector<double> iq(Kpad, 0.0);
-  for (int k = 0; k < K; ++k) iq[k] = 1.0 / (double)c->q[k];
+  std::vector<uint32_t> rq(Kpad, 0);
+  for (int k = 0; k < K; ++k) rq[k] = (uint32_t)((1ull << 56) / c->q[k]);
   // lift constants 2^(28 i) 2^32 mod q_p (Montgomery form)
   c->Lmax = (std::max(logQ_max, logP_max + logQ_max) + 31) / 32;
   c->TS = 8 * ((c->Lmax + 6) / 7);
@@ -1387,7 +1406,7 @@ int fhe_ctx_create(int device, int logQ_max, int logP_max, fhe_ctx** out) {
   // upload
   if ((e = upload(&c->pc, pc)) == hipSuccess && (e = upload(&c->tw, tw)) == hipSuccess &&
       (e = upload(&c->itw, itw)) == hipSuccess && (e = upload(&c->liftT, T)) == hipSuccess &&
-      (e = upload(&c->invq, iq)) == hipSuccess) {
+      (e = upload(&c->rq, rq)) == hipSuccess) {
     for (int lg = FHE_LOGN_MIN; lg <= kLogNMax && e == hipSuccess; ++lg) e = upload(&c->nscale[lg], ns[lg]);
   }
   if (e != hipSuccess) {
@@ -1403,7 +1422,7 @@ void fhe_ctx_destroy(fhe_ctx* c) {
   if (!c) return;
   hipSetDevice(c->device);
   hipDeviceSynchronize();
-  for (void* p : {(void*)c->pc, (void*)c->tw, (void*)c->itw, (void*)c->liftT, (void*)c->invq})
+  for (void* p : {(void*)c->pc, (void*)c->tw, (void*)c->itw, (void*)c->liftT, (void*)c->rq})
     if (p) hipFree(p);
   for (int lg = 0; lg <= kLogNMax; ++lg)
     if (c->nscale[lg]) hipFree(c->nscale[lg]);

@@ -16,6 +16,7 @@ constexpr int kLiftDigitBits = 28;    // lift input digits: 8 digits = 7 limbs
 constexpr int kLiftPrimes = 32;       // largest primes-per-thread choice of the lift
 constexpr int kCrtMarginBits = 16;    // prime product >= 2^(e + 1 + margin): exact alpha
 constexpr int kCrtMaxPrimes = 256;    // k-blocks of 32 held in registers by the CRT kernel (<= 8)
+constexpr int kCrtMaxLimbs = 512;     // output limbs of one reconstruction (tiles of 8)
 
 // Negacyclic NTT over a set of transforms.  Transform (group g, row r) lives at
 // data + g * group_stride + r * N and uses prime r % K; per_group (rows per group)
@@ -47,6 +48,7 @@ struct LiftArgs {
   const v4i_t* A = nullptr;
   const uint64_t* off = nullptr;
   int nkb = 0, ntiles = 0;
+  int lds_max = 0, cus = 0;  // device: LDS bytes per workgroup, compute units
 };
 
 struct PointwiseArgs {
@@ -71,10 +73,11 @@ struct CrtArgs {
   const v4i_t* A = nullptr; // [tile][k-block][lane]: the 16 MFMA A bytes of each lane
   const PrimeC* pc = nullptr;
   const uint32_t* d = nullptr;    // [k] = [2^e c_k]_(q_k)
-  const double* invq = nullptr;   // [k] = 1 / q_k
+  const uint32_t* rq = nullptr;   // [k] = floor(2^56 / q_k)
   const uint32_t* mneg = nullptr; // [l < 8 ntiles] limbs of (-M) mod 2^(32 Lout), zero beyond Lout
   const uint32_t* eneg = nullptr; // [l < 8 ntiles] limbs of (-2^e) mod 2^(32 Lout), zero beyond Lout
   int npoly = 0;                  // set by launch_crt
+  int lds_max = 0, cus = 0;       // device: LDS bytes per workgroup, compute units
 };
 
 struct ComposeArgs {

@@ -12,6 +12,12 @@ namespace fhe {
 typedef v4i_t v4i;
 typedef int v16i __attribute__((ext_vector_type(16)));
 
+// Makes a register value opaque to the optimizer.  Applied to loaded values and to
+// lane masks, it keeps clamped, always-in-bounds loads unconditional (otherwise the
+// compiler sinks each into a branch on the mask and waits for it there, one load
+// at a time).
+__device__ __forceinline__ void opaque(uint32_t& v) { asm volatile("" : "+v"(v)); }
+
 static thread_local EventRecorder* g_rec = nullptr;
 static thread_local long long g_launches = 0;
 void set_recorder(EventRecorder* r) { g_rec = r; }
@@ -333,51 +339,101 @@ static void lift_launch(const LiftArgs& b, int npoly, hipStream_t st) {
 // [C0 2^32]_(q_p) + 2^20 q_p (makes it positive), and Montgomery-reduces.
 // One wave per 32 coefficients; lane (c, h) supplies limbs 8 kb + 4 h + r (r < 4)
 // of coefficient c as B register r of k-block kb.
-template <int MAXKB>
-__global__ __launch_bounds__(256) void lift_mfma_kernel(LiftArgs a) {
+// Workgroups are persistent: each wave takes groups of 32 coefficients in turn.
+// With LDSA the A table is staged once per workgroup in LDS (else read from L2).
+template <int NKB, bool LDSA, int BLK>
+__global__ __launch_bounds__(BLK) void lift_mfma_kernel(LiftArgs a) {
+  extern __shared__ v4i sA[];
+  __shared__ uint32_t s_q[kCrtMaxPrimes], s_qn[kCrtMaxPrimes], s_olo[kCrtMaxPrimes], s_ohi[kCrtMaxPrimes];
+  const int nfrag = a.ntiles * NKB * 64;
+  if (LDSA)
+    for (int f = threadIdx.x; f < nfrag; f += BLK) sA[f] = a.A[f];
+  for (int p = threadIdx.x; p < 8 * a.ntiles; p += BLK) {
+    const int pl = min(p, a.K - 1);
+    s_q[p] = a.pc[pl].q;
+    s_qn[p] = a.pc[pl].qneg;
+    const uint64_t o = a.off[pl];
+    s_olo[p] = (uint32_t)o;
+    s_ohi[p] = (uint32_t)(o >> 32);
+  }
+  __syncthreads();
+  uint32_t m8 = 256, m16 = 65536, m24 = 16777216;  // not foldable into shifts
+  opaque(m8);
+  opaque(m16);
+  opaque(m24);
+  const v4i* At = LDSA ? sA : a.A;
   const int lane = threadIdx.x & 63, c = lane & 31, h = lane >> 5;
-  const long long unit = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int groups = a.N >> 5;
-  if (unit >= (long long)a.npoly * groups) return;
-  const int z = (int)(unit / groups);
-  const int j = (int)(unit % groups) * 32 + c;
-  const uint32_t* src = (a.in_ptrs ? a.in_ptrs[z] : a.limbs + (long long)z * a.in_stride) + j;
-  v4i B[MAXKB];
+  const long long total = (long long)a.npoly * groups;
+  for (long long unit = (long long)blockIdx.x * (BLK / 64) + (threadIdx.x >> 6); unit < total;
+       unit += (long long)gridDim.x * (BLK / 64)) {
+    const int z = (int)(unit / groups);
+    const int j = (int)(unit % groups) * 32 + c;
+    const uint32_t* src = (a.in_ptrs ? a.in_ptrs[z] : a.limbs + (long long)z * a.in_stride) + j;
+    // all limb loads issue together (index clamped to L - 1, value masked)
+    uint32_t w[NKB][4];
 #pragma unroll
-  for (int kb = 0; kb < MAXKB; ++kb) {
-    if (kb < a.nkb) {
+    for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) w[kb][r] = src[(long long)min(8 * kb + 4 * h + r, a.L - 1) * a.N];
+    v4i B[NKB];
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int li = 8 * kb + 4 * h + r;
-        B[kb][r] = (int)((li < a.L ? src[(long long)li * a.N] : 0x80808080u) ^ 0x80808080u);
+        uint32_t msk = 8 * kb + 4 * h + r < a.L ? 0xFFFFFFFFu : 0u;  // limbs beyond L: digits 0
+        opaque(msk);
+        opaque(w[kb][r]);
+        B[kb][r] = (int)((w[kb][r] ^ 0x80808080u) & msk);
       }
-    }
-  }
-  uint32_t* dst = a.res + (long long)z * a.out_stride + j;
-  for (int t = 0; t < a.ntiles; ++t) {
-    v16i acc = {};
-    const v4i* Ap = a.A + (long long)t * a.nkb * 64 + lane;
+    uint32_t* dst = a.res + (long long)z * a.out_stride + j;
+    for (int t = 0; t < a.ntiles; ++t) {
+      const v4i* Ap = At + (long long)t * NKB * 64 + lane;
+      v4i Af[NKB];
 #pragma unroll
-    for (int kb = 0; kb < MAXKB; ++kb)
-      if (kb < a.nkb) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(Ap[kb * 64], B[kb], acc, 0, 0, 0);
+      for (int kb = 0; kb < NKB; ++kb) Af[kb] = Ap[kb * 64];
+      v16i acc = {};
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int p = 8 * t + 4 * h + i;
-      if (p < a.K) {
-        const int64_t v = (int64_t)acc[i] + (int64_t)acc[4 + i] * 256 + (int64_t)acc[8 + i] * 65536 +
-                          (int64_t)acc[12 + i] * 16777216;
-        const PrimeC pc = a.pc[p];
-        const uint64_t u = (uint64_t)(v + (int64_t)a.off[p]);
-        dst[(long long)p * a.N] = csub(redc_lazy(u, pc.q, pc.qneg), pc.q);
+      for (int kb = 0; kb < NKB; ++kb) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[kb], B[kb], acc, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int p = 8 * t + 4 * h + i;
+        const uint32_t q = s_q[p];
+        int64_t v = (int64_t)(((uint64_t)s_ohi[p] << 32) | s_olo[p]);
+        v += (int64_t)acc[i];
+        v += (int64_t)acc[4 + i] * (int32_t)m8;
+        v += (int64_t)acc[8 + i] * (int32_t)m16;
+        v += (int64_t)acc[12 + i] * (int32_t)m24;
+        const uint32_t r = csub(redc_lazy((uint64_t)v, q, s_qn[p]), q);
+        if (p < a.K) dst[(long long)p * a.N] = r;
       }
     }
   }
 }
 
-template <int MAXKB>
+// Persistent grid: enough workgroups to fill the chip, no more than the work needs.
+static unsigned persistent_grid(long long units, int waves_per_block, int blocks_per_cu, int cus) {
+  const long long need = (units + waves_per_block - 1) / waves_per_block;
+  return (unsigned)std::max(1LL, std::min(need, (long long)blocks_per_cu * cus));
+}
+
+template <int NKB>
 static void lift_mfma_launch(const LiftArgs& b, hipStream_t st) {
   const long long units = (long long)b.npoly * (b.N >> 5);
-  hipLaunchKernelGGL((lift_mfma_kernel<MAXKB>), dim3((unsigned)((units + 3) / 4)), dim3(256), 0, st, b);
+  const size_t lds = (size_t)b.ntiles * NKB * 64 * sizeof(v4i);
+  const size_t lds_static = 4 * kCrtMaxPrimes * 4;
+  if (NKB <= 7 && lds + lds_static <= (size_t)b.lds_max) {  // larger k-block counts spill at 768 threads
+    static bool attr = false;  // allow the rest of the device's LDS for this instantiation (once)
+    if (!attr)
+      attr = hipFuncSetAttribute((const void*)lift_mfma_kernel<NKB, true, 768>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 b.lds_max - (int)lds_static) == hipSuccess;
+    hipLaunchKernelGGL((lift_mfma_kernel<NKB, true, 768>), dim3(persistent_grid(units, 12, 1, b.cus)), dim3(768),
+                       lds, st, b);
+  } else {
+    hipLaunchKernelGGL((lift_mfma_kernel<NKB, false, 256>), dim3(persistent_grid(units, 4, 8, b.cus)), dim3(256), 0,
+                       st, b);
+  }
 }
 
 hipError_t launch_lift(const LiftArgs& a, int npoly, hipStream_t st, const Tuning& t) {
@@ -387,20 +443,27 @@ hipError_t launch_lift(const LiftArgs& a, int npoly, hipStream_t st, const Tunin
   // algorithmic work: L limb-constant products per (coefficient, prime)
   Bracket br(KID_LIFT, st, (double)npoly * a.N * a.K * a.L);
   if (t.lift_primes == 0 && a.A) {
-    if (b.nkb <= 1)
-      lift_mfma_launch<1>(b, st);
-    else if (b.nkb <= 2)
-      lift_mfma_launch<2>(b, st);
-    else if (b.nkb <= 4)
-      lift_mfma_launch<4>(b, st);
-    else if (b.nkb <= 8)
-      lift_mfma_launch<8>(b, st);
-    else if (b.nkb <= 16)
-      lift_mfma_launch<16>(b, st);
-    else if (b.nkb <= 32)
-      lift_mfma_launch<32>(b, st);
-    else
-      return hipErrorInvalidValue;
+    // the table's k-block count: exact up to 16 (L <= 128), else padded to 32
+    switch (b.nkb) {
+      case 1: lift_mfma_launch<1>(b, st); break;
+      case 2: lift_mfma_launch<2>(b, st); break;
+      case 3: lift_mfma_launch<3>(b, st); break;
+      case 4: lift_mfma_launch<4>(b, st); break;
+      case 5: lift_mfma_launch<5>(b, st); break;
+      case 6: lift_mfma_launch<6>(b, st); break;
+      case 7: lift_mfma_launch<7>(b, st); break;
+      case 8: lift_mfma_launch<8>(b, st); break;
+      case 9: lift_mfma_launch<9>(b, st); break;
+      case 10: lift_mfma_launch<10>(b, st); break;
+      case 11: lift_mfma_launch<11>(b, st); break;
+      case 12: lift_mfma_launch<12>(b, st); break;
+      case 13: lift_mfma_launch<13>(b, st); break;
+      case 14: lift_mfma_launch<14>(b, st); break;
+      case 15: lift_mfma_launch<15>(b, st); break;
+      case 16: lift_mfma_launch<16>(b, st); break;
+      case 32: lift_mfma_launch<32>(b, st); break;
+      default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
   }
   switch (t.lift_primes) {
@@ -491,16 +554,17 @@ hipError_t launch_ring_pointwise(const PointwiseArgs& a, int cnum, hipStream_t s
 // Y = X + 2^e in [0, 2^(e+1)) (X the signed exact product, |X| < 2^e).  Then
 //   Y = sum_k y_k (M/q_k) - alpha M,   alpha = floor(sum_k y_k / q_k),
 // and the output is X mod 2^outbits = (Y - 2^e) mod 2^outbits.  The prime count
-// leaves Y / M < 2^-16, so alpha is the floor of a sum of fractions evaluated in
-// double precision (error < 2^-37, far inside the margin).
+// leaves Y / M < 2^-16, so alpha is exact from the sum in fixed point
+// sum_k y_k floor(2^56 / q_k) (each term < 2^56, truncation error < K 2^-26 <
+// 2^-18 in units of 2^56): alpha = (sum + 2^38) >> 56.
 //
 // The column sums sum_k y_k V_kl, V_kl = limb l of (M/q_k) mod 2^(32 Lout), are a
 // dense integer contraction [coefficients x K] x [K x Lout] and run on the i8
 // matrix cores: y_k and V_kl are split into 4 balanced base-256 digits each
 // (digits in [-128, 127], limbs of V taken in [-0x80808080, 0x7F7F7F7F]), the 16
 // digit-plane products accumulate exactly in int32 (|sum| <= K 2^14), and the VALU
-// recombines sum_(a,b) 2^(8(a+b)) C_ab per limb, adds alpha [-M] + [-2^e], and
-// propagates the carries.
+// recombines sum_(a,b) 2^(8(a+b)) C_ab per limb (the 7 diagonal sums in int32, then
+// 64-bit multiply-adds), adds alpha [-M] + [-2^e], and propagates the carries.
 //
 // One wave per 32 coefficients.  MFMA v_mfma_i32_32x32x32_i8: lane (c, h) = (lane
 // mod 32, lane / 32) supplies B bytes k = 32 kb + 16 h + i (i < 16) of coefficient
@@ -534,104 +598,141 @@ __device__ __forceinline__ int64_t add_carry4(uint32_t (&o)[4], int64_t cin) {
   return cin;
 }
 
-template <int NKB>
-__global__ __launch_bounds__(256) void crt_kernel(CrtArgs a) {
-  __shared__ uint32_t s_q[32 * NKB], s_d[32 * NKB];
-  __shared__ double s_iq[32 * NKB];
-  for (int k = threadIdx.x; k < 32 * NKB; k += 256) {
+template <int NKB, bool LDSA>
+__global__ __launch_bounds__(512) void crt_kernel(CrtArgs a) {
+  extern __shared__ v4i sA[];
+  __shared__ uint32_t s_q[32 * NKB], s_d[32 * NKB], s_r[32 * NKB];
+  __shared__ uint32_t s_mneg[kCrtMaxLimbs], s_eneg[kCrtMaxLimbs];
+  for (int k = threadIdx.x; k < 32 * NKB; k += 512) {
     const bool in = k < a.K;
     s_q[k] = in ? a.pc[k].q : 1u;
     s_d[k] = in ? a.d[k] : 0u;
-    s_iq[k] = in ? a.invq[k] : 0.0;
+    s_r[k] = in ? a.rq[k] : 0u;
   }
+  for (int l = threadIdx.x; l < 8 * a.ntiles; l += 512) {
+    s_mneg[l] = a.mneg[l];
+    s_eneg[l] = a.eneg[l];
+  }
+  if (LDSA)
+    for (int f = threadIdx.x; f < a.ntiles * NKB * 64; f += 512) sA[f] = a.A[f];
   __syncthreads();
+  const v4i* At = LDSA ? sA : a.A;
   const int lane = threadIdx.x & 63, c = lane & 31, h = lane >> 5;
-  const long long unit = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int groups = a.N >> 5;
-  if (unit >= (long long)a.npoly * groups) return;
-  const int z = (int)(unit / groups);
-  const int j = (int)(unit % groups) * 32 + c;
-  const uint32_t* x = a.res + (long long)(z / a.per_group) * a.gstride + (long long)(z % a.per_group) * a.pstride + j;
-
-  // phase 1: y_k, the partial sum of y_k / q_k, and the four digit planes per k-block
-  v4i B[NKB][4];
-  double frac = 0.0;
-#pragma unroll
-  for (int kb = 0; kb < NKB; ++kb) {
-    uint32_t s[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int k = 32 * kb + 16 * h + i;
-      uint32_t y = 0;
-      if (k < a.K) {
-        const uint32_t q = s_q[k];
-        y = x[(long long)k * a.N] + s_d[k];
-        y = min(y, y - q);
-        frac = __builtin_fma((double)y, s_iq[k], frac);
-      }
-      s[i] = (y + 0x80808080u) ^ 0x80808080u;  // balanced base-256 digits, as int8 bytes
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      uint32_t p0, p1, p2, p3;
-      byte_planes(s[4 * r], s[4 * r + 1], s[4 * r + 2], s[4 * r + 3], p0, p1, p2, p3);
-      B[kb][0][r] = (int)p0;
-      B[kb][1][r] = (int)p1;
-      B[kb][2][r] = (int)p2;
-      B[kb][3][r] = (int)p3;
-    }
-  }
-  frac += __shfl_xor(frac, 32);
-  const uint32_t alpha = (uint32_t)(frac + 0x1p-20);
-
-  // phase 2: per tile of 8 limbs, the digit-plane products, recombination, carries
-  uint32_t* o = a.out + (long long)z * a.ostride + j;
+  const long long total = (long long)a.npoly * groups;
   const int topbits = a.outbits - 32 * (a.Lout - 1);
-  int64_t cin = 0;  // carry into the tile (valid in lane half 0)
-  for (int t = 0; t < a.ntiles; ++t) {
-    v16i acc0 = {}, acc1 = {}, acc2 = {}, acc3 = {};
-    const v4i* Ap = a.A + ((long long)t * NKB) * 64 + lane;
+  {
+    const long long unit = (long long)blockIdx.x * 8 + (threadIdx.x >> 6);
+    if (unit >= total) return;  // after the only barrier
+    const int z = (int)(unit / groups);
+    const int j = (int)(unit % groups) * 32 + c;
+    const uint32_t* x =
+        a.res + (long long)(z / a.per_group) * a.gstride + (long long)(z % a.per_group) * a.pstride + j;
+
+    // phase 1: y_k, the partial sum of y_k / q_k, and the four digit planes per k-block.
+    // Loads are unconditional (index clamped to K - 1, value masked) so that a block's
+    // 16 loads issue together, and the next block's loads are in flight meanwhile.
+    v4i B[NKB][4];
+    uint64_t frac = 0;  // sum_k y_k floor(2^56 / q_k)
+    uint32_t xv[16], xn[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) xv[i] = x[(long long)min(16 * h + i, a.K - 1) * a.N];
 #pragma unroll
     for (int kb = 0; kb < NKB; ++kb) {
-      const v4i A = Ap[kb * 64];
-      acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B[kb][0], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B[kb][1], acc1, 0, 0, 0);
-      acc2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B[kb][2], acc2, 0, 0, 0);
-      acc3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B[kb][3], acc3, 0, 0, 0);
-    }
-    uint32_t ol[4];
-    int64_t carry = 0;
+      if (kb + 1 < NKB) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int limb = 8 * t + 4 * h + i;
-      // C_ab = acc_a[4 b + i]: y plane a times V plane b
-      const int64_t s0 = acc0[i];
-      const int64_t s1 = (int64_t)acc0[4 + i] + acc1[i];
-      const int64_t s2 = (int64_t)acc0[8 + i] + acc1[4 + i] + acc2[i];
-      const int64_t s3 = (int64_t)acc0[12 + i] + acc1[8 + i] + acc2[4 + i] + acc3[i];
-      const int64_t s4 = (int64_t)acc1[12 + i] + acc2[8 + i] + acc3[4 + i];
-      const int64_t s5 = (int64_t)acc2[12 + i] + acc3[8 + i];
-      const int64_t s6 = acc3[12 + i];
-      const int64_t lo = s0 + s1 * 256 + s2 * 65536 + s3 * 16777216 + (int64_t)((uint64_t)alpha * a.mneg[limb]) +
-                         (int64_t)a.eneg[limb];
-      const int64_t hi = s4 + s5 * 256 + s6 * 65536;
-      const int64_t tt = lo + carry;
-      ol[i] = (uint32_t)tt;
-      carry = (tt >> 32) + hi;
-    }
-    // carry across the lane halves: half 0 takes the carry into the tile, passes its
-    // carry out to half 1, whose carry out enters the next tile
-    carry += add_carry4(ol, h == 0 ? cin : 0);
-    const int64_t mid = __shfl_xor(carry, 32);
-    carry += add_carry4(ol, h == 1 ? mid : 0);
-    cin = __shfl_xor(carry, 32);
+        for (int i = 0; i < 16; ++i) xn[i] = x[(long long)min(32 * (kb + 1) + 16 * h + i, a.K - 1) * a.N];
+      }
+      uint32_t s[16];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int limb = 8 * t + 4 * h + i;
-      if (limb < a.Lout) {
-        uint32_t w = ol[i];
-        if (limb == a.Lout - 1 && topbits < 32) w &= (1u << topbits) - 1u;
-        o[(long long)limb * a.N] = w;
+      for (int i = 0; i < 16; ++i) {
+        const int k = 32 * kb + 16 * h + i;
+        uint32_t msk = k < a.K ? 0xFFFFFFFFu : 0u;
+        opaque(msk);
+        opaque(xv[i]);
+        uint32_t y = xv[i] + s_d[k];
+        y = min(y, y - s_q[k]) & msk;
+        frac += (uint64_t)y * s_r[k];
+        s[i] = (y + 0x80808080u) ^ 0x80808080u;           // balanced base-256 digits, as int8 bytes
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        uint32_t p0, p1, p2, p3;
+        byte_planes(s[4 * r], s[4 * r + 1], s[4 * r + 2], s[4 * r + 3], p0, p1, p2, p3);
+        B[kb][0][r] = (int)p0;
+        B[kb][1][r] = (int)p1;
+        B[kb][2][r] = (int)p2;
+        B[kb][3][r] = (int)p3;
+      }
+      if (kb + 1 < NKB) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) xv[i] = xn[i];
+      }
+    }
+    frac += __shfl_xor(frac, 32);
+    const uint32_t alpha = (uint32_t)((frac + (1ull << 38)) >> 56);
+    // multipliers the compiler cannot fold into shifts: the combination below is
+    // then one 64-bit multiply-add per term
+    uint32_t m8 = 256, m16 = 65536, m24 = 16777216;
+    opaque(m8);
+    opaque(m16);
+    opaque(m24);
+
+    // phase 2: per tile of 8 limbs, the digit-plane products, recombination, carries
+    uint32_t* o = a.out + (long long)z * a.ostride + j;
+    int64_t cin = 0;  // carry into the tile (valid in lane half 0)
+    for (int t = 0; t < a.ntiles; ++t) {
+      v16i acc0 = {}, acc1 = {}, acc2 = {}, acc3 = {};
+      const v4i* Ap = At + ((long long)t * NKB) * 64 + lane;
+      v4i Af[NKB];
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb) Af[kb] = Ap[kb * 64];
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb) {
+        acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[kb], B[kb][0], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[kb], B[kb][1], acc1, 0, 0, 0);
+        acc2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[kb], B[kb][2], acc2, 0, 0, 0);
+        acc3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[kb], B[kb][3], acc3, 0, 0, 0);
+      }
+      uint32_t ol[4];
+      int64_t carry = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int limb = 8 * t + 4 * h + i;
+        // C_ab = acc_a[4 b + i]: y plane a times V plane b; diagonal sums (|.| < 2^24)
+        const int32_t s0 = acc0[i];
+        const int32_t s1 = acc0[4 + i] + acc1[i];
+        const int32_t s2 = acc0[8 + i] + acc1[4 + i] + acc2[i];
+        const int32_t s3 = acc0[12 + i] + acc1[8 + i] + acc2[4 + i] + acc3[i];
+        const int32_t s4 = acc1[12 + i] + acc2[8 + i] + acc3[4 + i];
+        const int32_t s5 = acc2[12 + i] + acc3[8 + i];
+        const int32_t s6 = acc3[12 + i];
+        int64_t lo = (int64_t)((uint64_t)alpha * s_mneg[limb] + s_eneg[limb]);
+        lo += (int64_t)s0;
+        lo += (int64_t)s1 * (int32_t)m8;
+        lo += (int64_t)s2 * (int32_t)m16;
+        lo += (int64_t)s3 * (int32_t)m24;
+        int64_t hi = (int64_t)s4;
+        hi += (int64_t)s5 * (int32_t)m8;
+        hi += (int64_t)s6 * (int32_t)m16;
+        const int64_t tt = lo + carry;
+        ol[i] = (uint32_t)tt;
+        carry = (tt >> 32) + hi;
+      }
+      // carry across the lane halves: half 0 takes the carry into the tile, passes its
+      // carry out to half 1, whose carry out enters the next tile
+      carry += add_carry4(ol, h == 0 ? cin : 0);
+      const int64_t mid = __shfl_xor(carry, 32);
+      carry += add_carry4(ol, h == 1 ? mid : 0);
+      cin = __shfl_xor(carry, 32);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int limb = 8 * t + 4 * h + i;
+        if (limb < a.Lout) {
+          uint32_t w = ol[i];
+          if (limb == a.Lout - 1 && topbits < 32) w &= (1u << topbits) - 1u;
+          o[(long long)limb * a.N] = w;
+        }
       }
     }
   }
@@ -640,7 +741,18 @@ __global__ __launch_bounds__(256) void crt_kernel(CrtArgs a) {
 template <int NKB>
 static void crt_launch(const CrtArgs& a, hipStream_t st) {
   const long long units = (long long)a.npoly * (a.N >> 5);
-  hipLaunchKernelGGL(crt_kernel<NKB>, dim3((unsigned)((units + 3) / 4)), dim3(256), 0, st, a);
+  const size_t lds = (size_t)a.ntiles * NKB * 64 * sizeof(v4i);
+  const unsigned grid = (unsigned)((units + 7) / 8);
+  const size_t lds_static = 32 * NKB * 12 + 2 * kCrtMaxLimbs * 4;
+  if (lds + lds_static <= (size_t)a.lds_max) {
+    static bool attr = false;  // allow the full LDS of the device for this instantiation (once)
+    if (!attr)
+      attr = hipFuncSetAttribute((const void*)crt_kernel<NKB, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 a.lds_max - (int)lds_static) == hipSuccess;
+    hipLaunchKernelGGL((crt_kernel<NKB, true>), dim3(grid), dim3(512), lds, st, a);
+  } else {
+    hipLaunchKernelGGL((crt_kernel<NKB, false>), dim3(grid), dim3(512), 0, st, a);
+  }
 }
 
 hipError_t launch_crt(CrtArgs a, int npoly, hipStream_t st) {
