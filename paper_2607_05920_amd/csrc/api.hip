@@ -562,6 +562,17 @@ const LiftTab* lift_table(fhe_ctx* c, int L, int K, hipError_t* err) {
   return &(c->lifts[key] = t);
 }
 
+RowsArgs rows_args(fhe_ctx* c, int logN, int K, int cnum) {
+  RowsArgs a{};
+  a.logN = logN;
+  a.K = K;
+  a.cnum = cnum;
+  a.tw = c->tw;
+  a.itw = c->itw;
+  a.pc = c->pc;
+  return a;
+}
+
 LiftArgs lift_args(fhe_ctx* c, const uint32_t* limbs, uint32_t* res, long long in_stride,
                    long long out_stride, int N, int L, int K) {
   LiftArgs a{};
@@ -741,22 +752,20 @@ int pipeline(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, const PipeIO&
     if (io.ins) la.in_ptrs = io.ins + (long long)i * cnum;
     e = launch_lift(la, cnum, st, tu);
   }
-  // 2. forward NTT of all 4 cnum Kt transforms
+  // 2. forward NTT column pass of all 4 cnum Kt transforms
   if (e == hipSuccess)
-    e = launch_ntt(ntt_args(c, Rt, logN, Kt, 4 * Kt, 4LL * Kt * NN, false, nullptr), cnum * 4 * Kt, false, st, tu);
-  // 3. tensor products into slots 0..2
+    e = launch_ntt_cols(ntt_args(c, Rt, logN, Kt, 4 * Kt, 4LL * Kt * NN, false, nullptr), cnum * 4 * Kt, false, st,
+                        tu);
+  // 3. forward row pass, tensor products into slots 0..2, first inverse row pass
   if (e == hipSuccess) {
-    PointwiseArgs pa{};
-    pa.a = Rt;
-    pa.group_stride = 4LL * Kt * NN;
-    pa.N = N;
-    pa.K = Kt;
-    pa.pc = c->pc;
-    e = launch_tensor_pointwise(pa, cnum, st);
+    RowsArgs ra = rows_args(c, logN, Kt, cnum);
+    ra.data = Rt;
+    ra.group_stride = 4LL * Kt * NN;
+    e = launch_rows_fused(ra, ROWS_TENSOR, st, tu);
   }
-  // 4. inverse NTT of slots 0..2 (final factor N^-1 2^32 c_k)
+  // 4. inverse NTT column pass of slots 0..2 (final factor N^-1 2^32 c_k)
   if (e == hipSuccess)
-    e = launch_ntt(ntt_args(c, Rt, logN, Kt, 3 * Kt, 4LL * Kt * NN, true, sct), cnum * 3 * Kt, true, st, tu);
+    e = launch_ntt_cols(ntt_args(c, Rt, logN, Kt, 3 * Kt, 4LL * Kt * NN, true, sct), cnum * 3 * Kt, true, st, tu);
   // 5. CRT -> d0, d1, d2 mod 2^logq: Dl[c][i][L][N]
   if (e == hipSuccess)
     e = run_crt(c, Rt, 3, 4LL * Kt * NN, (long long)Kt * NN, Dl, polyw, N, Kt, et, logq, cnum * 3, st);
@@ -764,23 +773,22 @@ int pipeline(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, const PipeIO&
   if (e == hipSuccess)
     e = launch_lift(lift_args(c, Dl + 2 * polyw, Rr, 3 * polyw, (long long)Kr * NN, N, L, Kr), cnum, st, tu);
   if (e == hipSuccess)
-    e = launch_ntt(ntt_args(c, Rr, logN, Kr, Kr, (long long)Kr * NN, false, nullptr), cnum * Kr, false, st, tu);
-  // 8. products with the resident key: Rk[c][0..1][Kr][N]
+    e = launch_ntt_cols(ntt_args(c, Rr, logN, Kr, Kr, (long long)Kr * NN, false, nullptr), cnum * Kr, false, st,
+                        tu);
+  // 8. forward row pass, products with the resident key into Rk[c][0..1][Kr][N],
+  // first inverse row pass
   if (e == hipSuccess) {
-    PointwiseArgs pa{};
-    pa.a = Rr;
-    pa.b = evk_ntt;
-    pa.out = Rk;
-    pa.group_stride = (long long)Kr * NN;
-    pa.out_stride = 2LL * Kr * NN;
-    pa.N = N;
-    pa.K = Kr;
-    pa.pc = c->pc;
-    e = launch_relin_pointwise(pa, cnum, st);
+    RowsArgs ra = rows_args(c, logN, Kr, cnum);
+    ra.data = Rr;
+    ra.group_stride = (long long)Kr * NN;
+    ra.key = evk_ntt;
+    ra.out = Rk;
+    ra.out_stride = 2LL * Kr * NN;
+    e = launch_rows_fused(ra, ROWS_RELIN, st, tu);
   }
-  // 9. inverse NTT; 10. CRT -> k0, k1 mod 2^(logP + logq)
+  // 9. inverse NTT column pass; 10. CRT -> k0, k1 mod 2^(logP + logq)
   if (e == hipSuccess)
-    e = launch_ntt(ntt_args(c, Rk, logN, Kr, 2 * Kr, 2LL * Kr * NN, true, scr), cnum * 2 * Kr, true, st, tu);
+    e = launch_ntt_cols(ntt_args(c, Rk, logN, Kr, 2 * Kr, 2LL * Kr * NN, true, scr), cnum * 2 * Kr, true, st, tu);
   if (e == hipSuccess)
     e = run_crt(c, Rk, 2, 2LL * Kr * NN, (long long)Kr * NN, Kl, (long long)LK * NN, N, Kr, er, logP + logq,
                 cnum * 2, st);
@@ -1255,18 +1263,15 @@ int ring_mul_locked(fhe_ctx* c, int logN, int logq, const uint32_t* a, const uin
   uint32_t* Rb = R + (long long)cnum * KN;
   e = launch_lift(lift_args(c, a, Ra, (long long)L * N, KN, N, L, K), cnum, st);
   if (e == hipSuccess) e = launch_lift(lift_args(c, b, Rb, (long long)L * N, KN, N, L, K), cnum, st);
-  if (e == hipSuccess) e = launch_ntt(ntt_args(c, R, logN, K, K, KN, false, nullptr), 2 * cnum * K, false, st);
+  if (e == hipSuccess) e = launch_ntt_cols(ntt_args(c, R, logN, K, K, KN, false, nullptr), 2 * cnum * K, false, st);
   if (e == hipSuccess) {
-    PointwiseArgs pa{};
-    pa.a = Ra;
-    pa.b = Rb;
-    pa.group_stride = KN;
-    pa.N = N;
-    pa.K = K;
-    pa.pc = c->pc;
-    e = launch_ring_pointwise(pa, cnum, st);
+    RowsArgs ra = rows_args(c, logN, K, cnum);
+    ra.data = Ra;
+    ra.data2 = Rb;
+    ra.group_stride = KN;
+    e = launch_rows_fused(ra, ROWS_RING, st);
   }
-  if (e == hipSuccess) e = launch_ntt(ntt_args(c, Ra, logN, K, K, KN, true, sc), cnum * K, true, st);
+  if (e == hipSuccess) e = launch_ntt_cols(ntt_args(c, Ra, logN, K, K, KN, true, sc), cnum * K, true, st);
   if (e == hipSuccess) e = run_crt(c, Ra, 1, KN, 0, out, (long long)L * N, N, K, eb, logq, cnum, st);
   return set_sticky(c, e);
 }

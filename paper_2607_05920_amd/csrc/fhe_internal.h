@@ -33,6 +33,22 @@ struct NttArgs {
   int ntr = 0;         // number of transforms (set by launch_ntt; a multiple of K)
 };
 
+// Fused last forward row pass + pointwise products + first inverse row pass over
+// cnum groups of transforms whose column passes ran separately.
+enum { ROWS_TENSOR = 0, ROWS_RELIN = 1, ROWS_RING = 2 };
+struct RowsArgs {
+  uint32_t* data = nullptr;        // group c at data + c group_stride: tensor [4][K][N]; relin [K][N]; ring a [K][N]
+  const uint32_t* data2 = nullptr; // ring: b, group c at data2 + c group_stride
+  long long group_stride = 0;
+  const uint32_t* key = nullptr;   // relin: the key's [2][K][N] in NTT form
+  uint32_t* out = nullptr;         // relin: group c at out + c out_stride, [2][K][N]
+  long long out_stride = 0;
+  int logN = 0, K = 0, cnum = 0;
+  const uint2* tw = nullptr;       // forward and inverse twiddles, [prime][kNMax]
+  const uint2* itw = nullptr;
+  const PrimeC* pc = nullptr;
+};
+
 struct LiftArgs {
   const uint32_t* limbs = nullptr; // poly z at limbs + z * in_stride, uint32[L][N] (or in_ptrs[z])
   const uint32_t* const* in_ptrs = nullptr;  // optional device array of per-poly inputs
@@ -120,6 +136,7 @@ enum KernelId {
   KID_GARNER,
   KID_COMPOSE,
   KID_RESCALE,
+  KID_ROWS_FUSED,
   KID_COUNT
 };
 
@@ -141,6 +158,9 @@ struct Tuning {
 
 hipError_t launch_ntt(const NttArgs& a, int ntransforms, bool inverse, hipStream_t s,
                       const Tuning& t = Tuning());
+hipError_t launch_ntt_cols(const NttArgs& a, int ntransforms, bool inverse, hipStream_t s,
+                           const Tuning& t = Tuning());
+hipError_t launch_rows_fused(const RowsArgs& a, int mode, hipStream_t s, const Tuning& t = Tuning());
 hipError_t launch_lift(const LiftArgs& a, int npoly, hipStream_t s, const Tuning& t = Tuning());
 hipError_t launch_tensor_pointwise(const PointwiseArgs& a, int cnum, hipStream_t s);
 hipError_t launch_relin_pointwise(const PointwiseArgs& a, int cnum, hipStream_t s);

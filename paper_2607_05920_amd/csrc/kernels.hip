@@ -215,6 +215,255 @@ __global__ __launch_bounds__(256) void ntt_pass_kernel(NttArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------- fused row pass
+// The last forward pass, the pointwise products and the first inverse pass touch
+// the same n-point rows: one kernel loads each input row once, finishes its forward
+// transform in registers, multiplies (Eq. ntt_mul), runs the first inverse stages
+// and stores the outputs, instead of three kernels each reading and writing them.
+// After the forward row pass a thread holds elements e = 16 j + u of its row, which
+// is where the pointwise step and the inverse row pass work, so no exchange is
+// needed between them.  Two LDS buffers alternate, one barrier per exchange.
+//   tensor: rows x0, x1, y0, y1 -> d0 = x0 y0, d1 = x0 y1 + x1 y0, d2 = x1 y1 (slots 0..2)
+//   relin:  row d2 and the key's rows b', a' -> k0 = d2 b', k1 = d2 a' (to out)
+//   ring:   rows a, b -> a b (in place of a)
+
+// Forward n-point row transforms of NP rows at once (the values x[r][u] at
+// e = u T + j, loaded by the caller): each twiddle is loaded once for all rows and
+// the NP exchanges share one barrier.  Leaves canonical values at e = 16 j + u.
+template <int S, int NP>
+__device__ __forceinline__ void fwd_rows(uint32_t (&x)[NP][16], uint32_t* const (&l)[NP], int j, const uint2* tw,
+                                         int tw_mul, uint32_t q, uint32_t two_q) {
+  constexpr int n = 1 << S, T = n / 16;
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int m = 1 << st, h = 8 >> st;
+#pragma unroll
+    for (int g = 0; g < m; ++g) {
+      const uint2 w = tw[tw_mul * m + g];
+#pragma unroll
+      for (int r = 0; r < NP; ++r)
+#pragma unroll
+        for (int u = 2 * h * g; u < 2 * h * g + h; ++u) ct_bfly(x[r][u], x[r][u + h], w, q, two_q);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NP; ++r)
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = u * T + j;
+      l[r][e + (e >> 4)] = x[r][u];
+    }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < NP; ++r)
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = 16 * j + u;
+      x[r][u] = l[r][e + (e >> 4)];
+    }
+#pragma unroll
+  for (int t = T / 2; t >= 1; t >>= 1) {
+    const int m = n / (2 * t);
+#pragma unroll
+    for (int b0 = 0; b0 < 16; b0 += 2 * t) {
+      const uint2 w = tw[tw_mul * m + j * (8 / t) + b0 / (2 * t)];
+#pragma unroll
+      for (int r = 0; r < NP; ++r)
+#pragma unroll
+        for (int u = b0; u < b0 + t; ++u) ct_bfly(x[r][u], x[r][u + t], w, q, two_q);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NP; ++r)
+#pragma unroll
+    for (int u = 0; u < 16; ++u) x[r][u] = csub(csub(x[r][u], two_q), q);
+}
+
+// First inverse n-point row stages of NP rows at once, values at e = 16 j + u in
+// [0, 2q); leaves values in [0, 2q) at e = u T + j for the caller to store.
+template <int S, int NP>
+__device__ __forceinline__ void inv_rows(uint32_t (&x)[NP][16], uint32_t* const (&l)[NP], int j, const uint2* tw,
+                                         int tw_mul, uint32_t q, uint32_t two_q) {
+  constexpr int n = 1 << S, T = n / 16;
+#pragma unroll
+  for (int t = 1; t < T; t <<= 1) {
+    const int h = n / (2 * t);
+#pragma unroll
+    for (int b0 = 0; b0 < 16; b0 += 2 * t) {
+      const uint2 w = tw[tw_mul * h + j * (8 / t) + b0 / (2 * t)];
+#pragma unroll
+      for (int r = 0; r < NP; ++r)
+#pragma unroll
+        for (int u = b0; u < b0 + t; ++u) gs_bfly(x[r][u], x[r][u + t], w, q, two_q);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NP; ++r)
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = 16 * j + u;
+      l[r][e + (e >> 4)] = x[r][u];
+    }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < NP; ++r)
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = u * T + j;
+      x[r][u] = l[r][e + (e >> 4)];
+    }
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int hd = 1 << st, h = 8 >> st;
+#pragma unroll
+    for (int g = 0; g < h; ++g) {
+      const uint2 w = tw[tw_mul * h + g];
+#pragma unroll
+      for (int r = 0; r < NP; ++r)
+#pragma unroll
+        for (int u = 2 * hd * g; u < 2 * hd * g + hd; ++u) gs_bfly(x[r][u], x[r][u + hd], w, q, two_q);
+    }
+  }
+}
+
+// Rows per workgroup of the fused pass: 8 rows of 256 points (128 threads).
+template <int S>
+struct RowsShape {
+  static constexpr int n = 1 << S, T = n / 16;
+  static constexpr int NSUB = 128 / T;
+  static constexpr int SS = ((n + n / 16 + 1 + 31) / 32) * 32 + T;
+};
+
+template <int S, int MODE>
+__global__ __launch_bounds__(128) void rows_fused_kernel(RowsArgs a) {
+  constexpr int n = RowsShape<S>::n, T = RowsShape<S>::T, NSUB = RowsShape<S>::NSUB, SS = RowsShape<S>::SS;
+  __shared__ uint32_t lds[4][NSUB * SS];
+
+  const int tid = threadIdx.x;
+  const int s = tid / T, j = tid % T;
+  const int N = 1 << a.logN;
+  const int nsub_total = N / n;
+  // XCD-aware: workgroup w runs on XCD w % 8, which takes primes p = w % 8 (mod 8)
+  const int nwg = (nsub_total + NSUB - 1) / NSUB;
+  const int per_prime = a.cnum * nwg;
+  const int w = blockIdx.x, xcd = w & 7, l = w >> 3;
+  const int p = (l / per_prime) * 8 + xcd;
+  if (p >= a.K) return;  // whole workgroup exits
+  const int rem = l % per_prime;
+  const int c = rem / nwg;
+  const int sg = (rem % nwg) * NSUB + s;
+  const bool valid = sg < nsub_total;
+  const PrimeC pc = a.pc[p];
+  const uint32_t q = pc.q, two_q = pc.two_q, qneg = pc.qneg;
+  const uint2* tw = a.tw + (long long)p * kNMax;
+  const uint2* itw = a.itw + (long long)p * kNMax;
+  const int tw_mul = nsub_total + sg;
+  const long long KN = (long long)a.K * N;
+  const long long row = (long long)p * N + (long long)sg * n;  // row sg of prime p
+  uint32_t* const l0 = lds[0] + s * SS;
+  uint32_t* const l1 = lds[1] + s * SS;
+  uint32_t* const l2 = lds[2] + s * SS;
+  uint32_t* const l3 = lds[3] + s * SS;
+
+  if (MODE == 0) {  // tensor, in place: slots 0..3 in, 0..2 out
+    uint32_t* g = a.data + (long long)c * a.group_stride + row;
+    uint32_t x[4][16];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int u = 0; u < 16; ++u) x[r][u] = valid ? g[r * KN + u * T + j] : 0u;
+    uint32_t* const lf[4] = {l0, l1, l2, l3};
+    fwd_rows<S, 4>(x, lf, j, tw, tw_mul, q, two_q);
+    uint32_t d[3][16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      d[0][u] = mont_mul(x[0][u], x[2][u], q, qneg);
+      d[1][u] = add_mod(mont_mul(x[0][u], x[3][u], q, qneg), mont_mul(x[1][u], x[2][u], q, qneg), q);
+      d[2][u] = mont_mul(x[1][u], x[3][u], q, qneg);
+    }
+    __syncthreads();  // every thread has read the forward exchange before it is overwritten
+    uint32_t* const li[3] = {l0, l1, l2};
+    inv_rows<S, 3>(d, li, j, itw, tw_mul, q, two_q);
+    if (valid) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int u = 0; u < 16; ++u) g[r * KN + u * T + j] = d[r][u];
+    }
+  } else if (MODE == 1) {  // relin: d2 row times the key's two rows, to out
+    const uint32_t* g = a.data + (long long)c * a.group_stride + row;
+    uint32_t* o = a.out + (long long)c * a.out_stride + row;
+    uint32_t x[1][16], k[2][16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) x[0][u] = valid ? g[u * T + j] : 0u;
+    uint32_t* const lf[1] = {l0};
+    fwd_rows<S, 1>(x, lf, j, tw, tw_mul, q, two_q);
+    const uint32_t* kb = a.key + row;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const long long e = 16 * j + u;
+      const uint32_t b = valid ? kb[e] : 0u, ak = valid ? kb[KN + e] : 0u;
+      k[0][u] = mont_mul(x[0][u], b, q, qneg);
+      k[1][u] = mont_mul(x[0][u], ak, q, qneg);
+    }
+    uint32_t* const li[2] = {l1, l2};  // buffers the forward exchange did not use
+    inv_rows<S, 2>(k, li, j, itw, tw_mul, q, two_q);
+    if (valid) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int u = 0; u < 16; ++u) o[r * KN + u * T + j] = k[r][u];
+    }
+  } else {  // ring: a times b, in place of a
+    uint32_t* ga = a.data + (long long)c * a.group_stride + row;
+    const uint32_t* gb = a.data2 + (long long)c * a.group_stride + row;
+    uint32_t x[2][16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      x[0][u] = valid ? ga[u * T + j] : 0u;
+      x[1][u] = valid ? gb[u * T + j] : 0u;
+    }
+    uint32_t* const lf[2] = {l0, l1};
+    fwd_rows<S, 2>(x, lf, j, tw, tw_mul, q, two_q);
+    uint32_t y[1][16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) y[0][u] = mont_mul(x[0][u], x[1][u], q, qneg);
+    uint32_t* const li[1] = {l2};
+    inv_rows<S, 1>(y, li, j, itw, tw_mul, q, two_q);
+    if (valid) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) ga[u * T + j] = y[0][u];
+    }
+  }
+}
+
+template <int S, int MODE>
+static hipError_t rows_fused(const RowsArgs& a, hipStream_t st) {
+  constexpr int n = 1 << S;
+  constexpr int NSUB = RowsShape<S>::NSUB;
+  const int nsub_total = (1 << a.logN) / n;
+  const int nwg = (nsub_total + NSUB - 1) / NSUB;
+  const int kx = (a.K + 7) / 8;
+  dim3 grid(8 * kx * a.cnum * nwg);
+  // algorithmic HBM bytes per (ciphertext, prime): tensor 4 rows in, 3 out; relin
+  // 1 + 2 key rows in, 2 out; ring 2 in, 1 out
+  const double rows = MODE == 0 ? 7.0 : (MODE == 1 ? 5.0 : 3.0);
+  Bracket br(KID_ROWS_FUSED, st, 4.0 * rows * a.cnum * a.K * (double)(1 << a.logN));
+  hipLaunchKernelGGL((rows_fused_kernel<S, MODE>), grid, dim3(128), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t rows_fused_s(int S, const RowsArgs& a, hipStream_t st) {
+  switch (S) {
+    case 5: return rows_fused<5, MODE>(a, st);
+    case 6: return rows_fused<6, MODE>(a, st);
+    case 7: return rows_fused<7, MODE>(a, st);
+    case 8: return rows_fused<8, MODE>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int S, bool INV, bool ROWS>
 static hipError_t ntt_pass(const NttArgs& a, int ntr, hipStream_t st) {
   constexpr int n = 1 << S;
@@ -242,13 +491,35 @@ static hipError_t ntt_pass_s(int S, const NttArgs& a, int ntr, hipStream_t st) {
   }
 }
 
+int ntt_split_cols(int logN, const Tuning& tu) { return tu.ntt_cols_first ? logN - logN / 2 : logN / 2; }
+
+hipError_t launch_ntt_cols(const NttArgs& a0, int ntr, bool inverse, hipStream_t st, const Tuning& tu) {
+  if (ntr <= 0) return hipSuccess;
+  if (ntr % a0.K != 0 || a0.per_group % a0.K != 0) return hipErrorInvalidValue;
+  NttArgs a = a0;
+  a.ntr = ntr;
+  const int s_cols = ntt_split_cols(a.logN, tu);
+  return inverse ? ntt_pass_s<true, false>(s_cols, a, ntr, st) : ntt_pass_s<false, false>(s_cols, a, ntr, st);
+}
+
+hipError_t launch_rows_fused(const RowsArgs& a, int mode, hipStream_t st, const Tuning& tu) {
+  if (a.cnum <= 0) return hipSuccess;
+  const int s_rows = a.logN - ntt_split_cols(a.logN, tu);
+  switch (mode) {
+    case ROWS_TENSOR: return rows_fused_s<0>(s_rows, a, st);
+    case ROWS_RELIN: return rows_fused_s<1>(s_rows, a, st);
+    case ROWS_RING: return rows_fused_s<2>(s_rows, a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_ntt(const NttArgs& a0, int ntr, bool inverse, hipStream_t st, const Tuning& tu) {
   if (ntr <= 0) return hipSuccess;
   if (ntr % a0.K != 0 || a0.per_group % a0.K != 0) return hipErrorInvalidValue;
   NttArgs a = a0;
   a.ntr = ntr;
   // the split groups the same stages differently and does not change the result
-  const int s_cols = tu.ntt_cols_first ? a.logN - a.logN / 2 : a.logN / 2;
+  const int s_cols = ntt_split_cols(a.logN, tu);
   const int s_rows = a.logN - s_cols;
   hipError_t e;
   if (!inverse) {
