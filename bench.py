@@ -26,9 +26,9 @@ sys.path.insert(0, ROOT)
 LOGN, LOGQ, LOGP, BITS = 16, 1555, 1555, 40
 PEAK_PRODUCTS = 256 * 64 * 2.4e9  # 32x32-bit products per second: 256 CUs x 64 lanes x 2.4 GHz
 PEAK_HBM = 8.0e12                  # bytes per second
-# The library reports each kernel's algorithmic work in the unit of its bound: word
-# products for the lift (integer-ALU bound), HBM bytes for every other kernel.
-ALU_KERNELS = {"lift"}
+# The library reports each kernel's algorithmic work as HBM bytes (what it must read
+# and write at least once); every kernel class is reported against the HBM peak.
+ALU_KERNELS = set()
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_n16_q1555_cnum4.json")
 
 

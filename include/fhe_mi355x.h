@@ -97,9 +97,9 @@ int fhe_ctx_reset_error(fhe_ctx* ctx);
  * totals); fhe_ctx_profile(ctx, 0) stops.  fhe_ctx_profile_read waits for the
  * recorded events and returns, for one kernel class, the summed event time (ms),
  * the summed algorithmic work and the number of launches (host outputs).  The
- * work is 32x32-bit word products for the lift (limb products), the NTT passes
- * (one constant product per butterfly) and the pointwise products, and HBM bytes
- * (residues read, limbs written) for the reconstruction.  Kernel classes:
+ * work is the kernel's algorithmic HBM bytes: every input element it must read and
+ * every output element it must write, once (limbs and residues of the lift and the
+ * reconstruction, transform rows of the NTT passes, ...).  Kernel classes:
  * 0 lift, 1 forward NTT column pass, 2 forward NTT row pass, 3 inverse NTT row
  * pass, 4 inverse NTT column pass, 5 pointwise, 6 reconstruction (CRT),
  * 7 relinearization compose, 8 rescale, 9 fused row pass (last forward NTT row

@@ -24,7 +24,7 @@ void set_recorder(EventRecorder* r) { g_rec = r; }
 long long kernel_launch_count() { return g_launches; }
 
 // Brackets one kernel launch with the recorder's events; `work` is the kernel's
-// algorithmic work: 32x32-bit word products for the lift, HBM bytes otherwise.
+// algorithmic HBM bytes (what it must read and write at least once).
 struct Bracket {
   int kid;
   hipStream_t s;
@@ -56,11 +56,14 @@ struct Bracket {
 
 __device__ __forceinline__ void ct_bfly(uint32_t& X, uint32_t& Y, uint2 w, uint32_t q,
                                         uint32_t two_q) {
-  // Lazy Cooley-Tukey butterfly: X, Y in [0, 4q) -> [0, 4q).
-  uint32_t x = csub(X, two_q);
-  uint32_t t = shoup_lazy(Y, w.x, w.y, q);
-  X = x + t;
-  Y = x - t + two_q;
+  // Lazy Cooley-Tukey butterfly: X, Y in [0, 4q) -> [0, 4q).  With the Shoup product
+  // t = Y w - qh q in [0, 2q), nt = qh q - Y w = -t (mod 2^32); then X + t = X - nt
+  // and X - t + 2q = X + nt + 2q (one three-input add).
+  const uint32_t x = csub(X, two_q);
+  const uint32_t qh = __umulhi(Y, w.y);
+  const uint32_t nt = qh * q - Y * w.x;
+  X = x - nt;
+  Y = x + nt + two_q;
 }
 
 __device__ __forceinline__ void gs_bfly(uint32_t& X, uint32_t& Y, uint2 w, uint32_t q,
@@ -711,8 +714,8 @@ hipError_t launch_lift(const LiftArgs& a, int npoly, hipStream_t st, const Tunin
   if (npoly <= 0) return hipSuccess;
   LiftArgs b = a;
   b.npoly = npoly;
-  // algorithmic work: L limb-constant products per (coefficient, prime)
-  Bracket br(KID_LIFT, st, (double)npoly * a.N * a.K * a.L);
+  // algorithmic HBM bytes: L limbs read and K residues written per coefficient
+  Bracket br(KID_LIFT, st, 4.0 * npoly * a.N * (double)(a.L + a.K));
   if (t.lift_primes == 0 && a.A) {
     // the table's k-block count: exact up to 16 (L <= 128), else padded to 32
     switch (b.nkb) {
@@ -869,23 +872,25 @@ __device__ __forceinline__ int64_t add_carry4(uint32_t (&o)[4], int64_t cin) {
   return cin;
 }
 
+constexpr int kCrtWaves = 8;  // waves per workgroup (one workgroup with its LDS table per CU)
+
 template <int NKB, bool LDSA>
-__global__ __launch_bounds__(512) void crt_kernel(CrtArgs a) {
+__global__ __launch_bounds__(64 * kCrtWaves) void crt_kernel(CrtArgs a) {
   extern __shared__ v4i sA[];
   __shared__ uint32_t s_q[32 * NKB], s_d[32 * NKB], s_r[32 * NKB];
   __shared__ uint32_t s_mneg[kCrtMaxLimbs], s_eneg[kCrtMaxLimbs];
-  for (int k = threadIdx.x; k < 32 * NKB; k += 512) {
+  for (int k = threadIdx.x; k < 32 * NKB; k += 64 * kCrtWaves) {
     const bool in = k < a.K;
     s_q[k] = in ? a.pc[k].q : 1u;
     s_d[k] = in ? a.d[k] : 0u;
     s_r[k] = in ? a.rq[k] : 0u;
   }
-  for (int l = threadIdx.x; l < 8 * a.ntiles; l += 512) {
+  for (int l = threadIdx.x; l < 8 * a.ntiles; l += 64 * kCrtWaves) {
     s_mneg[l] = a.mneg[l];
     s_eneg[l] = a.eneg[l];
   }
   if (LDSA)
-    for (int f = threadIdx.x; f < a.ntiles * NKB * 64; f += 512) sA[f] = a.A[f];
+    for (int f = threadIdx.x; f < a.ntiles * NKB * 64; f += 64 * kCrtWaves) sA[f] = a.A[f];
   __syncthreads();
   const v4i* At = LDSA ? sA : a.A;
   const int lane = threadIdx.x & 63, c = lane & 31, h = lane >> 5;
@@ -893,7 +898,7 @@ __global__ __launch_bounds__(512) void crt_kernel(CrtArgs a) {
   const long long total = (long long)a.npoly * groups;
   const int topbits = a.outbits - 32 * (a.Lout - 1);
   {
-    const long long unit = (long long)blockIdx.x * 8 + (threadIdx.x >> 6);
+    const long long unit = (long long)blockIdx.x * kCrtWaves + (threadIdx.x >> 6);
     if (unit >= total) return;  // after the only barrier
     const int z = (int)(unit / groups);
     const int j = (int)(unit % groups) * 32 + c;
@@ -1013,16 +1018,16 @@ template <int NKB>
 static void crt_launch(const CrtArgs& a, hipStream_t st) {
   const long long units = (long long)a.npoly * (a.N >> 5);
   const size_t lds = (size_t)a.ntiles * NKB * 64 * sizeof(v4i);
-  const unsigned grid = (unsigned)((units + 7) / 8);
+  const unsigned grid = (unsigned)((units + kCrtWaves - 1) / kCrtWaves);
   const size_t lds_static = 32 * NKB * 12 + 2 * kCrtMaxLimbs * 4;
   if (lds + lds_static <= (size_t)a.lds_max) {
     static bool attr = false;  // allow the full LDS of the device for this instantiation (once)
     if (!attr)
       attr = hipFuncSetAttribute((const void*)crt_kernel<NKB, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  a.lds_max - (int)lds_static) == hipSuccess;
-    hipLaunchKernelGGL((crt_kernel<NKB, true>), dim3(grid), dim3(512), lds, st, a);
+    hipLaunchKernelGGL((crt_kernel<NKB, true>), dim3(grid), dim3(64 * kCrtWaves), lds, st, a);
   } else {
-    hipLaunchKernelGGL((crt_kernel<NKB, false>), dim3(grid), dim3(512), 0, st, a);
+    hipLaunchKernelGGL((crt_kernel<NKB, false>), dim3(grid), dim3(64 * kCrtWaves), 0, st, a);
   }
 }
 
