@@ -104,7 +104,7 @@ int fhe_ctx_reset_error(fhe_ctx* ctx);
  * pass, 4 inverse NTT column pass, 5 pointwise, 6 reconstruction (CRT),
  * 7 relinearization compose, 8 rescale, 9 fused row pass (last forward NTT row
  * pass + pointwise products + first inverse row pass, used by the HE-mult and the
- * ring multiply).  Errors: FHE_E_INVAL, FHE_E_STATE (not recording). */
+ * ring multiply), 10 compose and rescale in one pass (HE-mult with rescale).  Errors: FHE_E_INVAL, FHE_E_STATE (not recording). */
 int fhe_ctx_profile(fhe_ctx* ctx, int enable);
 int fhe_ctx_profile_read(fhe_ctx* ctx, int kernel, double* ms, double* work, long long* launches);
 

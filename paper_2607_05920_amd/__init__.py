@@ -173,7 +173,7 @@ class Context:
         return self._h
 
     KERNELS = ["lift", "ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "pointwise", "garner",
-               "compose", "rescale", "ntt_rows_fused"]
+               "compose", "rescale", "ntt_rows_fused", "compose_rescale"]
 
     def profile(self, enable: bool):
         _check("fhe_ctx_profile", load_library().fhe_ctx_profile(self._h, int(enable)))

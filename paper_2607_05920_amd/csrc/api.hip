@@ -275,7 +275,7 @@ struct PlanCell {
 struct fhe_plan {
   fhe_ctx* ctx = nullptr;
   std::vector<PlanCell> cells;
-  uint32_t *ws = nullptr, *stage = nullptr;
+  uint32_t* ws = nullptr;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -701,11 +701,10 @@ struct PipeIO {
   uint32_t* const* outs = nullptr;       // device: out0s, out1s (2 cnum pointers)
 };
 
-// Scratch words of one pipeline run (main area, staging of the relinearized
-// ciphertexts before rescale).
+// Scratch words of one pipeline run.
 struct PipeSize {
   int Kt = 0, Kr = 0, L = 0, LK = 0;
-  long long main_words = 0, stage_words = 0;
+  long long main_words = 0;
 };
 
 PipeSize pipe_size(const fhe_ctx* c, const fhe_evk* k, int logN, int logq, int cnum) {
@@ -717,15 +716,14 @@ PipeSize pipe_size(const fhe_ctx* c, const fhe_evk* k, int logN, int logq, int c
   z.Kr = primes_for_e(c, logN + 2 * logq + k->logP);
   if (z.Kt < 0 || z.Kr < 0) return z;
   z.main_words = (long long)cnum * NN * (4LL * z.Kt + 3LL * z.L + z.Kr + 2LL * z.Kr + 2LL * z.LK);
-  z.stage_words = 2LL * cnum * z.L * NN;
   return z;
 }
 
-// The HE-mult pipeline: lift, NTT, tensor products, iNTT, Garner (d0, d1, d2 mod
-// 2^logq); lift d2, NTT, products with the resident key, iNTT, Garner (k0, k1 mod
-// 2^(logP+logq)); c_i = [d_i + R(k_i)]_(2^logq); then, if bits > 0, the rescale.
+// The HE-mult pipeline: lift, NTT, tensor products, iNTT, CRT (d0, d1, d2 mod
+// 2^logq); lift d2, NTT, products with the resident key, iNTT, CRT (k0, k1 mod
+// 2^(logP+logq)); c_i = [d_i + R(k_i)]_(2^logq), rescaled in the same pass if bits > 0.
 int pipeline(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, const PipeIO& io, int cnum, hipStream_t st,
-             uint32_t* ws, uint32_t* stage, const Tuning& tu) {
+             uint32_t* ws, const Tuning& tu) {
   const int N = 1 << logN;
   const PipeSize z = pipe_size(c, k, logN, logq, cnum);
   if (z.Kt < 0 || z.Kr < 0) return FHE_E_RANGE;
@@ -801,17 +799,13 @@ int pipeline(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, const PipeIO&
     ca.kstride = (long long)LK * NN;
     ca.d = Dl;
     ca.dstride = polyw;
-    if (bits > 0) {
-      ca.out0 = stage;
-      ca.out1 = stage + (long long)cnum * polyw;
-      ca.ostride = polyw;
-    } else if (io.outs) {
+    if (io.outs) {
       ca.out0s = io.outs;
       ca.out1s = io.outs + cnum;
     } else {
       ca.out0 = io.out0;
       ca.out1 = io.out1;
-      ca.ostride = polyw;
+      ca.ostride = (long long)((logq - bits + 31) / 32) * NN;  // polyw when there is no rescale
     }
     ca.N = N;
     ca.L = L;
@@ -824,32 +818,10 @@ int pipeline(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, const PipeIO&
       ca.invP = (uint32_t)invmod(powmod(2, logP, k->t), k->t);
       ca.pw = pwt;
     }
-    e = launch_compose(ca, cnum, st);
-  }
-  // 12. rescale into the outputs
-  if (e == hipSuccess && bits > 0) {
-    RescaleArgs ra{};
-    ra.in0 = stage;
-    ra.in1 = stage + (long long)cnum * polyw;
-    ra.istride = polyw;
-    if (io.outs) {
-      ra.out0s = io.outs;
-      ra.out1s = io.outs + cnum;
-    } else {
-      ra.out0 = io.out0;
-      ra.out1 = io.out1;
-      ra.ostride = (long long)((logq - bits + 31) / 32) * NN;
-    }
-    ra.N = N;
-    ra.logq = logq;
-    ra.bits = bits;
-    ra.scheme = k->scheme;
-    if (k->scheme == FHE_BGV) {
-      ra.t = k->t;
-      ra.invB = (uint32_t)invmod(powmod(2, bits, k->t), k->t);
-      ra.pw = pwt;
-    }
-    e = launch_rescale(ra, cnum, st);
+    // 12. with a rescale, both in one pass: the relinearized c_i is never stored
+    ca.bits = bits;
+    if (bits > 0 && k->scheme == FHE_BGV) ca.invB = (uint32_t)invmod(powmod(2, bits, k->t), k->t);
+    e = bits > 0 ? launch_compose_rescale(ca, cnum, st) : launch_compose(ca, cnum, st);
   }
   return set_sticky(c, e);
 }
@@ -864,12 +836,7 @@ int mul_relin_locked(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, const
   hipError_t e = hipSuccess;
   uint32_t* ws = (uint32_t*)scratch(c, st, 0, (size_t)z.main_words * 4, &e);
   if (!ws) return set_sticky(c, e);
-  uint32_t* stage = nullptr;
-  if (bits > 0) {
-    stage = (uint32_t*)scratch(c, st, 1, (size_t)z.stage_words * 4, &e);
-    if (!stage) return set_sticky(c, e);
-  }
-  return pipeline(c, k, logN, logq, bits, io, cnum, st, ws, stage, Tuning());
+  return pipeline(c, k, logN, logq, bits, io, cnum, st, ws, Tuning());
 }
 
 int rescale_locked(fhe_ctx* c, int scheme, uint32_t t, int logN, int logq, int bits,
@@ -903,8 +870,8 @@ int plan_run_cells(fhe_plan* pl, hipStream_t st) {
     PipeIO io;
     io.ins = cell.ptrs;
     io.outs = cell.ptrs + 4LL * cell.cnum;
-    const int rc = pipeline(pl->ctx, cell.evk, cell.logN, cell.logq, cell.bits, io, cell.cnum, st, pl->ws,
-                            pl->stage, cell.tune);
+    const int rc =
+        pipeline(pl->ctx, cell.evk, cell.logN, cell.logq, cell.bits, io, cell.cnum, st, pl->ws, cell.tune);
     if (rc != FHE_OK) return rc;
   }
   return FHE_OK;
@@ -945,10 +912,10 @@ int plan_autotune(fhe_plan* pl, PlanCell& cell, hipStream_t st) {
   int rc = FHE_OK;
   for (const Tuning& t : cands) {
     float ts[3];
-    rc = pipeline(c, cell.evk, cell.logN, cell.logq, cell.bits, io, cell.cnum, st, pl->ws, pl->stage, t);
+    rc = pipeline(c, cell.evk, cell.logN, cell.logq, cell.bits, io, cell.cnum, st, pl->ws, t);
     for (int r = 0; r < 3 && rc == FHE_OK; ++r) {
       hipEventRecord(e0, st);
-      rc = pipeline(c, cell.evk, cell.logN, cell.logq, cell.bits, io, cell.cnum, st, pl->ws, pl->stage,
+      rc = pipeline(c, cell.evk, cell.logN, cell.logq, cell.bits, io, cell.cnum, st, pl->ws,
                     t);
       hipEventRecord(e1, st);
       if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ts[r], e0, e1) != hipSuccess)
@@ -975,7 +942,7 @@ void plan_free(fhe_plan* pl) {
   if (pl->cap) hipStreamDestroy(pl->cap);
   for (PlanCell& cell : pl->cells)
     if (cell.ptrs) hipFree(cell.ptrs);
-  for (void* p : {(void*)pl->ws, (void*)pl->stage})
+  for (void* p : {(void*)pl->ws})
     if (p) hipFree(p);
   delete pl;
 }
@@ -1000,9 +967,9 @@ struct SrvLater {
   }
 };
 
-// Scratch words one batch needs (main workspace, rescale staging).
+// Scratch words one batch needs.
 struct SrvNeed {
-  long long main = 0, stage = 0;
+  long long main = 0;
 };
 
 // One worker stream with its own scratch and pointer staging.
@@ -1012,8 +979,8 @@ struct SrvSlot {
   bool busy = false;
   std::vector<SrvReq> reqs;
   uint64_t t_start = 0;
-  uint32_t *ws = nullptr, *stage = nullptr;
-  long long ws_words = 0, stage_words = 0;
+  uint32_t* ws = nullptr;
+  long long ws_words = 0;
   const uint32_t** hptr = nullptr;  // pinned host staging of the pointer arrays
   uint32_t** dptr = nullptr;        // device pointer arrays (6 max_batch)
 };
@@ -1041,25 +1008,23 @@ SrvNeed batch_need(const fhe_ctx* c, const fhe_job& j, int cnum) {
   const PipeSize z = pipe_size(c, j.evk, j.evk->logN, j.logq, cnum);
   SrvNeed n;
   n.main = z.main_words;
-  n.stage = j.bits > 0 ? z.stage_words : 0;
   return n;
 }
 
-size_t need_bytes(const SrvNeed& n) { return (size_t)(n.main + n.stage) * 4; }
+size_t need_bytes(const SrvNeed& n) { return (size_t)n.main * 4; }
 
-size_t slot_held(const SrvSlot& s) { return (size_t)(s.ws_words + s.stage_words) * 4; }
+size_t slot_held(const SrvSlot& s) { return (size_t)s.ws_words * 4; }
 
 // Bytes the slot holds once grown for `n`.
 size_t slot_after(const SrvSlot& s, const SrvNeed& n) {
-  return (size_t)(std::max(s.ws_words, n.main) + std::max(s.stage_words, n.stage)) * 4;
+  return (size_t)std::max(s.ws_words, n.main) * 4;
 }
 
 // Frees an idle slot's scratch (its last batch has completed).
 void slot_release(SrvSlot& s) {
   hipStreamSynchronize(s.st);
-  for (uint32_t** p : {&s.ws, &s.stage})
-    if (*p) hipFree(*p), *p = nullptr;
-  s.ws_words = s.stage_words = 0;
+  if (s.ws) hipFree(s.ws), s.ws = nullptr;
+  s.ws_words = 0;
 }
 
 }  // namespace
@@ -1094,7 +1059,6 @@ int srv_launch(fhe_server* sv, SrvSlot& sl, std::vector<SrvReq>& reqs, const Srv
   int rc = evk_prepare_locked(j0.evk, j0.logq, sl.st);
   if (rc != FHE_OK) return rc;
   hipError_t e = grow(&sl.ws, &sl.ws_words, need.main, sl.st);
-  if (e == hipSuccess) e = grow(&sl.stage, &sl.stage_words, need.stage, sl.st);
   if (e != hipSuccess) return set_sticky(c, e);
   // the previous batch of this slot has completed, so its staging may be rewritten
   for (int m = 0; m < cnum; ++m) {
@@ -1111,7 +1075,7 @@ int srv_launch(fhe_server* sv, SrvSlot& sl, std::vector<SrvReq>& reqs, const Srv
   PipeIO io;
   io.ins = sl.dptr;
   io.outs = sl.dptr + 4LL * cnum;
-  rc = pipeline(c, j0.evk, j0.evk->logN, j0.logq, j0.bits, io, cnum, sl.st, sl.ws, sl.stage, Tuning());
+  rc = pipeline(c, j0.evk, j0.evk->logN, j0.logq, j0.bits, io, cnum, sl.st, sl.ws, Tuning());
   if (rc != FHE_OK) return rc;
   return set_sticky(c, hipEventRecord(sl.done, sl.st));
 }
@@ -1755,7 +1719,7 @@ int fhe_batch_plan(fhe_ctx* c, const fhe_job* jobs, int njobs, int flags, void* 
     members[ci].push_back(i);
   }
   int rc = FHE_OK;
-  long long mw = 0, sw = 0;
+  long long mw = 0;
   for (size_t ci = 0; ci < pl->cells.size() && rc == FHE_OK; ++ci) {
     PlanCell& cell = pl->cells[ci];
     cell.cnum = (int)members[ci].size();
@@ -1776,7 +1740,6 @@ int fhe_batch_plan(fhe_ctx* c, const fhe_job* jobs, int njobs, int flags, void* 
       break;
     }
     mw = std::max(mw, z.main_words);
-    sw = std::max(sw, z.stage_words);
     std::vector<const uint32_t*> h(6 * (size_t)cell.cnum);
     for (int m = 0; m < cell.cnum; ++m) {
       const fhe_job& j = jobs[members[ci][m]];
@@ -1793,7 +1756,6 @@ int fhe_batch_plan(fhe_ctx* c, const fhe_job* jobs, int njobs, int flags, void* 
   }
   if (rc == FHE_OK) {
     hipError_t e = hipMalloc((void**)&pl->ws, (size_t)std::max(mw, 1LL) * 4);
-    if (e == hipSuccess) e = hipMalloc((void**)&pl->stage, (size_t)std::max(sw, 1LL) * 4);
     if (e != hipSuccess) rc = set_sticky(c, e);
   }
   if (rc == FHE_OK && (flags & FHE_PLAN_AUTOTUNE)) {
@@ -1945,7 +1907,7 @@ void fhe_server_destroy(fhe_server* sv) {
   hipSetDevice(sv->ctx->device);
   for (SrvSlot& sl : sv->slots) {
     if (sl.st) hipStreamSynchronize(sl.st);
-    for (void* p : {(void*)sl.ws, (void*)sl.stage, (void*)sl.dptr})
+    for (void* p : {(void*)sl.ws, (void*)sl.dptr})
       if (p) hipFree(p);
     if (sl.hptr) hipHostFree(sl.hptr);
     if (sl.done) hipEventDestroy(sl.done);

@@ -109,6 +109,8 @@ struct ComposeArgs {
   int N = 0, L = 0, LK = 0, logq = 0, logP = 0, scheme = 0;
   uint32_t t = 0, invP = 0;  // BGV: t and 2^-logP mod t
   const uint32_t* pw = nullptr; // BGV: pw[l] = 2^(32 l) mod t
+  int bits = 0;              // compose + rescale: rescale bits (outputs hold logq - bits bits)
+  uint32_t invB = 0;         // BGV: 2^-bits mod t
 };
 
 struct RescaleArgs {
@@ -137,6 +139,7 @@ enum KernelId {
   KID_COMPOSE,
   KID_RESCALE,
   KID_ROWS_FUSED,
+  KID_COMPOSE_RESCALE,
   KID_COUNT
 };
 
@@ -168,6 +171,7 @@ hipError_t launch_ring_pointwise(const PointwiseArgs& a, int cnum, hipStream_t s
 hipError_t launch_crt(CrtArgs a, int npoly, hipStream_t s);
 hipError_t launch_compose(const ComposeArgs& a, int cnum, hipStream_t s);
 hipError_t launch_rescale(const RescaleArgs& a, int cnum, hipStream_t s);
+hipError_t launch_compose_rescale(const ComposeArgs& a, int cnum, hipStream_t s);
 hipError_t launch_small_to_limbs(const int8_t* v, uint32_t* out, int N, int L, uint32_t topmask, hipStream_t s);
 hipError_t launch_mask_rows(const uint32_t* in, uint32_t* out, int N, int L, uint32_t topmask, hipStream_t s);
 hipError_t launch_add_small(const uint32_t* x, const uint32_t* y, const int32_t* e, long long mult, uint32_t* out,

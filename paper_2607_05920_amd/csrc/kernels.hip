@@ -54,6 +54,14 @@ struct Bracket {
 // {16 j + u} ("contiguous"); one LDS exchange connects them.  Forward passes run
 // strided then contiguous; inverse passes the reverse.
 
+// Low 32 bits of a b + c in one v_mad_u64_u32 (the compiler would otherwise narrow
+// the expression to a 32-bit multiply and an add).
+__device__ __forceinline__ uint32_t mad_lo(uint32_t a, uint32_t b, uint32_t c) {
+  uint64_t r;
+  asm("v_mad_u64_u32 %0, vcc, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"((uint64_t)c) : "vcc");
+  return (uint32_t)r;
+}
+
 __device__ __forceinline__ void ct_bfly(uint32_t& X, uint32_t& Y, uint2 w, uint32_t q,
                                         uint32_t two_q) {
   // Lazy Cooley-Tukey butterfly: X, Y in [0, 4q) -> [0, 4q).  With the Shoup product
@@ -68,10 +76,13 @@ __device__ __forceinline__ void ct_bfly(uint32_t& X, uint32_t& Y, uint2 w, uint3
 
 __device__ __forceinline__ void gs_bfly(uint32_t& X, uint32_t& Y, uint2 w, uint32_t q,
                                         uint32_t two_q) {
-  // Lazy Gentleman-Sande butterfly: X, Y in [0, 2q) -> [0, 2q).
-  uint32_t x = X, y = Y;
+  // Lazy Gentleman-Sande butterfly: X, Y in [0, 2q) -> [0, 2q); the Shoup product of
+  // d = X - Y + 2q is d w - qh q = d w + qh (-q), one multiply-add.
+  const uint32_t x = X, y = Y;
   X = csub(x + y, two_q);
-  Y = shoup_lazy(x - y + two_q, w.x, w.y, q);
+  const uint32_t d = x - y + two_q;
+  const uint32_t qh = __umulhi(d, w.y);
+  Y = mad_lo(qh, 0u - q, d * w.x);
 }
 
 template <int S, bool INV, bool ROWS>
@@ -381,7 +392,8 @@ __global__ __launch_bounds__(128) void rows_fused_kernel(RowsArgs a) {
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       d[0][u] = mont_mul(x[0][u], x[2][u], q, qneg);
-      d[1][u] = add_mod(mont_mul(x[0][u], x[3][u], q, qneg), mont_mul(x[1][u], x[2][u], q, qneg), q);
+      // canonical inputs: x0 y1 + x1 y0 < 2 q^2 < q 2^32, one Montgomery reduction
+      d[1][u] = csub(redc_lazy(mad64(x[0][u], x[3][u], mad64(x[1][u], x[2][u], 0)), q, qneg), q);
       d[2][u] = mont_mul(x[1][u], x[3][u], q, qneg);
     }
     __syncthreads();  // every thread has read the forward exchange before it is overwritten
@@ -1105,6 +1117,78 @@ __global__ __launch_bounds__(256) void compose_kernel(ComposeArgs a) {
   }
 }
 
+// compose and rescale in one pass (a HE-mult with rescale): c = [d + R_P(k)]_(2^logq)
+// is produced limb by limb and never stored; the rescale's correction is collected
+// from its low limbs as they appear (the round bit, or (c mod 2^bits) mod t), and
+// output limb m of [R_B(c)]_(2^(logq - bits)) is emitted once c limbs sb + m and
+// sb + m + 1 exist (sb = bits / 32).
+__global__ __launch_bounds__(256) void compose_rescale_kernel(ComposeArgs a) {
+  const int jc = blockIdx.x * 256 + threadIdx.x;
+  const int z = blockIdx.y;  // 2 c + i
+  if (jc >= a.N) return;
+  const int c = z >> 1, i = z & 1;
+  const uint32_t* k = a.k + (long long)z * a.kstride + jc;
+  const uint32_t* d = a.d + (long long)(3 * c + i) * a.dstride + jc;
+  uint32_t* o = (a.out0s ? (i ? a.out1s[c] : a.out0s[c]) : (i ? a.out1 : a.out0) + (long long)c * a.ostride) + jc;
+  // compose state
+  const int64_t corrP = round_correction(k, a.N, a.LK, a.logP, a.scheme, a.t, a.invP, a.pw);
+  const int sl = a.logP >> 5, rs = a.logP & 31;
+  const uint32_t extP = corrP < 0 ? 0xFFFFFFFFu : 0u;
+  uint64_t carryP = 0;
+  uint32_t klo = sl < a.LK ? k[(long long)sl * a.N] : 0u;
+  const int topbits = a.logq - 32 * (a.L - 1);
+  // rescale state
+  const int sb = a.bits >> 5, rb = a.bits & 31;
+  const int newq = a.logq - a.bits, Lout = (newq + 31) >> 5, otop = newq - 32 * (Lout - 1);
+  uint64_t acc = 0;  // BGV: (c mod 2^bits) mod t, accumulated per limb
+  uint32_t rbit = 0;  // CKKS: bit bits-1 of c
+  int64_t corrB = 0;
+  uint32_t extB = 0, cprev = 0;
+  uint64_t carryB = 0;
+  auto emit = [&](int m, uint32_t xs) {
+    const uint32_t cl = m == 0 ? (uint32_t)corrB : extB;
+    const uint64_t sum = (uint64_t)xs + cl + carryB;
+    uint32_t w = (uint32_t)sum;
+    carryB = sum >> 32;
+    if (m == Lout - 1 && otop < 32) w &= (1u << otop) - 1u;
+    o[(long long)m * a.N] = w;
+  };
+  for (int l = 0; l < a.L; ++l) {
+    const uint32_t khi = (sl + l + 1 < a.LK) ? k[(long long)(sl + l + 1) * a.N] : 0u;
+    const uint32_t ks = rs ? ((klo >> rs) | (khi << (32 - rs))) : klo;
+    klo = khi;
+    const uint32_t cp = l == 0 ? (uint32_t)corrP : extP;
+    const uint64_t sum = (uint64_t)d[(long long)l * a.N] + ks + cp + carryP;
+    uint32_t cv = (uint32_t)sum;
+    carryP = sum >> 32;
+    if (l == a.L - 1 && topbits < 32) cv &= (1u << topbits) - 1u;
+    // the rescale's correction from the low bits of c
+    if (a.scheme == 0) {
+      if (l == ((a.bits - 1) >> 5)) rbit = (cv >> ((a.bits - 1) & 31)) & 1u;
+    } else if (l < sb) {
+      acc += (uint64_t)cv * a.pw[l];
+    } else if (l == sb && rb) {
+      acc += (uint64_t)(cv & ((1u << rb) - 1u)) * a.pw[sb];
+    }
+    if (l == sb) {
+      if (a.scheme == 0) {
+        corrB = rbit;
+      } else {
+        const uint64_t rr = (acc % a.t) * a.invB % a.t;
+        corrB = (2 * rr > a.t) ? (int64_t)rr - (int64_t)a.t : (int64_t)rr;
+      }
+      extB = corrB < 0 ? 0xFFFFFFFFu : 0u;
+    }
+    if (l > sb) {
+      const int m = l - sb - 1;
+      if (m < Lout) emit(m, rb ? ((cprev >> rb) | (cv << (32 - rb))) : cprev);
+    }
+    if (l >= sb) cprev = cv;
+  }
+  const int m = a.L - sb - 1;  // the last output limb takes zeros above c
+  if (m >= 0 && m < Lout) emit(m, rb ? (cprev >> rb) : cprev);
+}
+
 __global__ __launch_bounds__(256) void rescale_kernel(RescaleArgs a) {
   const int jc = blockIdx.x * 256 + threadIdx.x;
   const int z = blockIdx.y;
@@ -1139,6 +1223,15 @@ hipError_t launch_compose(const ComposeArgs& a, int cnum, hipStream_t st) {
   dim3 grid((a.N + 255) / 256, 2 * cnum);
   Bracket br(KID_COMPOSE, st, 8.0 * cnum * a.N * (double)(a.LK + 2 * a.L));  // bytes: k_i, d_i in, c_i out
   hipLaunchKernelGGL(compose_kernel, grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_compose_rescale(const ComposeArgs& a, int cnum, hipStream_t st) {
+  dim3 grid((a.N + 255) / 256, 2 * cnum);
+  // bytes: k_i and d_i in, the rescaled c_i out
+  Bracket br(KID_COMPOSE_RESCALE, st,
+             8.0 * cnum * a.N * (double)(a.LK + a.L + ((a.logq - a.bits + 31) >> 5)));
+  hipLaunchKernelGGL(compose_rescale_kernel, grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

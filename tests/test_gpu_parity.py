@@ -210,6 +210,29 @@ def test_he_mult_cfg2_encrypted(ctx, sch, t, bits):
         assert np.max(np.abs(z - z1 * z2)) <= 2.0 ** -20
 
 
+@pytest.mark.parametrize("sch,t,bits", [(scheme.CKKS, 0, 1), (scheme.CKKS, 0, 31), (scheme.CKKS, 0, 32),
+                                        (scheme.CKKS, 0, 33), (scheme.CKKS, 0, 64), (scheme.CKKS, 0, 73),
+                                        (scheme.CKKS, 0, 150), (scheme.BGV, 65537, 1), (scheme.BGV, 65537, 64),
+                                        (scheme.BGV, 1001, 73), (scheme.BGV, 65537, 150)])
+def test_fused_rescale_equals_separate(ctx, sch, t, bits):
+    """The one-pass relinearization + rescale gives the same bits as fhe_mul_relin then
+    fhe_rescale (uniform inputs, N = 2^10, logq = 181, logP = 200; rescale widths below,
+    at and above limb boundaries, up to logq - 31), and matches the oracle."""
+    say(f"fused vs separate rescale {sch} bits={bits}")
+    rk, rm, _, _ = synth.streams(80 + bits)
+    logN, logq, logP = 10, 181, 200
+    N = 1 << logN
+    x, y = random_ct(rm, logN, logq), random_ct(rm, logN, logq)
+    eb, ea = synth.uniform_limbs(rk, logq + logP, N), synth.uniform_limbs(rk, logq + logP, N)
+    f0, f1 = _gpu_he_mult(ctx, (eb, ea), sch, t, logN, logq, logP, x, y, bits, fused=True)
+    s0, s1 = _gpu_he_mult(ctx, (eb, ea), sch, t, logN, logq, logP, x, y, bits, fused=False)
+    assert np.array_equal(f0, s0) and np.array_equal(f1, s1)
+    want = scheme.mult_rescale(oracle_ct(*x, logN, logq, sch, t), oracle_ct(*y, logN, logq, sch, t),
+                               scheme.EvalKey(ints(eb), ints(ea), logN, logq, logP, sch, t), bits)
+    check(ints(f0), want.c0, "c0")
+    check(ints(f1), want.c1, "c1")
+
+
 @pytest.mark.parametrize("sch,t,bits", [(scheme.CKKS, 0, 40), (scheme.BGV, 65537, 32)])
 def test_he_mult_cfg3_sampled(ctx, sch, t, bits):
     """N = 2^16, logq = logP = 1555 (49 limbs; key 98 limbs): uniformly random
