@@ -375,6 +375,16 @@ void negate_trunc(std::vector<uint32_t>& r) {
   }
 }
 
+// r += x mod 2^(32 n) in place (equal lengths).
+void add_trunc(std::vector<uint32_t>& r, const std::vector<uint32_t>& x) {
+  uint64_t carry = 0;
+  for (size_t i = 0; i < r.size(); ++i) {
+    const uint64_t t = (uint64_t)r[i] + x[i] + carry;
+    r[i] = (uint32_t)t;
+    carry = t >> 32;
+  }
+}
+
 // Tables of the K-prime CRT reconstruction with offset 2^e into Lout output limbs.
 const CrtTab* crt_table(fhe_ctx* c, int K, int e, int Lout, hipError_t* err) {
   const auto key = std::make_tuple(K, e, Lout);
@@ -390,13 +400,16 @@ const CrtTab* crt_table(fhe_ctx* c, int K, int e, int Lout, hipError_t* err) {
   t.ntiles = ntiles;
   std::vector<uint32_t> d(c->Kpad, 0);
   for (int k = 0; k < K; ++k) d[k] = (uint32_t)mulmod64(powmod(2, e, c->q[k]), ck[k], c->q[k]);
-  // V_k = (M / q_k) mod 2^(32 Lout) in balanced limbs D_kl in [-0x80808080, 0x7F7F7F7F]
+  // V_k = (M / q_k) mod 2^(32 Lout) in balanced limbs D_kl in [-0x80808080, 0x7F7F7F7F];
+  // vsum = sum_k V_k mod 2^(32 Lout)
   std::vector<int64_t> D((size_t)K * Lp, 0);
+  std::vector<uint32_t> vsum(Lout, 0);
   for (int k = 0; k < K; ++k) {
     std::vector<uint32_t> v(Lout, 0);
     v[0] = 1;
     for (int j = 0; j < K; ++j)
       if (j != k) mul_small_trunc(v, c->q[j]);
+    add_trunc(vsum, v);
     int64_t carry = 0;
     for (int l = 0; l < Lout; ++l) {
       const int64_t u = (int64_t)v[l] + carry;
@@ -429,11 +442,14 @@ const CrtTab* crt_table(fhe_ctx* c, int K, int e, int Lout, hipError_t* err) {
   mneg[0] = 1;
   for (int j = 0; j < K; ++j) mul_small_trunc(mneg, c->q[j]);
   negate_trunc(mneg);
+  // [0x80808080 sum_k V_k - 2^e]: the digits of y_k ^ 0x80808080 stand for y_k - 0x80808080
   std::vector<uint32_t> eneg(Lout, 0);
   if (e < 32 * Lout) {
     eneg[e >> 5] = 1u << (e & 31);
     negate_trunc(eneg);
   }
+  mul_small_trunc(vsum, 0x80808080u);
+  add_trunc(eneg, vsum);
   mneg.resize(Lp, 0);
   eneg.resize(Lp, 0);
   *err = upload(&t.A, A);

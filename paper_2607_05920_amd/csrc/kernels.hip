@@ -18,6 +18,61 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 // at a time).
 __device__ __forceinline__ void opaque(uint32_t& v) { asm volatile("" : "+v"(v)); }
 
+// A pointer the caller knows to be equal on every lane of the wave, moved to scalar
+// registers: buffer resources need it there, and stores through it take the scalar
+// base + 32-bit lane offset form (no 64-bit address arithmetic per lane).
+template <typename T>
+__device__ __forceinline__ T* wave_uniform(T* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (T*)(((uint64_t)hi << 32) | lo);
+}
+
+// Raw buffer over `bytes` bytes from the wave-uniform `base`.  Loads at lane offsets at
+// or beyond `bytes` return zero (the buffer range check), which stands in for clamping
+// and masking rows past the end of a polynomial.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_buffer(const uint32_t* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ uint32_t buffer_word(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0);
+}
+
+// Global store at a byte offset from a wave-uniform base (the global address space is
+// stated: the pointer's provenance is lost through the scalar move).
+__device__ __forceinline__ void store_at(uint32_t* base, uint32_t byte_off, uint32_t v) {
+  typedef __attribute__((address_space(1))) char gchar;
+  typedef __attribute__((address_space(1))) uint32_t gu32;
+  *(gu32*)((gchar*)base + byte_off) = v;
+}
+
+// a * b + c as one v_mad_i64_i32.  b must be opaque (a register the compiler cannot
+// see the value of), or the product is strength-reduced into shifts and adds; and two
+// terms of one sum must not share a multiplier register, or the compiler merges them
+// into a 64 x 64-bit product.  (Not inline asm: a compiler-visible instruction gets
+// the wait states after the matrix-core op that produced its operand.)
+__device__ __forceinline__ int64_t mad_i64(int32_t a, uint32_t b, int64_t c) { return (int64_t)a * (int32_t)b + c; }
+
+// o += cin over 4 limbs (unsigned words, least significant first), cin signed 64-bit:
+// one add-with-carry chain over (cin_lo, cin_hi, ext, ext), ext the sign extension.
+// Returns the signed carry out of the top limb, in {-1, 0, 1}.
+__device__ __forceinline__ int32_t add_carry4(uint32_t (&o)[4], int64_t cin) {
+  const uint32_t lo = (uint32_t)cin, hi = (uint32_t)((uint64_t)cin >> 32);
+  const uint32_t ext = (uint32_t)((int32_t)hi >> 31);
+  uint32_t co;
+  asm("v_add_co_u32 %0, vcc, %0, %5\n\t"
+      "v_addc_co_u32 %1, vcc, %1, %6, vcc\n\t"
+      "v_addc_co_u32 %2, vcc, %2, %7, vcc\n\t"
+      "v_addc_co_u32 %3, vcc, %3, %7, vcc\n\t"
+      "v_addc_co_u32 %4, vcc, 0, %7, vcc"
+      : "+v"(o[0]), "+v"(o[1]), "+v"(o[2]), "+v"(o[3]), "=&v"(co)
+      : "v"(lo), "v"(hi), "v"(ext)
+      : "vcc");
+  return (int32_t)co;
+}
+
 static thread_local EventRecorder* g_rec = nullptr;
 static thread_local long long g_launches = 0;
 void set_recorder(EventRecorder* r) { g_rec = r; }
@@ -643,37 +698,31 @@ __global__ __launch_bounds__(BLK) void lift_mfma_kernel(LiftArgs a) {
     s_ohi[p] = (uint32_t)(o >> 32);
   }
   __syncthreads();
-  uint32_t m8 = 256, m16 = 65536, m24 = 16777216;  // not foldable into shifts
+  uint32_t one = 1, m8 = 256, m16 = 65536, m24 = 16777216;  // opaque multipliers of mad_i64
+  opaque(one);
   opaque(m8);
   opaque(m16);
   opaque(m24);
   const v4i* At = LDSA ? sA : a.A;
   const int lane = threadIdx.x & 63, c = lane & 31, h = lane >> 5;
-  const int groups = a.N >> 5;
-  const long long total = (long long)a.npoly * groups;
-  for (long long unit = (long long)blockIdx.x * (BLK / 64) + (threadIdx.x >> 6); unit < total;
-       unit += (long long)gridDim.x * (BLK / 64)) {
-    const int z = (int)(unit / groups);
-    const int j = (int)(unit % groups) * 32 + c;
-    const uint32_t* src = (a.in_ptrs ? a.in_ptrs[z] : a.limbs + (long long)z * a.in_stride) + j;
-    // all limb loads issue together (index clamped to L - 1, value masked)
-    uint32_t w[NKB][4];
-#pragma unroll
-    for (int kb = 0; kb < NKB; ++kb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) w[kb][r] = src[(long long)min(8 * kb + 4 * h + r, a.L - 1) * a.N];
+  const int lg = __builtin_ctz((unsigned)a.N) - 5;  // log2 of the 32-coefficient groups per poly
+  const uint32_t total = (uint32_t)a.npoly << lg;
+  const uint32_t row = 4u * (uint32_t)a.N;          // bytes between limb (or residue) rows
+  const uint32_t lane_off = 4u * h * row + 4u * c;  // row 4 h, column c of a 32-coefficient group
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (uint32_t unit = blockIdx.x * (BLK / 64) + wave; unit < total; unit += gridDim.x * (BLK / 64)) {
+    const uint32_t z = unit >> lg, j0 = (unit & ((1u << lg) - 1u)) << 5;
+    const uint32_t* src = wave_uniform((a.in_ptrs ? a.in_ptrs[z] : a.limbs + (long long)z * a.in_stride) + j0);
+    // limbs 8 kb + 4 h + r; rows at or beyond L read as zero, where the table is zero too
+    const __amdgpu_buffer_rsrc_t rs = row_buffer(src, 4u * ((uint32_t)a.L * (uint32_t)a.N - j0));
     v4i B[NKB];
 #pragma unroll
     for (int kb = 0; kb < NKB; ++kb)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        uint32_t msk = 8 * kb + 4 * h + r < a.L ? 0xFFFFFFFFu : 0u;  // limbs beyond L: digits 0
-        opaque(msk);
-        opaque(w[kb][r]);
-        B[kb][r] = (int)((w[kb][r] ^ 0x80808080u) & msk);
-      }
-    uint32_t* dst = a.res + (long long)z * a.out_stride + j;
-    for (int t = 0; t < a.ntiles; ++t) {
+      for (int r = 0; r < 4; ++r) B[kb][r] = (int)(buffer_word(rs, lane_off + (8 * kb + r) * row) ^ 0x80808080u);
+    uint32_t* dst = wave_uniform(a.res + (long long)z * a.out_stride + j0);
+    // one tile: residues 8 t + 4 h + i (i < 4); `last` guards the rows past K
+    auto tile = [&](int t, bool last) {
       const v4i* Ap = At + (long long)t * NKB * 64 + lane;
       v4i Af[NKB];
 #pragma unroll
@@ -686,14 +735,19 @@ __global__ __launch_bounds__(BLK) void lift_mfma_kernel(LiftArgs a) {
         const int p = 8 * t + 4 * h + i;
         const uint32_t q = s_q[p];
         int64_t v = (int64_t)(((uint64_t)s_ohi[p] << 32) | s_olo[p]);
-        v += (int64_t)acc[i];
-        v += (int64_t)acc[4 + i] * (int32_t)m8;
-        v += (int64_t)acc[8 + i] * (int32_t)m16;
-        v += (int64_t)acc[12 + i] * (int32_t)m24;
+        v = mad_i64(acc[i], one, v);
+        v = mad_i64(acc[4 + i], m8, v);
+        v = mad_i64(acc[8 + i], m16, v);
+        v = mad_i64(acc[12 + i], m24, v);
         const uint32_t r = csub(redc_lazy((uint64_t)v, q, s_qn[p]), q);
-        if (p < a.K) dst[(long long)p * a.N] = r;
+        if (!last || p < a.K) store_at(dst, lane_off + i * row, r);
       }
+    };
+    for (int t = 0; t < a.ntiles - 1; ++t) {
+      tile(t, false);
+      dst += 8 * a.N;
     }
+    tile(a.ntiles - 1, true);
   }
 }
 
@@ -846,11 +900,13 @@ hipError_t launch_ring_pointwise(const PointwiseArgs& a, int cnum, hipStream_t s
 //
 // The column sums sum_k y_k V_kl, V_kl = limb l of (M/q_k) mod 2^(32 Lout), are a
 // dense integer contraction [coefficients x K] x [K x Lout] and run on the i8
-// matrix cores: y_k and V_kl are split into 4 balanced base-256 digits each
-// (digits in [-128, 127], limbs of V taken in [-0x80808080, 0x7F7F7F7F]), the 16
+// matrix cores: y_k - 0x80808080 and V_kl are split into 4 balanced base-256 digits
+// each (digits in [-128, 127]; the digits of y_k - 0x80808080 are the bytes of
+// y_k ^ 0x80808080, and limbs of V are taken in [-0x80808080, 0x7F7F7F7F]), the 16
 // digit-plane products accumulate exactly in int32 (|sum| <= K 2^14), and the VALU
 // recombines sum_(a,b) 2^(8(a+b)) C_ab per limb (the 7 diagonal sums in int32, then
-// 64-bit multiply-adds), adds alpha [-M] + [-2^e], and propagates the carries.
+// 64-bit multiply-adds), adds alpha [-M] + [0x80808080 sum_k V_k - 2^e] (both
+// constants as limbs mod 2^(32 Lout)), and propagates the carries.
 //
 // One wave per 32 coefficients.  MFMA v_mfma_i32_32x32x32_i8: lane (c, h) = (lane
 // mod 32, lane / 32) supplies B bytes k = 32 kb + 16 h + i (i < 16) of coefficient
@@ -873,17 +929,6 @@ __device__ __forceinline__ void byte_planes(uint32_t w0, uint32_t w1, uint32_t w
   p3 = __builtin_amdgcn_perm(hi23, hi01, 0x07060302u);
 }
 
-// Adds a signed carry to 4 unsigned limbs; returns the carry out of the top limb.
-__device__ __forceinline__ int64_t add_carry4(uint32_t (&o)[4], int64_t cin) {
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int64_t t = (int64_t)o[i] + cin;
-    o[i] = (uint32_t)t;
-    cin = t >> 32;
-  }
-  return cin;
-}
-
 constexpr int kCrtWaves = 8;  // waves per workgroup (one workgroup with its LDS table per CU)
 
 template <int NKB, bool LDSA>
@@ -895,7 +940,7 @@ __global__ __launch_bounds__(64 * kCrtWaves) void crt_kernel(CrtArgs a) {
     const bool in = k < a.K;
     s_q[k] = in ? a.pc[k].q : 1u;
     s_d[k] = in ? a.d[k] : 0u;
-    s_r[k] = in ? a.rq[k] : 0u;
+    s_r[k] = in ? a.rq[k] : 0u;  // rows past K add nothing to the quotient
   }
   for (int l = threadIdx.x; l < 8 * a.ntiles; l += 64 * kCrtWaves) {
     s_mneg[l] = a.mneg[l];
@@ -906,124 +951,143 @@ __global__ __launch_bounds__(64 * kCrtWaves) void crt_kernel(CrtArgs a) {
   __syncthreads();
   const v4i* At = LDSA ? sA : a.A;
   const int lane = threadIdx.x & 63, c = lane & 31, h = lane >> 5;
-  const int groups = a.N >> 5;
-  const long long total = (long long)a.npoly * groups;
-  const int topbits = a.outbits - 32 * (a.Lout - 1);
-  {
-    const long long unit = (long long)blockIdx.x * kCrtWaves + (threadIdx.x >> 6);
-    if (unit >= total) return;  // after the only barrier
-    const int z = (int)(unit / groups);
-    const int j = (int)(unit % groups) * 32 + c;
-    const uint32_t* x =
-        a.res + (long long)(z / a.per_group) * a.gstride + (long long)(z % a.per_group) * a.pstride + j;
+  const int lg = __builtin_ctz((unsigned)a.N) - 5;  // log2 of the 32-coefficient groups per poly
+  const uint32_t unit = blockIdx.x * kCrtWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (unit >= ((uint32_t)a.npoly << lg)) return;  // after the only barrier
+  const uint32_t z = unit >> lg, j0 = (unit & ((1u << lg) - 1u)) << 5;
+  const uint32_t row = 4u * (uint32_t)a.N;  // bytes between residue (or limb) rows
+  const uint32_t* xb = wave_uniform(a.res + (long long)(z / a.per_group) * a.gstride +
+                                    (long long)(z % a.per_group) * a.pstride + j0);
+  // residue rows 32 kb + 16 h + i; rows at or beyond K read as zero
+  const __amdgpu_buffer_rsrc_t rs = row_buffer(xb, 4u * ((uint32_t)a.K * (uint32_t)a.N - j0));
+  const uint32_t in_off = 16u * h * row + 4u * c;
 
-    // phase 1: y_k, the partial sum of y_k / q_k, and the four digit planes per k-block.
-    // Loads are unconditional (index clamped to K - 1, value masked) so that a block's
-    // 16 loads issue together, and the next block's loads are in flight meanwhile.
-    v4i B[NKB][4];
-    uint64_t frac = 0;  // sum_k y_k floor(2^56 / q_k)
-    uint32_t xv[16], xn[16];
+  // phase 1: y_k, the partial sum of y_k / q_k, and the four digit planes per k-block.
+  // The digits are the bytes of y_k ^ 0x80808080, i.e. of y_k - 0x80808080 in balanced
+  // base 256; the table's constant adds back 0x80808080 sum_k V_k.  The next block's
+  // loads are in flight while a block is converted.
+  v4i B[NKB][4];
+  uint64_t frac = 0;  // sum_k y_k floor(2^56 / q_k)
+  uint32_t xv[16], xn[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) xv[i] = x[(long long)min(16 * h + i, a.K - 1) * a.N];
+  for (int i = 0; i < 16; ++i) xv[i] = buffer_word(rs, in_off + i * row);
 #pragma unroll
-    for (int kb = 0; kb < NKB; ++kb) {
-      if (kb + 1 < NKB) {
+  for (int kb = 0; kb < NKB; ++kb) {
+    if (kb + 1 < NKB) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) xn[i] = x[(long long)min(32 * (kb + 1) + 16 * h + i, a.K - 1) * a.N];
-      }
-      uint32_t s[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int k = 32 * kb + 16 * h + i;
-        uint32_t msk = k < a.K ? 0xFFFFFFFFu : 0u;
-        opaque(msk);
-        opaque(xv[i]);
-        uint32_t y = xv[i] + s_d[k];
-        y = min(y, y - s_q[k]) & msk;
-        frac += (uint64_t)y * s_r[k];
-        s[i] = (y + 0x80808080u) ^ 0x80808080u;           // balanced base-256 digits, as int8 bytes
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        uint32_t p0, p1, p2, p3;
-        byte_planes(s[4 * r], s[4 * r + 1], s[4 * r + 2], s[4 * r + 3], p0, p1, p2, p3);
-        B[kb][0][r] = (int)p0;
-        B[kb][1][r] = (int)p1;
-        B[kb][2][r] = (int)p2;
-        B[kb][3][r] = (int)p3;
-      }
-      if (kb + 1 < NKB) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) xv[i] = xn[i];
-      }
+      for (int i = 0; i < 16; ++i) xn[i] = buffer_word(rs, in_off + (32 * (kb + 1) + i) * row);
     }
-    frac += __shfl_xor(frac, 32);
-    const uint32_t alpha = (uint32_t)((frac + (1ull << 38)) >> 56);
-    // multipliers the compiler cannot fold into shifts: the combination below is
-    // then one 64-bit multiply-add per term
-    uint32_t m8 = 256, m16 = 65536, m24 = 16777216;
-    opaque(m8);
-    opaque(m16);
-    opaque(m24);
-
-    // phase 2: per tile of 8 limbs, the digit-plane products, recombination, carries
-    uint32_t* o = a.out + (long long)z * a.ostride + j;
-    int64_t cin = 0;  // carry into the tile (valid in lane half 0)
-    for (int t = 0; t < a.ntiles; ++t) {
-      v16i acc0 = {}, acc1 = {}, acc2 = {}, acc3 = {};
-      const v4i* Ap = At + ((long long)t * NKB) * 64 + lane;
-      v4i Af[NKB];
+    uint32_t s[16];
 #pragma unroll
-      for (int kb = 0; kb < NKB; ++kb) Af[kb] = Ap[kb * 64];
+    for (int i = 0; i < 16; ++i) {
+      const int k = 32 * kb + 16 * h + i;
+      uint32_t y = xv[i] + s_d[k];
+      y = min(y, y - s_q[k]);
+      frac += (uint64_t)y * s_r[k];
+      s[i] = y ^ 0x80808080u;
+    }
 #pragma unroll
-      for (int kb = 0; kb < NKB; ++kb) {
-        acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[kb], B[kb][0], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[kb], B[kb][1], acc1, 0, 0, 0);
-        acc2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[kb], B[kb][2], acc2, 0, 0, 0);
-        acc3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[kb], B[kb][3], acc3, 0, 0, 0);
-      }
-      uint32_t ol[4];
-      int64_t carry = 0;
+    for (int r = 0; r < 4; ++r) {
+      uint32_t p0, p1, p2, p3;
+      byte_planes(s[4 * r], s[4 * r + 1], s[4 * r + 2], s[4 * r + 3], p0, p1, p2, p3);
+      // materialised here: left to the compiler, the planes may be recomputed later
+      opaque(p0);
+      opaque(p1);
+      opaque(p2);
+      opaque(p3);
+      B[kb][0][r] = (int)p0;
+      B[kb][1][r] = (int)p1;
+      B[kb][2][r] = (int)p2;
+      B[kb][3][r] = (int)p3;
+    }
+    if (kb + 1 < NKB) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int limb = 8 * t + 4 * h + i;
-        // C_ab = acc_a[4 b + i]: y plane a times V plane b; diagonal sums (|.| < 2^24)
-        const int32_t s0 = acc0[i];
-        const int32_t s1 = acc0[4 + i] + acc1[i];
-        const int32_t s2 = acc0[8 + i] + acc1[4 + i] + acc2[i];
-        const int32_t s3 = acc0[12 + i] + acc1[8 + i] + acc2[4 + i] + acc3[i];
-        const int32_t s4 = acc1[12 + i] + acc2[8 + i] + acc3[4 + i];
-        const int32_t s5 = acc2[12 + i] + acc3[8 + i];
-        const int32_t s6 = acc3[12 + i];
-        int64_t lo = (int64_t)((uint64_t)alpha * s_mneg[limb] + s_eneg[limb]);
-        lo += (int64_t)s0;
-        lo += (int64_t)s1 * (int32_t)m8;
-        lo += (int64_t)s2 * (int32_t)m16;
-        lo += (int64_t)s3 * (int32_t)m24;
-        int64_t hi = (int64_t)s4;
-        hi += (int64_t)s5 * (int32_t)m8;
-        hi += (int64_t)s6 * (int32_t)m16;
-        const int64_t tt = lo + carry;
-        ol[i] = (uint32_t)tt;
-        carry = (tt >> 32) + hi;
-      }
-      // carry across the lane halves: half 0 takes the carry into the tile, passes its
-      // carry out to half 1, whose carry out enters the next tile
-      carry += add_carry4(ol, h == 0 ? cin : 0);
-      const int64_t mid = __shfl_xor(carry, 32);
-      carry += add_carry4(ol, h == 1 ? mid : 0);
-      cin = __shfl_xor(carry, 32);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int limb = 8 * t + 4 * h + i;
-        if (limb < a.Lout) {
-          uint32_t w = ol[i];
-          if (limb == a.Lout - 1 && topbits < 32) w &= (1u << topbits) - 1u;
-          o[(long long)limb * a.N] = w;
-        }
-      }
+      for (int i = 0; i < 16; ++i) xv[i] = xn[i];
     }
   }
+  frac += __shfl_xor(frac, 32);
+  const uint32_t alpha = (uint32_t)((frac + (1ull << 38)) >> 56);
+  // opaque multipliers of mad_i64 (the unit multipliers distinct per term of a sum)
+  uint32_t one0 = 1, one1 = 1, one2 = 1, one3 = 1, m8 = 256, m16 = 65536, m24 = 16777216;
+  opaque(one0);
+  opaque(one1);
+  opaque(one2);
+  opaque(one3);
+  opaque(m8);
+  opaque(m16);
+  opaque(m24);
+
+  // phase 2, per tile of 8 limbs: the digit-plane products, recombination, carries.
+  // Lane half h holds limbs l = 8 t + 4 h + i (i < 4) with C_ab = acc_a[4 b + i] (y plane
+  // a, V plane b) and diagonal sums S_p = sum_(a+b=p) C_ab.  S_4..S_6 weigh 2^0..2^16 in
+  // limb l + 1: inside the lane they join the next limb's sums, from the top limb they
+  // leave with the carry.
+  uint32_t* o = wave_uniform(a.out + (long long)z * a.ostride + j0);
+  const uint32_t out_off = 4u * h * row + 4u * c;
+  const int topbits = a.outbits - 32 * (a.Lout - 1);
+  int64_t cin = 0;  // carry into the tile (used in lane half 0)
+  auto tile = [&](int t, bool last) {
+    v16i acc0 = {}, acc1 = {}, acc2 = {}, acc3 = {};
+    const v4i* Ap = At + ((long long)t * NKB) * 64 + lane;
+    v4i Af[NKB];
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) Af[kb] = Ap[kb * 64];
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) {
+      acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[kb], B[kb][0], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[kb], B[kb][1], acc1, 0, 0, 0);
+      acc2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[kb], B[kb][2], acc2, 0, 0, 0);
+      acc3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[kb], B[kb][3], acc3, 0, 0, 0);
+    }
+    uint32_t ol[4];
+    int32_t s4 = 0, s5 = 0, s6 = 0;  // S_4..S_6 of the limb below
+    int64_t u = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int limb = 8 * t + 4 * h + i;
+      const int32_t t0 = acc0[i] + s4;
+      const int32_t t1 = acc0[4 + i] + acc1[i] + s5;
+      const int32_t t2 = acc0[8 + i] + acc1[4 + i] + acc2[i] + s6;
+      const int32_t t3 = acc0[12 + i] + acc1[8 + i] + acc2[4 + i] + acc3[i];
+      s4 = acc1[12 + i] + acc2[8 + i] + acc3[4 + i];
+      s5 = acc2[12 + i] + acc3[8 + i];
+      s6 = acc3[12 + i];
+      // |t_p| <= 4 K 2^14 < 2^25: the limb value fits 64 bits with the constant and carry
+      int64_t v = (int64_t)((uint64_t)alpha * s_mneg[limb] + s_eneg[limb]);
+      v = mad_i64(t0, one0, v);
+      v = mad_i64(t1, m8, v);
+      v = mad_i64(t2, m16, v);
+      v = mad_i64(t3, m24, v);
+      if (i > 0) v = mad_i64((int32_t)(u >> 32), one1, v);
+      u = v;
+      ol[i] = (uint32_t)v;
+    }
+    int64_t carry = mad_i64(s4, one0, 0);
+    carry = mad_i64(s5, m8, carry);
+    carry = mad_i64(s6, m16, carry);
+    carry = mad_i64((int32_t)(u >> 32), one1, carry);
+    // carry across the lane halves: half 0 takes the carry into the tile, passes its
+    // carry out to half 1, whose carry out enters the next tile
+    carry = mad_i64(add_carry4(ol, h == 0 ? cin : 0), one2, carry);
+    const int64_t mid = __shfl_xor(carry, 32);
+    carry = mad_i64(add_carry4(ol, h == 1 ? mid : 0), one3, carry);
+    cin = __shfl_xor(carry, 32);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int limb = 8 * t + 4 * h + i;
+      uint32_t w = ol[i];
+      if (last) {
+        if (limb >= a.Lout) continue;
+        if (limb == a.Lout - 1 && topbits < 32) w &= (1u << topbits) - 1u;
+      }
+      store_at(o, out_off + i * row, w);
+    }
+  };
+  for (int t = 0; t < a.ntiles - 1; ++t) {
+    tile(t, false);
+    o += 8 * a.N;
+  }
+  tile(a.ntiles - 1, true);
 }
 
 template <int NKB>
