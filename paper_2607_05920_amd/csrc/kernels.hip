@@ -55,6 +55,29 @@ __device__ __forceinline__ void store_at(uint32_t* base, uint32_t byte_off, uint
 // the wait states after the matrix-core op that produced its operand.)
 __device__ __forceinline__ int64_t mad_i64(int32_t a, uint32_t b, int64_t c) { return (int64_t)a * (int32_t)b + c; }
 
+// Exchanges between the wave's lane halves with v_permlane32_swap (a vector op, no LDS
+// round trip).  swap(x, x) returns {r0, r1}: r0 holds, in lanes 32..63, x of the lane 32
+// below (lanes 0..31 keep theirs); r1 holds, in lanes 0..31, x of the lane 32 above.
+__device__ __forceinline__ int64_t from_lane_below(int64_t x) {  // valid in lanes 32..63
+  const uint32_t lo = (uint32_t)x, hi = (uint32_t)((uint64_t)x >> 32);
+  const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto u = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return (int64_t)(((uint64_t)u[0] << 32) | l[0]);
+}
+__device__ __forceinline__ int64_t from_lane_above(int64_t x) {  // valid in lanes 0..31
+  const uint32_t lo = (uint32_t)x, hi = (uint32_t)((uint64_t)x >> 32);
+  const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto u = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return (int64_t)(((uint64_t)u[1] << 32) | l[1]);
+}
+// x plus x of the lane 32 apart, in every lane
+__device__ __forceinline__ uint64_t sum_lane_halves(uint64_t x) {
+  const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+  const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto u = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return ((((uint64_t)u[0] << 32) | l[0])) + ((((uint64_t)u[1] << 32) | l[1]));
+}
+
 // o += cin over 4 limbs (unsigned words, least significant first), cin signed 64-bit:
 // one add-with-carry chain over (cin_lo, cin_hi, ext, ext), ext the sign extension.
 // Returns the signed carry out of the top limb, in {-1, 0, 1}.
@@ -708,9 +731,12 @@ __global__ __launch_bounds__(BLK) void lift_mfma_kernel(LiftArgs a) {
   const int lg = __builtin_ctz((unsigned)a.N) - 5;  // log2 of the 32-coefficient groups per poly
   const uint32_t total = (uint32_t)a.npoly << lg;
   const uint32_t row = 4u * (uint32_t)a.N;          // bytes between limb (or residue) rows
-  const uint32_t lane_off = 4u * h * row + 4u * c;  // row 4 h, column c of a 32-coefficient group
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (uint32_t unit = blockIdx.x * (BLK / 64) + wave; unit < total; unit += gridDim.x * (BLK / 64)) {
+    // row 4 h, column c of a 32-coefficient group; recomputed per unit (opaque), or the
+    // row offsets derived from it are hoisted out of the loop, each holding a register
+    uint32_t lane_off = 4u * h * row + 4u * c;
+    opaque(lane_off);
     const uint32_t z = unit >> lg, j0 = (unit & ((1u << lg) - 1u)) << 5;
     const uint32_t* src = wave_uniform((a.in_ptrs ? a.in_ptrs[z] : a.limbs + (long long)z * a.in_stride) + j0);
     // limbs 8 kb + 4 h + r; rows at or beyond L read as zero, where the table is zero too
@@ -727,9 +753,13 @@ __global__ __launch_bounds__(BLK) void lift_mfma_kernel(LiftArgs a) {
       v4i Af[NKB];
 #pragma unroll
       for (int kb = 0; kb < NKB; ++kb) Af[kb] = Ap[kb * 64];
-      v16i acc = {};
+      // two independent accumulation chains (a single dependent chain issues at 2/3 rate)
+      v16i acc = {}, acc2 = {};
 #pragma unroll
-      for (int kb = 0; kb < NKB; ++kb) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[kb], B[kb], acc, 0, 0, 0);
+      for (int kb = 0; kb < NKB; kb += 2) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[kb], B[kb], acc, 0, 0, 0);
+#pragma unroll
+      for (int kb = 1; kb < NKB; kb += 2) acc2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[kb], B[kb], acc2, 0, 0, 0);
+      if (NKB > 1) acc += acc2;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int p = 8 * t + 4 * h + i;
@@ -929,10 +959,14 @@ __device__ __forceinline__ void byte_planes(uint32_t w0, uint32_t w1, uint32_t w
   p3 = __builtin_amdgcn_perm(hi23, hi01, 0x07060302u);
 }
 
-constexpr int kCrtWaves = 8;  // waves per workgroup (one workgroup with its LDS table per CU)
+// Waves per workgroup: one persistent workgroup per CU holds the LDS table; 12 waves
+// (3 per SIMD) where the registers allow it, else 8.
+template <int NKB>
+constexpr int crt_waves() { return NKB <= 4 ? 12 : 8; }
 
 template <int NKB, bool LDSA>
-__global__ __launch_bounds__(64 * kCrtWaves) void crt_kernel(CrtArgs a) {
+__global__ __launch_bounds__(64 * crt_waves<NKB>()) void crt_kernel(CrtArgs a) {
+  constexpr int kCrtWaves = crt_waves<NKB>();
   extern __shared__ v4i sA[];
   __shared__ uint32_t s_q[32 * NKB], s_d[32 * NKB], s_r[32 * NKB];
   __shared__ uint32_t s_mneg[kCrtMaxLimbs], s_eneg[kCrtMaxLimbs];
@@ -952,15 +986,22 @@ __global__ __launch_bounds__(64 * kCrtWaves) void crt_kernel(CrtArgs a) {
   const v4i* At = LDSA ? sA : a.A;
   const int lane = threadIdx.x & 63, c = lane & 31, h = lane >> 5;
   const int lg = __builtin_ctz((unsigned)a.N) - 5;  // log2 of the 32-coefficient groups per poly
-  const uint32_t unit = blockIdx.x * kCrtWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (unit >= ((uint32_t)a.npoly << lg)) return;  // after the only barrier
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t total = (uint32_t)a.npoly << lg;
+  // the waves sharing a SIMD start apart, so that one's loads overlap another's products
+  if (wave >= 4) __builtin_amdgcn_s_sleep(63);
+  if (wave >= 8) __builtin_amdgcn_s_sleep(63);
+  for (uint32_t unit = blockIdx.x * kCrtWaves + wave; unit < total; unit += gridDim.x * kCrtWaves) {
   const uint32_t z = unit >> lg, j0 = (unit & ((1u << lg) - 1u)) << 5;
   const uint32_t row = 4u * (uint32_t)a.N;  // bytes between residue (or limb) rows
   const uint32_t* xb = wave_uniform(a.res + (long long)(z / a.per_group) * a.gstride +
                                     (long long)(z % a.per_group) * a.pstride + j0);
   // residue rows 32 kb + 16 h + i; rows at or beyond K read as zero
   const __amdgpu_buffer_rsrc_t rs = row_buffer(xb, 4u * ((uint32_t)a.K * (uint32_t)a.N - j0));
-  const uint32_t in_off = 16u * h * row + 4u * c;
+  // recomputed per unit (opaque): hoisted out of the unit loop, the 80-odd row offsets
+  // derived from it would each hold a register for the whole kernel
+  uint32_t in_off = 16u * h * row + 4u * c;
+  opaque(in_off);
 
   // phase 1: y_k, the partial sum of y_k / q_k, and the four digit planes per k-block.
   // The digits are the bytes of y_k ^ 0x80808080, i.e. of y_k - 0x80808080 in balanced
@@ -1005,7 +1046,7 @@ __global__ __launch_bounds__(64 * kCrtWaves) void crt_kernel(CrtArgs a) {
       for (int i = 0; i < 16; ++i) xv[i] = xn[i];
     }
   }
-  frac += __shfl_xor(frac, 32);
+  frac = sum_lane_halves(frac);
   const uint32_t alpha = (uint32_t)((frac + (1ull << 38)) >> 56);
   // opaque multipliers of mad_i64 (the unit multipliers distinct per term of a sum)
   uint32_t one0 = 1, one1 = 1, one2 = 1, one3 = 1, m8 = 256, m16 = 65536, m24 = 16777216;
@@ -1023,15 +1064,20 @@ __global__ __launch_bounds__(64 * kCrtWaves) void crt_kernel(CrtArgs a) {
   // limb l + 1: inside the lane they join the next limb's sums, from the top limb they
   // leave with the carry.
   uint32_t* o = wave_uniform(a.out + (long long)z * a.ostride + j0);
-  const uint32_t out_off = 4u * h * row + 4u * c;
+  uint32_t out_off = 4u * h * row + 4u * c;
+  opaque(out_off);
   const int topbits = a.outbits - 32 * (a.Lout - 1);
   int64_t cin = 0;  // carry into the tile (used in lane half 0)
-  auto tile = [&](int t, bool last) {
-    v16i acc0 = {}, acc1 = {}, acc2 = {}, acc3 = {};
+  v16i acc0, acc1, acc2, acc3;
+  auto products = [&](int t) {
     const v4i* Ap = At + ((long long)t * NKB) * 64 + lane;
     v4i Af[NKB];
 #pragma unroll
     for (int kb = 0; kb < NKB; ++kb) Af[kb] = Ap[kb * 64];
+    acc0 = v16i{};
+    acc1 = v16i{};
+    acc2 = v16i{};
+    acc3 = v16i{};
 #pragma unroll
     for (int kb = 0; kb < NKB; ++kb) {
       acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[kb], B[kb][0], acc0, 0, 0, 0);
@@ -1039,25 +1085,34 @@ __global__ __launch_bounds__(64 * kCrtWaves) void crt_kernel(CrtArgs a) {
       acc2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[kb], B[kb][2], acc2, 0, 0, 0);
       acc3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[kb], B[kb][3], acc3, 0, 0, 0);
     }
+  };
+  // tile sums: tt[i][p] = T_p of limb i (S_p plus S_(p+4) of limb i - 1), s4..s6 of limb 3
+  int32_t tt[4][4], s4, s5, s6;
+  auto sums = [&]() {
+    s4 = s5 = s6 = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      tt[i][0] = acc0[i] + s4;
+      tt[i][1] = acc0[4 + i] + acc1[i] + s5;
+      tt[i][2] = acc0[8 + i] + acc1[4 + i] + acc2[i] + s6;
+      tt[i][3] = acc0[12 + i] + acc1[8 + i] + acc2[4 + i] + acc3[i];
+      s4 = acc1[12 + i] + acc2[8 + i] + acc3[4 + i];
+      s5 = acc2[12 + i] + acc3[8 + i];
+      s6 = acc3[12 + i];
+    }
+  };
+  auto finish = [&](int t, bool last) {
     uint32_t ol[4];
-    int32_t s4 = 0, s5 = 0, s6 = 0;  // S_4..S_6 of the limb below
     int64_t u = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int limb = 8 * t + 4 * h + i;
-      const int32_t t0 = acc0[i] + s4;
-      const int32_t t1 = acc0[4 + i] + acc1[i] + s5;
-      const int32_t t2 = acc0[8 + i] + acc1[4 + i] + acc2[i] + s6;
-      const int32_t t3 = acc0[12 + i] + acc1[8 + i] + acc2[4 + i] + acc3[i];
-      s4 = acc1[12 + i] + acc2[8 + i] + acc3[4 + i];
-      s5 = acc2[12 + i] + acc3[8 + i];
-      s6 = acc3[12 + i];
-      // |t_p| <= 4 K 2^14 < 2^25: the limb value fits 64 bits with the constant and carry
+      // |T_p| <= 4 K 2^14 < 2^25: the limb value fits 64 bits with the constant and carry
       int64_t v = (int64_t)((uint64_t)alpha * s_mneg[limb] + s_eneg[limb]);
-      v = mad_i64(t0, one0, v);
-      v = mad_i64(t1, m8, v);
-      v = mad_i64(t2, m16, v);
-      v = mad_i64(t3, m24, v);
+      v = mad_i64(tt[i][0], one0, v);
+      v = mad_i64(tt[i][1], m8, v);
+      v = mad_i64(tt[i][2], m16, v);
+      v = mad_i64(tt[i][3], m24, v);
       if (i > 0) v = mad_i64((int32_t)(u >> 32), one1, v);
       u = v;
       ol[i] = (uint32_t)v;
@@ -1069,9 +1124,9 @@ __global__ __launch_bounds__(64 * kCrtWaves) void crt_kernel(CrtArgs a) {
     // carry across the lane halves: half 0 takes the carry into the tile, passes its
     // carry out to half 1, whose carry out enters the next tile
     carry = mad_i64(add_carry4(ol, h == 0 ? cin : 0), one2, carry);
-    const int64_t mid = __shfl_xor(carry, 32);
+    const int64_t mid = from_lane_below(carry);
     carry = mad_i64(add_carry4(ol, h == 1 ? mid : 0), one3, carry);
-    cin = __shfl_xor(carry, 32);
+    cin = from_lane_above(carry);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int limb = 8 * t + 4 * h + i;
@@ -1084,17 +1139,23 @@ __global__ __launch_bounds__(64 * kCrtWaves) void crt_kernel(CrtArgs a) {
     }
   };
   for (int t = 0; t < a.ntiles - 1; ++t) {
-    tile(t, false);
+    products(t);
+    sums();
+    finish(t, false);
     o += 8 * a.N;
   }
-  tile(a.ntiles - 1, true);
+  products(a.ntiles - 1);
+  sums();
+  finish(a.ntiles - 1, true);
+  }
 }
 
 template <int NKB>
 static void crt_launch(const CrtArgs& a, hipStream_t st) {
+  constexpr int kCrtWaves = crt_waves<NKB>();
   const long long units = (long long)a.npoly * (a.N >> 5);
   const size_t lds = (size_t)a.ntiles * NKB * 64 * sizeof(v4i);
-  const unsigned grid = (unsigned)((units + kCrtWaves - 1) / kCrtWaves);
+  const unsigned grid = persistent_grid(units, kCrtWaves, 1, a.cus);
   const size_t lds_static = 32 * NKB * 12 + 2 * kCrtMaxLimbs * 4;
   if (lds + lds_static <= (size_t)a.lds_max) {
     static bool attr = false;  // allow the full LDS of the device for this instantiation (once)
