@@ -288,7 +288,10 @@ struct fhe_evk {
   uint32_t t = 0;
   int logN = 0, logQ = 0, logP = 0;
   std::vector<uint32_t> hb, ha;  // host limbs [L_PQ][N]
-  std::map<int, uint32_t*> ntt;  // per logq: [2][K_r][N]
+  // per logq: [2][K_r][N] in NTT form, each row of the fused pass transposed into its
+  // register order (launch_row_transpose) for rows of 2^(logN/2) points; for odd logN,
+  // ntt_alt holds the same for rows of 2^(logN - logN/2) points
+  std::map<int, uint32_t*> ntt, ntt_alt;
 };
 
 namespace {
@@ -703,7 +706,24 @@ int evk_prepare_locked(fhe_evk* k, int logq, hipStream_t stream) {
     hipFree(out);
     return set_sticky(c, e);
   }
-  k->ntt[logq] = out;
+  // the fused relinearization pass reads each row in its transposed register order; the
+  // row length depends on the column/row split, which differs by tuning for odd logN
+  const long long words = 2LL * Kr * N;
+  const int Sa = k->logN / 2, Sb = k->logN - k->logN / 2;
+  uint32_t* perm[2] = {nullptr, nullptr};
+  for (int v = 0; v < (Sa == Sb ? 1 : 2) && e == hipSuccess; ++v) {
+    e = hipMalloc(&perm[v], (size_t)words * 4);
+    if (e == hipSuccess) e = launch_row_transpose(out, perm[v], words, v ? Sb : Sa, stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  hipFree(out);
+  if (e != hipSuccess) {
+    for (uint32_t* q : perm)
+      if (q) hipFree(q);
+    return set_sticky(c, e);
+  }
+  k->ntt[logq] = perm[0];
+  if (perm[1]) k->ntt_alt[logq] = perm[1];
   return FHE_OK;
 }
 
@@ -745,7 +765,8 @@ int pipeline(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, const PipeIO&
   if (z.Kt < 0 || z.Kr < 0) return FHE_E_RANGE;
   const int Kt = z.Kt, Kr = z.Kr, L = z.L, LK = z.LK;
   const int logP = k->logP;
-  const uint32_t* evk_ntt = k->ntt.at(logq);
+  const int rows_log = logN - ntt_split_cols(logN, tu);  // the fused pass's row length
+  const uint32_t* evk_ntt = rows_log == logN / 2 ? k->ntt.at(logq) : k->ntt_alt.at(logq);
   hipError_t e = hipSuccess;
   const int et = 2 * logq + logN + 1, er = logN + 2 * logq + logP;  // |d_i| < 2^et, |k_i| < 2^er
   const uint2* sct = crt_scale(c, logN, Kt, &e);
@@ -1632,6 +1653,7 @@ void fhe_evk_destroy(fhe_evk* k) {
     hipDeviceSynchronize();
   }
   for (auto& kv : k->ntt) hipFree(kv.second);
+  for (auto& kv : k->ntt_alt) hipFree(kv.second);
   delete k;
 }
 

@@ -164,6 +164,10 @@ hipError_t launch_ntt(const NttArgs& a, int ntransforms, bool inverse, hipStream
 hipError_t launch_ntt_cols(const NttArgs& a, int ntransforms, bool inverse, hipStream_t s,
                            const Tuning& t = Tuning());
 hipError_t launch_rows_fused(const RowsArgs& a, int mode, hipStream_t s, const Tuning& t = Tuning());
+// log2 of the column pass's length for a transform of 2^logN points
+int ntt_split_cols(int logN, const Tuning& t);
+// Transposes rows of 2^S words into the register order of the fused relinearization pass.
+hipError_t launch_row_transpose(const uint32_t* src, uint32_t* dst, long long total, int S, hipStream_t s);
 hipError_t launch_lift(const LiftArgs& a, int npoly, hipStream_t s, const Tuning& t = Tuning());
 hipError_t launch_tensor_pointwise(const PointwiseArgs& a, int cnum, hipStream_t s);
 hipError_t launch_relin_pointwise(const PointwiseArgs& a, int cnum, hipStream_t s);

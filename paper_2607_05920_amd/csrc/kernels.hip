@@ -322,8 +322,8 @@ __global__ __launch_bounds__(256) void ntt_pass_kernel(NttArgs a) {
 // Forward n-point row transforms of NP rows at once (the values x[r][u] at
 // e = u T + j, loaded by the caller): each twiddle is loaded once for all rows and
 // the NP exchanges share one barrier.  Leaves canonical values at e = 16 j + u.
-template <int S, int NP>
-__device__ __forceinline__ void fwd_rows(uint32_t (&x)[NP][16], uint32_t* const (&l)[NP], int j, const uint2* tw,
+template <int S, int NP, int NB>
+__device__ __forceinline__ void fwd_rows(uint32_t (&x)[NP][16], uint32_t* const (&l)[NB], int j, const uint2* tw,
                                          int tw_mul, uint32_t q, uint32_t two_q) {
   constexpr int n = 1 << S, T = n / 16;
 #pragma unroll
@@ -338,21 +338,26 @@ __device__ __forceinline__ void fwd_rows(uint32_t (&x)[NP][16], uint32_t* const 
         for (int u = 2 * h * g; u < 2 * h * g + h; ++u) ct_bfly(x[r][u], x[r][u + h], w, q, two_q);
     }
   }
+  // the transpose through LDS, NB rows at a time (fewer buffers, more workgroups per CU)
 #pragma unroll
-  for (int r = 0; r < NP; ++r)
+  for (int r0 = 0; r0 < NP; r0 += NB) {
+    if (r0 > 0) __syncthreads();  // every thread has read the previous round
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int e = u * T + j;
-      l[r][e + (e >> 4)] = x[r][u];
-    }
-  __syncthreads();
+    for (int r = r0; r < NP && r < r0 + NB; ++r)
 #pragma unroll
-  for (int r = 0; r < NP; ++r)
+      for (int u = 0; u < 16; ++u) {
+        const int e = u * T + j;
+        l[r - r0][e + (e >> 4)] = x[r][u];
+      }
+    __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int e = 16 * j + u;
-      x[r][u] = l[r][e + (e >> 4)];
-    }
+    for (int r = r0; r < NP && r < r0 + NB; ++r)
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = 16 * j + u;
+        x[r][u] = l[r - r0][e + (e >> 4)];
+      }
+  }
 #pragma unroll
   for (int t = T / 2; t >= 1; t >>= 1) {
     const int m = n / (2 * t);
@@ -373,8 +378,8 @@ __device__ __forceinline__ void fwd_rows(uint32_t (&x)[NP][16], uint32_t* const 
 
 // First inverse n-point row stages of NP rows at once, values at e = 16 j + u in
 // [0, 2q); leaves values in [0, 2q) at e = u T + j for the caller to store.
-template <int S, int NP>
-__device__ __forceinline__ void inv_rows(uint32_t (&x)[NP][16], uint32_t* const (&l)[NP], int j, const uint2* tw,
+template <int S, int NP, int NB>
+__device__ __forceinline__ void inv_rows(uint32_t (&x)[NP][16], uint32_t* const (&l)[NB], int j, const uint2* tw,
                                          int tw_mul, uint32_t q, uint32_t two_q) {
   constexpr int n = 1 << S, T = n / 16;
 #pragma unroll
@@ -390,20 +395,24 @@ __device__ __forceinline__ void inv_rows(uint32_t (&x)[NP][16], uint32_t* const 
     }
   }
 #pragma unroll
-  for (int r = 0; r < NP; ++r)
+  for (int r0 = 0; r0 < NP; r0 += NB) {
+    if (r0 > 0) __syncthreads();  // every thread has read the previous round
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int e = 16 * j + u;
-      l[r][e + (e >> 4)] = x[r][u];
-    }
-  __syncthreads();
+    for (int r = r0; r < NP && r < r0 + NB; ++r)
 #pragma unroll
-  for (int r = 0; r < NP; ++r)
+      for (int u = 0; u < 16; ++u) {
+        const int e = 16 * j + u;
+        l[r - r0][e + (e >> 4)] = x[r][u];
+      }
+    __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int e = u * T + j;
-      x[r][u] = l[r][e + (e >> 4)];
-    }
+    for (int r = r0; r < NP && r < r0 + NB; ++r)
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = u * T + j;
+        x[r][u] = l[r - r0][e + (e >> 4)];
+      }
+  }
 #pragma unroll
   for (int st = 0; st < 4; ++st) {
     const int hd = 1 << st, h = 8 >> st;
@@ -418,7 +427,9 @@ __device__ __forceinline__ void inv_rows(uint32_t (&x)[NP][16], uint32_t* const 
   }
 }
 
-// Rows per workgroup of the fused pass: 8 rows of 256 points (128 threads).
+// Rows per workgroup of the fused pass: 8 rows of 256 points (128 threads).  The LDS
+// transposes go through kRowsBuffers buffers of 8 rows, as many rows at a time.
+constexpr int kRowsBuffers = 4;
 template <int S>
 struct RowsShape {
   static constexpr int n = 1 << S, T = n / 16;
@@ -429,7 +440,8 @@ struct RowsShape {
 template <int S, int MODE>
 __global__ __launch_bounds__(128) void rows_fused_kernel(RowsArgs a) {
   constexpr int n = RowsShape<S>::n, T = RowsShape<S>::T, NSUB = RowsShape<S>::NSUB, SS = RowsShape<S>::SS;
-  __shared__ uint32_t lds[4][NSUB * SS];
+  constexpr int NB = kRowsBuffers;
+  __shared__ uint32_t lds[NB][NSUB * SS];
 
   const int tid = threadIdx.x;
   const int s = tid / T, j = tid % T;
@@ -452,10 +464,9 @@ __global__ __launch_bounds__(128) void rows_fused_kernel(RowsArgs a) {
   const int tw_mul = nsub_total + sg;
   const long long KN = (long long)a.K * N;
   const long long row = (long long)p * N + (long long)sg * n;  // row sg of prime p
-  uint32_t* const l0 = lds[0] + s * SS;
-  uint32_t* const l1 = lds[1] + s * SS;
-  uint32_t* const l2 = lds[2] + s * SS;
-  uint32_t* const l3 = lds[3] + s * SS;
+  uint32_t* lb[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) lb[b] = lds[b] + s * SS;
 
   if (MODE == 0) {  // tensor, in place: slots 0..3 in, 0..2 out
     uint32_t* g = a.data + (long long)c * a.group_stride + row;
@@ -464,8 +475,7 @@ __global__ __launch_bounds__(128) void rows_fused_kernel(RowsArgs a) {
     for (int r = 0; r < 4; ++r)
 #pragma unroll
       for (int u = 0; u < 16; ++u) x[r][u] = valid ? g[r * KN + u * T + j] : 0u;
-    uint32_t* const lf[4] = {l0, l1, l2, l3};
-    fwd_rows<S, 4>(x, lf, j, tw, tw_mul, q, two_q);
+    fwd_rows<S, 4, NB>(x, lb, j, tw, tw_mul, q, two_q);
     uint32_t d[3][16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
@@ -475,8 +485,7 @@ __global__ __launch_bounds__(128) void rows_fused_kernel(RowsArgs a) {
       d[2][u] = mont_mul(x[1][u], x[3][u], q, qneg);
     }
     __syncthreads();  // every thread has read the forward exchange before it is overwritten
-    uint32_t* const li[3] = {l0, l1, l2};
-    inv_rows<S, 3>(d, li, j, itw, tw_mul, q, two_q);
+    inv_rows<S, 3, NB>(d, lb, j, itw, tw_mul, q, two_q);
     if (valid) {
 #pragma unroll
       for (int r = 0; r < 3; ++r)
@@ -489,18 +498,30 @@ __global__ __launch_bounds__(128) void rows_fused_kernel(RowsArgs a) {
     uint32_t x[1][16], k[2][16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) x[0][u] = valid ? g[u * T + j] : 0u;
-    uint32_t* const lf[1] = {l0};
-    fwd_rows<S, 1>(x, lf, j, tw, tw_mul, q, two_q);
+    uint32_t* const lf[1] = {lb[0]};
+    fwd_rows<S, 1, 1>(x, lf, j, tw, tw_mul, q, two_q);
+    // the key rows are stored transposed (launch_row_transpose): thread j's element
+    // 16 j + u sits at u T + j, so that these loads are coalesced
     const uint32_t* kb = a.key + row;
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const long long e = 16 * j + u;
+      const long long e = u * T + j;
       const uint32_t b = valid ? kb[e] : 0u, ak = valid ? kb[KN + e] : 0u;
       k[0][u] = mont_mul(x[0][u], b, q, qneg);
       k[1][u] = mont_mul(x[0][u], ak, q, qneg);
     }
-    uint32_t* const li[2] = {l1, l2};  // buffers the forward exchange did not use
-    inv_rows<S, 2>(k, li, j, itw, tw_mul, q, two_q);
+    // buffers the forward exchange did not use, or after a barrier the same one
+    if constexpr (NB >= 3) {
+      uint32_t* const li[2] = {lb[1 % NB], lb[2 % NB]};
+      inv_rows<S, 2, 2>(k, li, j, itw, tw_mul, q, two_q);
+    } else if constexpr (NB == 2) {
+      uint32_t* const li[1] = {lb[1 % NB]};
+      inv_rows<S, 2, 1>(k, li, j, itw, tw_mul, q, two_q);
+    } else {
+      __syncthreads();
+      uint32_t* const li[1] = {lb[0]};
+      inv_rows<S, 2, 1>(k, li, j, itw, tw_mul, q, two_q);
+    }
     if (valid) {
 #pragma unroll
       for (int r = 0; r < 2; ++r)
@@ -516,13 +537,19 @@ __global__ __launch_bounds__(128) void rows_fused_kernel(RowsArgs a) {
       x[0][u] = valid ? ga[u * T + j] : 0u;
       x[1][u] = valid ? gb[u * T + j] : 0u;
     }
-    uint32_t* const lf[2] = {l0, l1};
-    fwd_rows<S, 2>(x, lf, j, tw, tw_mul, q, two_q);
+    if constexpr (NB >= 2) {
+      uint32_t* const lf[2] = {lb[0], lb[1 % NB]};
+      fwd_rows<S, 2, 2>(x, lf, j, tw, tw_mul, q, two_q);
+    } else {
+      uint32_t* const lf[1] = {lb[0]};
+      fwd_rows<S, 2, 1>(x, lf, j, tw, tw_mul, q, two_q);
+    }
     uint32_t y[1][16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) y[0][u] = mont_mul(x[0][u], x[1][u], q, qneg);
-    uint32_t* const li[1] = {l2};
-    inv_rows<S, 1>(y, li, j, itw, tw_mul, q, two_q);
+    if (NB < 3) __syncthreads();  // the forward exchange's buffers are reused
+    uint32_t* const li[1] = {lb[2 % NB]};
+    inv_rows<S, 1, 1>(y, li, j, itw, tw_mul, q, two_q);
     if (valid) {
 #pragma unroll
       for (int u = 0; u < 16; ++u) ga[u * T + j] = y[0][u];
@@ -582,6 +609,23 @@ static hipError_t ntt_pass_s(int S, const NttArgs& a, int ntr, hipStream_t st) {
     case 8: return ntt_pass<8, INV, ROWS>(a, ntr, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+// dst[r n + u T + j] = src[r n + 16 j + u] within rows of n = 2^S words (T = n / 16):
+// a key in NTT form laid out in the order the fused relinearization pass holds it.
+__global__ __launch_bounds__(256) void row_transpose_kernel(const uint32_t* src, uint32_t* dst, long long total, int S) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= total) return;
+  const int n = 1 << S, T = n >> 4;
+  const int pos = (int)(i & (n - 1)), u = pos / T, j = pos % T;
+  dst[i] = src[(i - pos) + 16 * j + u];
+}
+
+hipError_t launch_row_transpose(const uint32_t* src, uint32_t* dst, long long total, int S, hipStream_t st) {
+  if (total <= 0) return hipSuccess;
+  if (S < 4 || (total & ((1LL << S) - 1)) != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(row_transpose_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, src, dst, total, S);
+  return hipGetLastError();
 }
 
 int ntt_split_cols(int logN, const Tuning& tu) { return tu.ntt_cols_first ? logN - logN / 2 : logN / 2; }
