@@ -780,12 +780,16 @@ int pipeline(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, const PipeIO&
   uint32_t* Rk = Rr + (long long)cnum * Kr * NN;        // [cnum][2][Kr][N]
   uint32_t* Kl = Rk + (long long)cnum * 2 * Kr * NN;    // [cnum][2][LK][N]
   const long long polyw = (long long)L * NN;
-  // 1. lift the four inputs: Rt[c][i][Kt][N], i = x0, x1, y0, y1
-  const uint32_t* ins[4] = {io.x0, io.x1, io.y0, io.y1};
-  for (int i = 0; i < 4 && e == hipSuccess; ++i) {
-    LiftArgs la = lift_args(c, ins[i], Rt + (long long)i * Kt * NN, polyw, 4LL * Kt * NN, N, L, Kt);
-    if (io.ins) la.in_ptrs = io.ins + (long long)i * cnum;
-    e = launch_lift(la, cnum, st, tu);
+  // 1. lift the four inputs in one launch: Rt[c][i][Kt][N], i = x0, x1, y0, y1
+  {
+    LiftArgs la = lift_args(c, io.x0, Rt, polyw, (long long)Kt * NN, N, L, Kt);
+    la.interleave4 = true;
+    la.in4[0] = io.x0;
+    la.in4[1] = io.x1;
+    la.in4[2] = io.y0;
+    la.in4[3] = io.y1;
+    la.in_ptrs = io.ins;
+    e = launch_lift(la, 4 * cnum, st, tu);
   }
   // 2. forward NTT column pass of all 4 cnum Kt transforms
   if (e == hipSuccess)

@@ -52,6 +52,10 @@ struct RowsArgs {
 struct LiftArgs {
   const uint32_t* limbs = nullptr; // poly z at limbs + z * in_stride, uint32[L][N] (or in_ptrs[z])
   const uint32_t* const* in_ptrs = nullptr;  // optional device array of per-poly inputs
+  // four interleaved inputs (the tensor's x0, x1, y0, y1): poly z = 4 c + i is ciphertext c
+  // of input i, at in4[i] + c * in_stride, or in_ptrs[i * (npoly / 4) + c]
+  const uint32_t* in4[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool interleave4 = false;
   uint32_t* res = nullptr;          // poly z at res + z * out_stride, uint32[K][N]
   long long in_stride = 0, out_stride = 0;
   int N = 0, L = 0, K = 0;

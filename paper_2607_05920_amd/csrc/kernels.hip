@@ -675,6 +675,15 @@ hipError_t launch_ntt(const NttArgs& a0, int ntr, bool inverse, hipStream_t st, 
 // 40 of them fit a 64-bit accumulator between folds.  The constants are
 // 2^(28 i) 2^32 mod q, and the final Montgomery reduction removes the 2^32.
 
+// The limbs of input polynomial z of a lift.
+__device__ __forceinline__ const uint32_t* lift_source(const LiftArgs& a, uint32_t z) {
+  if (a.interleave4) {
+    const uint32_t i = z & 3u, c = z >> 2;
+    return a.in_ptrs ? a.in_ptrs[i * (uint32_t)(a.npoly >> 2) + c] : a.in4[i] + (long long)c * a.in_stride;
+  }
+  return a.in_ptrs ? a.in_ptrs[z] : a.limbs + (long long)z * a.in_stride;
+}
+
 template <int PB>
 __global__ __launch_bounds__(256) void lift_kernel(LiftArgs a) {
   // Workgroup w runs on XCD w % 8.  The prime groups of one (polynomial,
@@ -689,7 +698,7 @@ __global__ __launch_bounds__(256) void lift_kernel(LiftArgs a) {
   const int z = unit / nb;
   const int jc = (unit % nb) * 256 + threadIdx.x;  // coefficient
   if (jc >= a.N) return;
-  const uint32_t* src = (a.in_ptrs ? a.in_ptrs[z] : a.limbs + (long long)z * a.in_stride) + jc;
+  const uint32_t* src = lift_source(a, (uint32_t)z) + jc;
   uint64_t acc[PB];
 #pragma unroll
   for (int pp = 0; pp < PB; ++pp) acc[pp] = 0;
@@ -782,7 +791,7 @@ __global__ __launch_bounds__(BLK) void lift_mfma_kernel(LiftArgs a) {
     uint32_t lane_off = 4u * h * row + 4u * c;
     opaque(lane_off);
     const uint32_t z = unit >> lg, j0 = (unit & ((1u << lg) - 1u)) << 5;
-    const uint32_t* src = wave_uniform((a.in_ptrs ? a.in_ptrs[z] : a.limbs + (long long)z * a.in_stride) + j0);
+    const uint32_t* src = wave_uniform(lift_source(a, z) + j0);
     // limbs 8 kb + 4 h + r; rows at or beyond L read as zero, where the table is zero too
     const __amdgpu_buffer_rsrc_t rs = row_buffer(src, 4u * ((uint32_t)a.L * (uint32_t)a.N - j0));
     v4i B[NKB];
