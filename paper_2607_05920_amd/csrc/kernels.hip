@@ -314,7 +314,8 @@ __global__ __launch_bounds__(256) void ntt_pass_kernel(NttArgs a) {
 // and stores the outputs, instead of three kernels each reading and writing them.
 // After the forward row pass a thread holds elements e = 16 j + u of its row, which
 // is where the pointwise step and the inverse row pass work, so no exchange is
-// needed between them.  Two LDS buffers alternate, one barrier per exchange.
+// needed between them.  The transposes go through kRowsBuffers LDS buffers, one
+// barrier per exchange of that many rows.
 //   tensor: rows x0, x1, y0, y1 -> d0 = x0 y0, d1 = x0 y1 + x1 y0, d2 = x1 y1 (slots 0..2)
 //   relin:  row d2 and the key's rows b', a' -> k0 = d2 b', k1 = d2 a' (to out)
 //   ring:   rows a, b -> a b (in place of a)

@@ -127,6 +127,30 @@ def test_ring_mul_ragged_batched_in_place(ctx, logN, logq, cnum):
         check(ints(got[c]), want, f"ring_mul {c}")
 
 
+@pytest.mark.parametrize("logq", [2600, 3000, 3500])
+def test_ring_mul_many_primes(logq):
+    """Products that need 175-235 primes: the reconstruction's 6, 7 and 8 k-block
+    forms and the lift's table in global memory, against the oracle on every
+    coefficient (N = 2^10)."""
+    say(f"ring_mul many primes logq={logq}")
+    import torch
+    c = fhe.Context(2400, 2400)
+    try:
+        logN = 10
+        N = 1 << logN
+        need = c.primes_needed(logN, logq, logq, 1)
+        assert 160 < need <= 256 and need <= c.prime_count()
+        rng = np.random.default_rng(logq + 7)
+        a = synth.uniform_limbs(rng, logq, N)
+        b = synth.uniform_limbs(rng, logq, N)
+        out = torch.empty(synth.nlimbs(logq) * N, dtype=torch.int32, device="cuda")
+        c.ring_mul(logN, logq, dev(a), dev(b), out)
+        want = ring.ring_mul(ints(a), ints(b), 1 << logq)
+        check(ints(host(out, (synth.nlimbs(logq), N))), want, f"ring_mul logq={logq}")
+    finally:
+        c.close()
+
+
 def _gpu_he_mult(ctx, evk_limbs, sch, t, logN, logq, logP, x, y, bits, fused=True):
     import torch
     N = 1 << logN
