@@ -429,7 +429,8 @@ __device__ __forceinline__ void inv_rows(uint32_t (&x)[NP][16], uint32_t* const 
 }
 
 // Rows per workgroup of the fused pass: 8 rows of 256 points (128 threads).  The LDS
-// transposes go through kRowsBuffers buffers of 8 rows, as many rows at a time.
+// transposes go through kRowsBuffers buffers of 8 rows in the tensor form (2 in the
+// relin and ring forms), as many rows at a time.
 constexpr int kRowsBuffers = 4;
 template <int S>
 struct RowsShape {
@@ -441,7 +442,9 @@ struct RowsShape {
 template <int S, int MODE>
 __global__ __launch_bounds__(128) void rows_fused_kernel(RowsArgs a) {
   constexpr int n = RowsShape<S>::n, T = RowsShape<S>::T, NSUB = RowsShape<S>::NSUB, SS = RowsShape<S>::SS;
-  constexpr int NB = kRowsBuffers;
+  // the relin and ring forms keep fewer rows live, so fewer buffers (one more barrier)
+  // leave LDS for 3 waves per SIMD, which their registers allow
+  constexpr int NB = MODE == 0 ? kRowsBuffers : 2;
   __shared__ uint32_t lds[NB][NSUB * SS];
 
   const int tid = threadIdx.x;
