@@ -101,7 +101,8 @@ int fhe_ctx_reset_error(fhe_ctx* ctx);
  * every output element it must write, once (limbs and residues of the lift and the
  * reconstruction, transform rows of the NTT passes, ...).  Kernel classes:
  * 0 lift, 1 forward NTT column pass, 2 forward NTT row pass, 3 inverse NTT row
- * pass, 4 inverse NTT column pass, 5 pointwise, 6 reconstruction (CRT),
+ * pass, 4 inverse NTT column pass, 5 pointwise (no longer launched: the fused row
+ * pass does the products), 6 reconstruction (CRT),
  * 7 relinearization compose, 8 rescale, 9 fused row pass (last forward NTT row
  * pass + pointwise products + first inverse row pass, used by the HE-mult and the
  * ring multiply), 10 compose and rescale in one pass (HE-mult with rescale).  Errors: FHE_E_INVAL, FHE_E_STATE (not recording). */

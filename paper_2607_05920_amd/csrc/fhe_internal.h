@@ -71,15 +71,6 @@ struct LiftArgs {
   int lds_max = 0, cus = 0;  // device: LDS bytes per workgroup, compute units
 };
 
-struct PointwiseArgs {
-  uint32_t* a = nullptr; // tensor: group c at a + c * group_stride, 4 x [K][N] (x0, x1, y0, y1)
-  const uint32_t* b = nullptr; // relin: key (B', A') [2][K][N]; ring: second operand
-  uint32_t* out = nullptr;
-  long long group_stride = 0, out_stride = 0;
-  int N = 0, K = 0;
-  const PrimeC* pc = nullptr;
-};
-
 // CRT reconstruction of `npoly` polynomials from canonical residues (the inverse
 // NTT's output with the CRT factor c_k folded in).
 struct CrtArgs {
@@ -173,9 +164,6 @@ int ntt_split_cols(int logN, const Tuning& t);
 // Transposes rows of 2^S words into the register order of the fused relinearization pass.
 hipError_t launch_row_transpose(const uint32_t* src, uint32_t* dst, long long total, int S, hipStream_t s);
 hipError_t launch_lift(const LiftArgs& a, int npoly, hipStream_t s, const Tuning& t = Tuning());
-hipError_t launch_tensor_pointwise(const PointwiseArgs& a, int cnum, hipStream_t s);
-hipError_t launch_relin_pointwise(const PointwiseArgs& a, int cnum, hipStream_t s);
-hipError_t launch_ring_pointwise(const PointwiseArgs& a, int cnum, hipStream_t s);
 hipError_t launch_crt(CrtArgs a, int npoly, hipStream_t s);
 hipError_t launch_compose(const ComposeArgs& a, int cnum, hipStream_t s);
 hipError_t launch_rescale(const RescaleArgs& a, int cnum, hipStream_t s);

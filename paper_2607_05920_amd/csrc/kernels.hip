@@ -480,6 +480,10 @@ __global__ __launch_bounds__(128) void rows_fused_kernel(RowsArgs a) {
 #pragma unroll
       for (int u = 0; u < 16; ++u) x[r][u] = valid ? g[r * KN + u * T + j] : 0u;
     fwd_rows<S, 4, NB>(x, lb, j, tw, tw_mul, q, two_q);
+    // Montgomery products (Eq. ntt_mul) carry a factor 2^-32, compensated in the inverse
+    // transform's final factor.  d1 is formed directly (the Karatsuba identity of
+    // Section 5.4 gives the same value; with full-rate multiplies the direct form issues
+    // fewer instructions).
     uint32_t d[3][16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
@@ -898,78 +902,6 @@ hipError_t launch_lift(const LiftArgs& a, int npoly, hipStream_t st, const Tunin
     case 32: lift_launch<32>(b, npoly, st); break;
     default: lift_launch<16>(b, npoly, st); break;
   }
-  return hipGetLastError();
-}
-
-// ============================================================================ pointwise
-//
-// Hadamard products in the NTT domain (Section 2.3, Eq. ntt_mul).  Montgomery
-// products carry a factor 2^-32, compensated in the inverse transform's final
-// factor.  Tensor: d0 = x0 y0, d1 = x0 y1 + x1 y0, d2 = x1 y1 (the Karatsuba
-// identity of Section 5.4 gives the same d1; with full-rate multiplies the direct
-// form issues fewer instructions).
-
-__global__ __launch_bounds__(256) void tensor_pointwise_kernel(PointwiseArgs a) {
-  const int jc = blockIdx.x * 256 + threadIdx.x;
-  const int p = blockIdx.y;
-  const int c = blockIdx.z;
-  if (jc >= a.N) return;
-  const long long KN = (long long)a.K * a.N;
-  uint32_t* g = a.a + (long long)c * a.group_stride + (long long)p * a.N + jc;
-  const PrimeC pc = a.pc[p];
-  const uint32_t x0 = g[0], x1 = g[KN], y0 = g[2 * KN], y1 = g[3 * KN];
-  const uint32_t d0 = mont_mul(x0, y0, pc.q, pc.qneg);
-  const uint32_t d2 = mont_mul(x1, y1, pc.q, pc.qneg);
-  const uint32_t d1 = add_mod(mont_mul(x0, y1, pc.q, pc.qneg), mont_mul(x1, y0, pc.q, pc.qneg), pc.q);
-  g[0] = d0;
-  g[KN] = d1;
-  g[2 * KN] = d2;
-}
-
-__global__ __launch_bounds__(256) void relin_pointwise_kernel(PointwiseArgs a) {
-  const int jc = blockIdx.x * 256 + threadIdx.x;
-  const int p = blockIdx.y;
-  const int c = blockIdx.z;
-  if (jc >= a.N) return;
-  const long long KN = (long long)a.K * a.N;
-  const long long off = (long long)p * a.N + jc;
-  const PrimeC pc = a.pc[p];
-  const uint32_t d = a.a[(long long)c * a.group_stride + off];
-  uint32_t* o = a.out + (long long)c * a.out_stride + off;
-  o[0] = mont_mul(d, a.b[off], pc.q, pc.qneg);
-  o[KN] = mont_mul(d, a.b[KN + off], pc.q, pc.qneg);
-}
-
-__global__ __launch_bounds__(256) void ring_pointwise_kernel(PointwiseArgs a) {
-  const int jc = blockIdx.x * 256 + threadIdx.x;
-  const int p = blockIdx.y;
-  const int c = blockIdx.z;
-  if (jc >= a.N) return;
-  const long long off = (long long)p * a.N + jc;
-  const PrimeC pc = a.pc[p];
-  uint32_t* x = a.a + (long long)c * a.group_stride + off;
-  const uint32_t y = a.b[(long long)c * a.group_stride + off];
-  *x = mont_mul(*x, y, pc.q, pc.qneg);
-}
-
-hipError_t launch_tensor_pointwise(const PointwiseArgs& a, int cnum, hipStream_t st) {
-  dim3 grid((a.N + 255) / 256, a.K, cnum);
-  Bracket br(KID_POINTWISE, st, 28.0 * cnum * a.K * a.N);  // bytes: 4 residue rows in, 3 out
-  hipLaunchKernelGGL(tensor_pointwise_kernel, grid, dim3(256), 0, st, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_relin_pointwise(const PointwiseArgs& a, int cnum, hipStream_t st) {
-  dim3 grid((a.N + 255) / 256, a.K, cnum);
-  Bracket br(KID_POINTWISE, st, 20.0 * cnum * a.K * a.N);  // bytes: d2 and the key's 2 rows in, 2 out
-  hipLaunchKernelGGL(relin_pointwise_kernel, grid, dim3(256), 0, st, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_ring_pointwise(const PointwiseArgs& a, int cnum, hipStream_t st) {
-  dim3 grid((a.N + 255) / 256, a.K, cnum);
-  Bracket br(KID_POINTWISE, st, 12.0 * cnum * a.K * a.N);  // bytes: 2 rows in, 1 out
-  hipLaunchKernelGGL(ring_pointwise_kernel, grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
