@@ -289,9 +289,8 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    # ---- timed region (per-kernel HIP events recorded on the launch stream)
+    # ---- timed region: K steps bracketed by two HIP events on the launch stream
     log(f"timed: {args.steps} steps of cnum={cnum}")
-    ctx.profile(True)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record(stream)
@@ -302,9 +301,24 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1)
+    value = cnum * args.steps / (ms / 1e3)
+
+    # ---- the same K steps again with a HIP event pair around every kernel launch (on
+    # the launch stream): per-kernel times for the roofline.  The event pairs keep
+    # consecutive kernels from overlapping, so this pass is a little slower and is not
+    # the one `value` comes from.
+    log(f"instrumented: {args.steps} steps of cnum={cnum}")
+    ctx.profile(True)
+    ev2, ev3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev2.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev3.record(stream)
+    torch.cuda.synchronize()
+    ms_instr = ev2.elapsed_time(ev3)
     prof = ctx.profile_read()
     ctx.profile(False)
-    value = cnum * args.steps / (ms / 1e3)
 
     dom = max(prof, key=lambda k: prof[k]["ms"])
     d = prof[dom]
@@ -317,6 +331,7 @@ def main():
         "work_per_launch": d["work"] / max(1, d["launches"]),
         "avg_launch_ms": d["ms"] / max(1, d["launches"]), "launches": d["launches"],
         "share_of_kernel_time": d["ms"] / total_kernel_ms if total_kernel_ms else None,
+        "instrumented_ms_per_step": ms_instr / args.steps,
     }
     kernels = {}
     for k, v in prof.items():
