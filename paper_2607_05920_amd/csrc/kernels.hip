@@ -163,11 +163,17 @@ __device__ __forceinline__ void gs_bfly(uint32_t& X, uint32_t& Y, uint2 w, uint3
   Y = mad_lo(qh, 0u - q, d * w.x);
 }
 
+// Threads per workgroup: column passes of 2^8 and 2^7 points take 64 columns of 1024
+// threads and 64 of 512 (256- and 128-byte runs per row); row passes, and column passes
+// of shorter transforms (fewer columns exist), take 256.
+template <int S, bool ROWS>
+constexpr int ntt_pass_threads() { return ROWS ? 256 : (S >= 8 ? 1024 : (S == 7 ? 512 : 256)); }
+
 template <int S, bool INV, bool ROWS>
-__global__ __launch_bounds__(256) void ntt_pass_kernel(NttArgs a) {
+__global__ __launch_bounds__(ROWS ? 256 : (S >= 8 ? 1024 : (S == 7 ? 512 : 256))) void ntt_pass_kernel(NttArgs a) {
   constexpr int n = 1 << S;
   constexpr int T = n / 16;
-  constexpr int NSUB = 256 / T;
+  constexpr int NSUB = ntt_pass_threads<S, ROWS>() / T;
   // Row stride in LDS, chosen so that both access patterns are free of bank
   // conflicts (element e sits at s * SS + e + e / 16).
   constexpr int SS = ((n + n / 16 + 1 + 31) / 32) * 32 + (ROWS ? T : (NSUB >= 32 ? 1 : 2));
@@ -595,7 +601,8 @@ static hipError_t rows_fused_s(int S, const RowsArgs& a, hipStream_t st) {
 template <int S, bool INV, bool ROWS>
 static hipError_t ntt_pass(const NttArgs& a, int ntr, hipStream_t st) {
   constexpr int n = 1 << S;
-  constexpr int NSUB = 256 / (n / 16);
+  constexpr int BLK = ntt_pass_threads<S, ROWS>();
+  constexpr int NSUB = BLK / (n / 16);
   const int nsub_total = (1 << a.logN) / n;
   const int nwg = (nsub_total + NSUB - 1) / NSUB;
   const int kx = (a.K + 7) / 8;  // primes per XCD (the largest share)
@@ -604,7 +611,7 @@ static hipError_t ntt_pass(const NttArgs& a, int ntr, hipStream_t st) {
   // algorithmic HBM bytes: every element of every transform read and written once
   Bracket br(INV ? (ROWS ? KID_NTT_INV_ROWS : KID_NTT_INV_COLS) : (ROWS ? KID_NTT_FWD_ROWS : KID_NTT_FWD_COLS), st,
              8.0 * ntr * (double)(1 << a.logN));
-  hipLaunchKernelGGL((ntt_pass_kernel<S, INV, ROWS>), grid, dim3(256), 0, st, a);
+  hipLaunchKernelGGL((ntt_pass_kernel<S, INV, ROWS>), grid, dim3(BLK), 0, st, a);
   return hipGetLastError();
 }
 
