@@ -32,21 +32,26 @@ ALU_KERNELS = set()
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_n16_q1555_cnum4.json")
 
 
-def kernels_source_hash() -> str:
+def library_hash() -> str:
+    """SHA-256 of the built library (its kernels and their launch code); the build is
+    deterministic, so edits that change no code leave it as it was."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_2607_05920_amd", "csrc", "kernels.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    try:
+        with open(os.path.join(ROOT, "paper_2607_05920_amd", "libfhe_mi355x.so"), "rb") as f:
+            return hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return ""
 
 
 def measured_traffic(kernel: str):
     """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter summary,
-    or None when there is none or the kernels changed since it was taken."""
+    or None when there is none or the library changed since it was taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernels_source_sha256") != kernels_source_hash():
+    if not t.get("library_sha256") or t.get("library_sha256") != library_hash():
         return None
     k = t.get("kernels", {}).get(kernel)
     return k.get("traffic_bytes_per_dispatch") if k else None

@@ -1249,7 +1249,7 @@ void srv_loop(fhe_server* sv) {
 }
 
 // c = a b in Z_(2^logq)[X]/(X^N + 1) for cnum pairs (lift, NTT, pointwise, iNTT,
-// Garner); the caller holds the context lock and has checked the arguments.
+// CRT reconstruction); the caller holds the context lock and has checked the arguments.
 int ring_mul_locked(fhe_ctx* c, int logN, int logq, const uint32_t* a, const uint32_t* b, uint32_t* out, int cnum,
                     void* stream) {
   hipStream_t st = (hipStream_t)stream;

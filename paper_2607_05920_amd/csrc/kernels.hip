@@ -12,10 +12,10 @@ namespace fhe {
 typedef v4i_t v4i;
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-// Makes a register value opaque to the optimizer.  Applied to loaded values and to
-// lane masks, it keeps clamped, always-in-bounds loads unconditional (otherwise the
-// compiler sinks each into a branch on the mask and waits for it there, one load
-// at a time).
+// Makes a register value opaque to the optimizer.  Uses here: multipliers that must
+// stay 64-bit multiply-adds (not shifts and adds), values that must be computed where
+// written (not re-derived later), and per-iteration offsets of persistent loops (not
+// hoisted out of the loop, where each would hold a register).
 __device__ __forceinline__ void opaque(uint32_t& v) { asm volatile("" : "+v"(v)); }
 
 // A pointer the caller knows to be equal on every lane of the wave, moved to scalar
