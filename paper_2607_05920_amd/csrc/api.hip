@@ -272,11 +272,20 @@ struct PlanCell {
   Tuning tune;
 };
 
+// Graph branches of a captured plan: cells run on up to kPlanBranches concurrent
+// branches of the graph, each with its own scratch, so that small cells (which do not
+// fill the device) overlap.
+constexpr int kPlanBranches = 4;
+
 struct fhe_plan {
   fhe_ctx* ctx = nullptr;
   std::vector<PlanCell> cells;
-  uint32_t* ws = nullptr;
+  std::vector<int> branch;         // per cell: its graph branch
+  uint32_t* ws = nullptr;          // scratch of eager runs and of branch 0
+  uint32_t* bws[kPlanBranches] = {nullptr, nullptr, nullptr, nullptr};  // scratch of branches 1..
   hipStream_t cap = nullptr;
+  hipStream_t bst[kPlanBranches] = {nullptr, nullptr, nullptr, nullptr};  // capture streams 1..
+  hipEvent_t fork = nullptr, join[kPlanBranches] = {nullptr, nullptr, nullptr, nullptr};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int kernels = 0;
@@ -981,11 +990,42 @@ void plan_free(fhe_plan* pl) {
   if (pl->exec) hipGraphExecDestroy(pl->exec);
   if (pl->graph) hipGraphDestroy(pl->graph);
   if (pl->cap) hipStreamDestroy(pl->cap);
+  for (int b = 0; b < kPlanBranches; ++b) {
+    if (pl->bst[b]) hipStreamDestroy(pl->bst[b]);
+    if (pl->join[b]) hipEventDestroy(pl->join[b]);
+    if (pl->bws[b]) hipFree(pl->bws[b]);
+  }
+  if (pl->fork) hipEventDestroy(pl->fork);
   for (PlanCell& cell : pl->cells)
     if (cell.ptrs) hipFree(cell.ptrs);
   for (void* p : {(void*)pl->ws})
     if (p) hipFree(p);
   delete pl;
+}
+
+// Captures the plan's cells as concurrent graph branches on `cap`: branch 0 on `cap`
+// itself, branches 1.. on their own streams, forked from and joined back into `cap`.
+int plan_capture_branches(fhe_plan* pl) {
+  hipError_t e = hipEventRecord(pl->fork, pl->cap);
+  for (int b = 1; b < kPlanBranches && e == hipSuccess; ++b)
+    if (pl->bst[b]) e = hipStreamWaitEvent(pl->bst[b], pl->fork, 0);
+  if (e != hipSuccess) return set_sticky(pl->ctx, e);
+  for (size_t ci = 0; ci < pl->cells.size(); ++ci) {
+    PlanCell& cell = pl->cells[ci];
+    const int b = pl->branch[ci];
+    PipeIO io;
+    io.ins = cell.ptrs;
+    io.outs = cell.ptrs + 4LL * cell.cnum;
+    const int rc = pipeline(pl->ctx, cell.evk, cell.logN, cell.logq, cell.bits, io, cell.cnum,
+                            b ? pl->bst[b] : pl->cap, b ? pl->bws[b] : pl->ws, cell.tune);
+    if (rc != FHE_OK) return rc;
+  }
+  for (int b = 1; b < kPlanBranches && e == hipSuccess; ++b)
+    if (pl->bst[b]) {
+      e = hipEventRecord(pl->join[b], pl->bst[b]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(pl->cap, pl->join[b], 0);
+    }
+  return e == hipSuccess ? FHE_OK : set_sticky(pl->ctx, e);
 }
 
 // ---------------------------------------------------------------- serving loop
@@ -1800,6 +1840,36 @@ int fhe_batch_plan(fhe_ctx* c, const fhe_job* jobs, int njobs, int flags, void* 
     hipError_t e = hipMalloc((void**)&pl->ws, (size_t)std::max(mw, 1LL) * 4);
     if (e != hipSuccess) rc = set_sticky(c, e);
   }
+  // graph branches: cells by decreasing scratch size (a proxy for their work), each to
+  // the branch with the least so far; branches 1.. get scratch for their largest cell
+  pl->branch.assign(pl->cells.size(), 0);
+  if (rc == FHE_OK && (flags & FHE_PLAN_GRAPH)) {
+    std::vector<long long> words(pl->cells.size());
+    std::vector<int> order(pl->cells.size());
+    for (size_t ci = 0; ci < pl->cells.size(); ++ci) {
+      const PlanCell& cell = pl->cells[ci];
+      words[ci] = pipe_size(c, cell.evk, cell.logN, cell.logq, cell.cnum).main_words;
+      order[ci] = (int)ci;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return words[x] > words[y]; });
+    long long load[kPlanBranches] = {0, 0, 0, 0}, need[kPlanBranches] = {0, 0, 0, 0};
+    for (int ci : order) {
+      int b = 0;
+      for (int v = 1; v < kPlanBranches; ++v)
+        if (load[v] < load[b]) b = v;
+      pl->branch[ci] = b;
+      load[b] += words[ci];
+      need[b] = std::max(need[b], words[ci]);
+    }
+    hipError_t e = hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming);
+    for (int b = 1; b < kPlanBranches && e == hipSuccess; ++b) {
+      if (need[b] == 0) continue;  // an empty branch
+      e = hipMalloc((void**)&pl->bws[b], (size_t)need[b] * 4);
+      if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->bst[b], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->join[b], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) rc = set_sticky(c, e);
+  }
   if (rc == FHE_OK && (flags & FHE_PLAN_AUTOTUNE)) {
     set_recorder(nullptr);
     for (PlanCell& cell : pl->cells)
@@ -1812,7 +1882,7 @@ int fhe_batch_plan(fhe_ctx* c, const fhe_job* jobs, int njobs, int flags, void* 
       hipError_t e = hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking);
       if (e == hipSuccess) e = hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess) {
-        rc = plan_run_cells(pl, pl->cap);
+        rc = plan_capture_branches(pl);
         hipGraph_t gr = nullptr;
         const hipError_t e2 = hipStreamEndCapture(pl->cap, &gr);
         pl->graph = gr;
