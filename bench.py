@@ -32,26 +32,30 @@ ALU_KERNELS = set()
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_n16_q1555_cnum4.json")
 
 
-def library_hash() -> str:
-    """SHA-256 of the built library (its kernels and their launch code); the build is
-    deterministic, so edits that change no code leave it as it was."""
+def kernels_code_hash() -> str:
+    """SHA-256 of the kernels' code: `kernels.hip` (the kernels and their launch
+    configuration) without its comments and blank lines, so that comment edits keep a
+    profile taken of the same code."""
     import hashlib
+    import re
     try:
-        with open(os.path.join(ROOT, "paper_2607_05920_amd", "libfhe_mi355x.so"), "rb") as f:
-            return hashlib.sha256(f.read()).hexdigest()
+        with open(os.path.join(ROOT, "paper_2607_05920_amd", "csrc", "kernels.hip")) as f:
+            src = f.read()
     except OSError:
         return ""
+    lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in src.splitlines()]
+    return hashlib.sha256("\n".join(ln for ln in lines if ln.strip()).encode()).hexdigest()
 
 
 def measured_traffic(kernel: str):
     """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter summary,
-    or None when there is none or the library changed since it was taken."""
+    or None when there is none or the kernels' code changed since it was taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if not t.get("library_sha256") or t.get("library_sha256") != library_hash():
+    if not t.get("kernels_code_sha256") or t.get("kernels_code_sha256") != kernels_code_hash():
         return None
     k = t.get("kernels", {}).get(kernel)
     return k.get("traffic_bytes_per_dispatch") if k else None
