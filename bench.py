@@ -32,30 +32,43 @@ ALU_KERNELS = set()
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_n16_q1555_cnum4.json")
 
 
-def kernels_code_hash() -> str:
-    """SHA-256 of the kernels' code: `kernels.hip` (the kernels and their launch
-    configuration) without its comments and blank lines, so that comment edits keep a
-    profile taken of the same code."""
+def device_code_hash() -> str:
+    """SHA-256 of the device code the library carries (its `.hip_fatbin` ELF section,
+    the gfx950 code objects).  The build is deterministic: edits that change no kernel
+    (comments, host code) keep it; any kernel change alters it."""
     import hashlib
-    import re
+    import struct
     try:
-        with open(os.path.join(ROOT, "paper_2607_05920_amd", "csrc", "kernels.hip")) as f:
-            src = f.read()
+        with open(os.path.join(ROOT, "paper_2607_05920_amd", "libfhe_mi355x.so"), "rb") as f:
+            b = f.read()
     except OSError:
         return ""
-    lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in src.splitlines()]
-    return hashlib.sha256("\n".join(ln for ln in lines if ln.strip()).encode()).hexdigest()
+    if b[:4] != b"\x7fELF" or b[4] != 2:
+        return ""
+    shoff, = struct.unpack_from("<Q", b, 0x28)
+    shentsize, shnum, shstrndx = struct.unpack_from("<HHH", b, 0x3A)
+
+    def header(i):  # (name offset, type, flags, addr, file offset, size, ...)
+        return struct.unpack_from("<IIQQQQIIQQ", b, shoff + i * shentsize)
+
+    names = header(shstrndx)[4]
+    for i in range(shnum):
+        h = header(i)
+        name = b[names + h[0]:b.index(b"\0", names + h[0])]
+        if name == b".hip_fatbin":
+            return hashlib.sha256(b[h[4]:h[4] + h[5]]).hexdigest()
+    return ""
 
 
 def measured_traffic(kernel: str):
     """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter summary,
-    or None when there is none or the kernels' code changed since it was taken."""
+    or None when there is none or the device code changed since it was taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if not t.get("kernels_code_sha256") or t.get("kernels_code_sha256") != kernels_code_hash():
+    if not t.get("device_code_sha256") or t.get("device_code_sha256") != device_code_hash():
         return None
     k = t.get("kernels", {}).get(kernel)
     return k.get("traffic_bytes_per_dispatch") if k else None

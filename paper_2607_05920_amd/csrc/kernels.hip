@@ -170,7 +170,7 @@ template <int S, bool ROWS>
 constexpr int ntt_pass_threads() { return ROWS ? 256 : (S >= 8 ? 1024 : (S == 7 ? 512 : 256)); }
 
 template <int S, bool INV, bool ROWS>
-__global__ __launch_bounds__(ROWS ? 256 : (S >= 8 ? 1024 : (S == 7 ? 512 : 256))) void ntt_pass_kernel(NttArgs a) {
+__global__ __launch_bounds__((ntt_pass_threads<S, ROWS>())) void ntt_pass_kernel(NttArgs a) {
   constexpr int n = 1 << S;
   constexpr int T = n / 16;
   constexpr int NSUB = ntt_pass_threads<S, ROWS>() / T;
