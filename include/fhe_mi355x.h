@@ -229,7 +229,9 @@ typedef struct {
  * into cells of equal (key, logq, bits); each cell runs as one CipherTensor pipeline
  * reading and writing the jobs' buffers through device pointer arrays.  The plan
  * owns its scratch memory, the prepared key levels it needs, and (FHE_PLAN_GRAPH)
- * an instantiated hipGraph.  Planning prepares keys and, with FHE_PLAN_AUTOTUNE, runs
+ * an instantiated hipGraph in which the cells run on up to 4 concurrent branches,
+ * each with its own scratch (so a graphed plan holds up to 4 cells' scratch at once,
+ * against 1 for an eager plan).  Planning prepares keys and, with FHE_PLAN_AUTOTUNE, runs
  * every cell a few times on `stream` (writing the outputs); it synchronizes.  The
  * job buffers must stay valid for the plan's lifetime.  Errors: FHE_E_INVAL,
  * FHE_E_SHAPE, FHE_E_RANGE, FHE_E_NOMEM, FHE_E_DEVICE. */
