@@ -709,6 +709,10 @@ int evk_prepare_locked(fhe_evk* k, int logq, hipStream_t stream) {
     e = launch_lift(lift_args(c, limbs, out, (long long)Lk * N, (long long)Kr * N, N, Lk, Kr), 2, stream);
   if (e == hipSuccess)
     e = launch_ntt(ntt_args(c, out, k->logN, Kr, 2 * Kr, 0, false, nullptr), 2 * Kr, false, stream);
+  // the relinearization's inverse transforms take their final factor (N^-1 2^32 c_k,
+  // see crt_scale) from the key: multiplied in here once
+  const uint2* scr = e == hipSuccess ? crt_scale(c, k->logN, Kr, &e) : nullptr;
+  if (e == hipSuccess) e = launch_scale_rows(out, 2LL * Kr, Kr, N, scr, c->pc, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   hipFree(limbs);
   if (e != hipSuccess) {
@@ -780,8 +784,6 @@ int pipeline(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, const PipeIO&
   const int et = 2 * logq + logN + 1, er = logN + 2 * logq + logP;  // |d_i| < 2^et, |k_i| < 2^er
   const uint2* sct = crt_scale(c, logN, Kt, &e);
   if (!sct) return set_sticky(c, e);
-  const uint2* scr = crt_scale(c, logN, Kr, &e);
-  if (!scr) return set_sticky(c, e);
   const long long NN = N;
   uint32_t* Rt = ws;                                    // [cnum][4][Kt][N]
   uint32_t* Dl = Rt + (long long)cnum * 4 * Kt * NN;    // [cnum][3][L][N]
@@ -836,7 +838,8 @@ int pipeline(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, const PipeIO&
   }
   // 9. inverse NTT column pass; 10. CRT -> k0, k1 mod 2^(logP + logq)
   if (e == hipSuccess)
-    e = launch_ntt_cols(ntt_args(c, Rk, logN, Kr, 2 * Kr, 2LL * Kr * NN, true, scr), cnum * 2 * Kr, true, st, tu);
+    e = launch_ntt_cols(ntt_args(c, Rk, logN, Kr, 2 * Kr, 2LL * Kr * NN, true, nullptr), cnum * 2 * Kr, true, st,
+                        tu);  // the factor is in the prepared key
   if (e == hipSuccess)
     e = run_crt(c, Rk, 2, 2LL * Kr * NN, (long long)Kr * NN, Kl, (long long)LK * NN, N, Kr, er, logP + logq,
                 cnum * 2, st);

@@ -29,7 +29,8 @@ struct NttArgs {
   long long group_stride = 0;
   const uint2* tw = nullptr; // [prime][kNMax] (w, floor(w 2^32 / q)), bit-reversed powers
   const PrimeC* pc = nullptr;
-  const uint2* scale = nullptr; // inverse only: per-prime final factor (w, w')
+  const uint2* scale = nullptr; // inverse only: per-prime final factor (w, w'); null: the
+                                // inputs already carry it (only the canonical reduction)
   int ntr = 0;         // number of transforms (set by launch_ntt; a multiple of K)
 };
 
@@ -163,6 +164,10 @@ hipError_t launch_rows_fused(const RowsArgs& a, int mode, hipStream_t s, const T
 int ntt_split_cols(int logN, const Tuning& t);
 // Transposes rows of 2^S words into the register order of the fused relinearization pass.
 hipError_t launch_row_transpose(const uint32_t* src, uint32_t* dst, long long total, int S, hipStream_t s);
+// data[r][j] <- data[r][j] scale[r mod K] mod q_(r mod K) for `rows` rows of N words
+// (canonical in, canonical out).
+hipError_t launch_scale_rows(uint32_t* data, long long rows, int K, int N, const uint2* scale, const PrimeC* pc,
+                             hipStream_t s);
 hipError_t launch_lift(const LiftArgs& a, int npoly, hipStream_t s, const Tuning& t = Tuning());
 hipError_t launch_crt(CrtArgs a, int npoly, hipStream_t s);
 hipError_t launch_compose(const ComposeArgs& a, int cnum, hipStream_t s);

@@ -301,10 +301,15 @@ __global__ __launch_bounds__((ntt_pass_threads<S, ROWS>())) void ntt_pass_kernel
         for (int u = 2 * hd * g; u < 2 * hd * g + hd; ++u) gs_bfly(x[u], x[u + hd], w, q, two_q);
       }
     }
-    if (!ROWS) {  // last inverse pass: final factor, canonical output
-      const uint2 sc = a.scale[p];
+    if (!ROWS) {  // last inverse pass: final factor (unless the inputs carry it), canonical output
+      if (a.scale) {
+        const uint2 sc = a.scale[p];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) x[u] = csub(shoup_lazy(x[u], sc.x, sc.y, q), q);
+        for (int u = 0; u < 16; ++u) x[u] = csub(shoup_lazy(x[u], sc.x, sc.y, q), q);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) x[u] = csub(x[u], q);
+      }
     }
     if (valid) {
 #pragma unroll
@@ -640,6 +645,25 @@ hipError_t launch_row_transpose(const uint32_t* src, uint32_t* dst, long long to
   if (total <= 0) return hipSuccess;
   if (S < 4 || (total & ((1LL << S) - 1)) != 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(row_transpose_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, src, dst, total, S);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void scale_rows_kernel(uint32_t* data, long long total, int K, int logN,
+                                                        const uint2* scale, const PrimeC* pc) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= total) return;
+  const int p = (int)((i >> logN) % K);
+  const uint32_t q = pc[p].q;
+  data[i] = csub(shoup_lazy(data[i], scale[p].x, scale[p].y, q), q);
+}
+
+hipError_t launch_scale_rows(uint32_t* data, long long rows, int K, int N, const uint2* scale, const PrimeC* pc,
+                             hipStream_t st) {
+  const long long total = rows * N;
+  if (total <= 0) return hipSuccess;
+  if (K <= 0 || (N & (N - 1)) != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(scale_rows_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, data, total, K,
+                     __builtin_ctz((unsigned)N), scale, pc);
   return hipGetLastError();
 }
 
