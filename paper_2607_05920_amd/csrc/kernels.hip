@@ -440,9 +440,9 @@ __device__ __forceinline__ void inv_rows(uint32_t (&x)[NP][16], uint32_t* const 
 }
 
 // Rows per workgroup of the fused pass: 8 rows of 256 points (128 threads).  The LDS
-// transposes go through kRowsBuffers buffers of 8 rows in the tensor form (2 in the
-// relin and ring forms), as many rows at a time.
-constexpr int kRowsBuffers = 4;
+// transposes go through kRowsBuffers buffers of 8 rows, as many rows at a time: with
+// the registers of 3 waves per SIMD (168), 6 workgroups of 2 buffers fit in the LDS.
+constexpr int kRowsBuffers = 2;
 template <int S>
 struct RowsShape {
   static constexpr int n = 1 << S, T = n / 16;
@@ -451,11 +451,10 @@ struct RowsShape {
 };
 
 template <int S, int MODE>
-__global__ __launch_bounds__(128) void rows_fused_kernel(RowsArgs a) {
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void rows_fused_kernel(RowsArgs a) {
   constexpr int n = RowsShape<S>::n, T = RowsShape<S>::T, NSUB = RowsShape<S>::NSUB, SS = RowsShape<S>::SS;
-  // the relin and ring forms keep fewer rows live, so fewer buffers (one more barrier)
-  // leave LDS for 3 waves per SIMD, which their registers allow
-  constexpr int NB = MODE == 0 ? kRowsBuffers : 2;
+  constexpr int NB = kRowsBuffers;
+  static_assert(NB == 2, "the relin and ring forms below pair their exchanges with 2 buffers");
   __shared__ uint32_t lds[NB][NSUB * SS];
 
   const int tid = threadIdx.x;
@@ -484,12 +483,20 @@ __global__ __launch_bounds__(128) void rows_fused_kernel(RowsArgs a) {
   for (int b = 0; b < NB; ++b) lb[b] = lds[b] + s * SS;
 
   if (MODE == 0) {  // tensor, in place: slots 0..3 in, 0..2 out
-    uint32_t* g = a.data + (long long)c * a.group_stride + row;
+    // one buffer over the workgroup's rows: a lane's 32-bit offset addresses its
+    // sub-row, the slot goes into the scalar offset, and the lanes of a sub-row past the
+    // last take an offset beyond the buffer, so that their loads return zero and their
+    // stores are dropped (the range check), with no branches
+    const long long sg0 = (long long)(rem % nwg) * NSUB;
+    uint32_t* gw = wave_uniform(a.data + (long long)c * a.group_stride + (long long)p * N + sg0 * n);
+    const __amdgpu_buffer_rsrc_t rs = row_buffer(gw, (uint32_t)((3 * KN + NSUB * n) * 4));
+    const uint32_t lane = valid ? 4u * (uint32_t)(s * n + j) : 0x7FFFFF00u;
     uint32_t x[4][16];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int u = 0; u < 16; ++u) x[r][u] = valid ? g[r * KN + u * T + j] : 0u;
+      for (int u = 0; u < 16; ++u)
+        x[r][u] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(lane + 4u * u * T), (int)(4 * r * KN), 0);
     fwd_rows<S, 4, NB>(x, lb, j, tw, tw_mul, q, two_q);
     // Montgomery products (Eq. ntt_mul) carry a factor 2^-32, compensated in the inverse
     // transform's final factor.  d1 is formed directly (the Karatsuba identity of
@@ -505,12 +512,11 @@ __global__ __launch_bounds__(128) void rows_fused_kernel(RowsArgs a) {
     }
     __syncthreads();  // every thread has read the forward exchange before it is overwritten
     inv_rows<S, 3, NB>(d, lb, j, itw, tw_mul, q, two_q);
-    if (valid) {
 #pragma unroll
-      for (int r = 0; r < 3; ++r)
+    for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int u = 0; u < 16; ++u) g[r * KN + u * T + j] = d[r][u];
-    }
+      for (int u = 0; u < 16; ++u)
+        __builtin_amdgcn_raw_buffer_store_b32(d[r][u], rs, (int)(lane + 4u * u * T), (int)(4 * r * KN), 0);
   } else if (MODE == 1) {  // relin: d2 row times the key's two rows, to out
     const uint32_t* g = a.data + (long long)c * a.group_stride + row;
     uint32_t* o = a.out + (long long)c * a.out_stride + row;
@@ -529,18 +535,9 @@ __global__ __launch_bounds__(128) void rows_fused_kernel(RowsArgs a) {
       k[0][u] = mont_mul(x[0][u], b, q, qneg);
       k[1][u] = mont_mul(x[0][u], ak, q, qneg);
     }
-    // buffers the forward exchange did not use, or after a barrier the same one
-    if constexpr (NB >= 3) {
-      uint32_t* const li[2] = {lb[1 % NB], lb[2 % NB]};
-      inv_rows<S, 2, 2>(k, li, j, itw, tw_mul, q, two_q);
-    } else if constexpr (NB == 2) {
-      uint32_t* const li[1] = {lb[1 % NB]};
-      inv_rows<S, 2, 1>(k, li, j, itw, tw_mul, q, two_q);
-    } else {
-      __syncthreads();
-      uint32_t* const li[1] = {lb[0]};
-      inv_rows<S, 2, 1>(k, li, j, itw, tw_mul, q, two_q);
-    }
+    // the buffer the forward exchange did not use
+    uint32_t* const li[1] = {lb[1]};
+    inv_rows<S, 2, 1>(k, li, j, itw, tw_mul, q, two_q);
     if (valid) {
 #pragma unroll
       for (int r = 0; r < 2; ++r)
@@ -556,18 +553,13 @@ __global__ __launch_bounds__(128) void rows_fused_kernel(RowsArgs a) {
       x[0][u] = valid ? ga[u * T + j] : 0u;
       x[1][u] = valid ? gb[u * T + j] : 0u;
     }
-    if constexpr (NB >= 2) {
-      uint32_t* const lf[2] = {lb[0], lb[1 % NB]};
-      fwd_rows<S, 2, 2>(x, lf, j, tw, tw_mul, q, two_q);
-    } else {
-      uint32_t* const lf[1] = {lb[0]};
-      fwd_rows<S, 2, 1>(x, lf, j, tw, tw_mul, q, two_q);
-    }
+    uint32_t* const lf[2] = {lb[0], lb[1]};
+    fwd_rows<S, 2, 2>(x, lf, j, tw, tw_mul, q, two_q);
     uint32_t y[1][16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) y[0][u] = mont_mul(x[0][u], x[1][u], q, qneg);
-    if (NB < 3) __syncthreads();  // the forward exchange's buffers are reused
-    uint32_t* const li[1] = {lb[2 % NB]};
+    __syncthreads();  // the forward exchange's buffers are reused
+    uint32_t* const li[1] = {lb[0]};
     inv_rows<S, 1, 1>(y, li, j, itw, tw_mul, q, two_q);
     if (valid) {
 #pragma unroll
@@ -583,6 +575,9 @@ static hipError_t rows_fused(const RowsArgs& a, hipStream_t st) {
   const int nsub_total = (1 << a.logN) / n;
   const int nwg = (nsub_total + NSUB - 1) / NSUB;
   const int kx = (a.K + 7) / 8;
+  // the tensor form's buffer spans 3 K N + NSUB n words and must stay below the
+  // out-of-range lane offset 0x7FFFFF00 (bytes)
+  if ((3LL * a.K * (1LL << a.logN) + (long long)NSUB * n) * 4 >= 0x70000000LL) return hipErrorInvalidValue;
   dim3 grid(8 * kx * a.cnum * nwg);
   // algorithmic HBM bytes per (ciphertext, prime): tensor 4 rows in, 3 out; relin
   // 1 + 2 key rows in, 2 out; ring 2 in, 1 out
