@@ -450,8 +450,10 @@ struct RowsShape {
   static constexpr int SS = ((n + n / 16 + 1 + 31) / 32) * 32 + T;
 };
 
+// 3 waves per SIMD where the LDS allows it (rows of 64 points and more)
 template <int S, int MODE>
-__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void rows_fused_kernel(RowsArgs a) {
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 : 2))) void rows_fused_kernel(
+    RowsArgs a) {
   constexpr int n = RowsShape<S>::n, T = RowsShape<S>::T, NSUB = RowsShape<S>::NSUB, SS = RowsShape<S>::SS;
   constexpr int NB = kRowsBuffers;
   static_assert(NB == 2, "the relin and ring forms below pair their exchanges with 2 buffers");
@@ -477,20 +479,20 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void r
   const uint2* itw = a.itw + (long long)p * kNMax;
   const int tw_mul = nsub_total + sg;
   const long long KN = (long long)a.K * N;
-  const long long row = (long long)p * N + (long long)sg * n;  // row sg of prime p
+  // Rows are addressed through buffer resources from the workgroup's first row of
+  // prime p: a lane's 32-bit offset selects its sub-row, a slot or key row goes into
+  // the scalar offset, and the lanes of a sub-row past the last take an offset beyond
+  // the buffer, so that their loads return zero and their stores are dropped (the
+  // range check), with no branches and no 64-bit addresses held in registers.
+  const long long base = (long long)p * N + (long long)(rem % nwg) * NSUB * n;
+  const uint32_t lane = valid ? 4u * (uint32_t)(s * n + j) : 0x7FFFFF00u;
   uint32_t* lb[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) lb[b] = lds[b] + s * SS;
 
   if (MODE == 0) {  // tensor, in place: slots 0..3 in, 0..2 out
-    // one buffer over the workgroup's rows: a lane's 32-bit offset addresses its
-    // sub-row, the slot goes into the scalar offset, and the lanes of a sub-row past the
-    // last take an offset beyond the buffer, so that their loads return zero and their
-    // stores are dropped (the range check), with no branches
-    const long long sg0 = (long long)(rem % nwg) * NSUB;
-    uint32_t* gw = wave_uniform(a.data + (long long)c * a.group_stride + (long long)p * N + sg0 * n);
-    const __amdgpu_buffer_rsrc_t rs = row_buffer(gw, (uint32_t)((3 * KN + NSUB * n) * 4));
-    const uint32_t lane = valid ? 4u * (uint32_t)(s * n + j) : 0x7FFFFF00u;
+    const __amdgpu_buffer_rsrc_t rs =
+        row_buffer(wave_uniform(a.data + (long long)c * a.group_stride + base), (uint32_t)((3 * KN + NSUB * n) * 4));
     uint32_t x[4][16];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -518,40 +520,41 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void r
       for (int u = 0; u < 16; ++u)
         __builtin_amdgcn_raw_buffer_store_b32(d[r][u], rs, (int)(lane + 4u * u * T), (int)(4 * r * KN), 0);
   } else if (MODE == 1) {  // relin: d2 row times the key's two rows, to out
-    const uint32_t* g = a.data + (long long)c * a.group_stride + row;
-    uint32_t* o = a.out + (long long)c * a.out_stride + row;
+    const uint32_t bytes = (uint32_t)((KN + NSUB * n) * 4);
+    const __amdgpu_buffer_rsrc_t ri = row_buffer(wave_uniform(a.data + (long long)c * a.group_stride + base), bytes);
+    const __amdgpu_buffer_rsrc_t rk = row_buffer(wave_uniform(a.key + base), bytes);
+    const __amdgpu_buffer_rsrc_t ro = row_buffer(wave_uniform(a.out + (long long)c * a.out_stride + base), bytes);
     uint32_t x[1][16], k[2][16];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) x[0][u] = valid ? g[u * T + j] : 0u;
+    for (int u = 0; u < 16; ++u) x[0][u] = __builtin_amdgcn_raw_buffer_load_b32(ri, (int)(lane + 4u * u * T), 0, 0);
     uint32_t* const lf[1] = {lb[0]};
     fwd_rows<S, 1, 1>(x, lf, j, tw, tw_mul, q, two_q);
     // the key rows are stored transposed (launch_row_transpose): thread j's element
     // 16 j + u sits at u T + j, so that these loads are coalesced
-    const uint32_t* kb = a.key + row;
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const long long e = u * T + j;
-      const uint32_t b = valid ? kb[e] : 0u, ak = valid ? kb[KN + e] : 0u;
+      const uint32_t b = __builtin_amdgcn_raw_buffer_load_b32(rk, (int)(lane + 4u * u * T), 0, 0);
+      const uint32_t ak = __builtin_amdgcn_raw_buffer_load_b32(rk, (int)(lane + 4u * u * T), (int)(4 * KN), 0);
       k[0][u] = mont_mul(x[0][u], b, q, qneg);
       k[1][u] = mont_mul(x[0][u], ak, q, qneg);
     }
     // the buffer the forward exchange did not use
     uint32_t* const li[1] = {lb[1]};
     inv_rows<S, 2, 1>(k, li, j, itw, tw_mul, q, two_q);
-    if (valid) {
 #pragma unroll
-      for (int r = 0; r < 2; ++r)
+    for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int u = 0; u < 16; ++u) o[r * KN + u * T + j] = k[r][u];
-    }
+      for (int u = 0; u < 16; ++u)
+        __builtin_amdgcn_raw_buffer_store_b32(k[r][u], ro, (int)(lane + 4u * u * T), (int)(4 * r * KN), 0);
   } else {  // ring: a times b, in place of a
-    uint32_t* ga = a.data + (long long)c * a.group_stride + row;
-    const uint32_t* gb = a.data2 + (long long)c * a.group_stride + row;
+    const uint32_t bytes = (uint32_t)(NSUB * n * 4);
+    const __amdgpu_buffer_rsrc_t ra = row_buffer(wave_uniform(a.data + (long long)c * a.group_stride + base), bytes);
+    const __amdgpu_buffer_rsrc_t rb = row_buffer(wave_uniform(a.data2 + (long long)c * a.group_stride + base), bytes);
     uint32_t x[2][16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      x[0][u] = valid ? ga[u * T + j] : 0u;
-      x[1][u] = valid ? gb[u * T + j] : 0u;
+      x[0][u] = __builtin_amdgcn_raw_buffer_load_b32(ra, (int)(lane + 4u * u * T), 0, 0);
+      x[1][u] = __builtin_amdgcn_raw_buffer_load_b32(rb, (int)(lane + 4u * u * T), 0, 0);
     }
     uint32_t* const lf[2] = {lb[0], lb[1]};
     fwd_rows<S, 2, 2>(x, lf, j, tw, tw_mul, q, two_q);
@@ -561,10 +564,8 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void r
     __syncthreads();  // the forward exchange's buffers are reused
     uint32_t* const li[1] = {lb[0]};
     inv_rows<S, 1, 1>(y, li, j, itw, tw_mul, q, two_q);
-    if (valid) {
 #pragma unroll
-      for (int u = 0; u < 16; ++u) ga[u * T + j] = y[0][u];
-    }
+    for (int u = 0; u < 16; ++u) __builtin_amdgcn_raw_buffer_store_b32(y[0][u], ra, (int)(lane + 4u * u * T), 0, 0);
   }
 }
 
@@ -575,8 +576,8 @@ static hipError_t rows_fused(const RowsArgs& a, hipStream_t st) {
   const int nsub_total = (1 << a.logN) / n;
   const int nwg = (nsub_total + NSUB - 1) / NSUB;
   const int kx = (a.K + 7) / 8;
-  // the tensor form's buffer spans 3 K N + NSUB n words and must stay below the
-  // out-of-range lane offset 0x7FFFFF00 (bytes)
+  // the largest buffer (the tensor form's) spans 3 K N + NSUB n words and must stay
+  // below the out-of-range lane offset 0x7FFFFF00 (bytes)
   if ((3LL * a.K * (1LL << a.logN) + (long long)NSUB * n) * 4 >= 0x70000000LL) return hipErrorInvalidValue;
   dim3 grid(8 * kx * a.cnum * nwg);
   // algorithmic HBM bytes per (ciphertext, prime): tensor 4 rows in, 3 out; relin
