@@ -463,11 +463,15 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 
   const int s = tid / T, j = tid % T;
   const int N = 1 << a.logN;
   const int nsub_total = N / n;
-  // XCD-aware: workgroup w runs on XCD w % 8, which takes primes p = w % 8 (mod 8)
+  // XCD-aware: workgroup w runs on XCD w % 8, which takes primes p = w % 8 (mod 8).
+  // The primes run in descending order, the reverse of the column passes, so that
+  // this pass starts on the rows the forward column pass wrote last and the inverse
+  // column pass on the rows this pass wrote last: those still sit in the device's
+  // last-level cache.
   const int nwg = (nsub_total + NSUB - 1) / NSUB;
   const int per_prime = a.cnum * nwg;
   const int w = blockIdx.x, xcd = w & 7, l = w >> 3;
-  const int p = (l / per_prime) * 8 + xcd;
+  const int p = (((a.K + 7) >> 3) - 1 - l / per_prime) * 8 + xcd;
   if (p >= a.K) return;  // whole workgroup exits
   const int rem = l % per_prime;
   const int c = rem / nwg;
