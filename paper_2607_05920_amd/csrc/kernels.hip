@@ -186,17 +186,21 @@ __global__ __launch_bounds__((ntt_pass_threads<S, ROWS>())) void ntt_pass_kernel
   const int N = 1 << a.logN;
   const int nsub_total = N / n;  // blocks (ROWS) or columns (COLS)
   // Workgroup w runs on XCD w % 8 (round-robin dispatch).  XCD x takes the primes
-  // p = x (mod 8), one at a time, and every transform of that prime in turn, so a
-  // prime's twiddle table is read into one L2 once.
+  // p = x (mod 8).  A row pass takes them one at a time, and every transform of that
+  // prime in turn, so a prime's twiddle table is read into one L2 once.  A column
+  // pass reads only the first n entries of each table; the forward one goes through
+  // the transforms in descending order instead, all its primes for each, so that it
+  // starts on the residues the lift wrote last (the last-level cache still holds them).
   const int nwg = (nsub_total + NSUB - 1) / NSUB;  // workgroups per transform
   const int npp = a.ntr / a.K;                     // transforms per prime
+  const int kx = (a.K + 7) >> 3;                   // primes per XCD (the largest share)
   const int w = blockIdx.x, xcd = w & 7, l = w >> 3;
-  const int per_prime = npp * nwg;
-  const int p = (l / per_prime) * 8 + xcd;
+  constexpr bool BY_TRANSFORM = !INV && !ROWS;
+  const int p = (BY_TRANSFORM ? (l / nwg) % kx : l / (npp * nwg)) * 8 + xcd;
   if (p >= a.K) return;  // whole workgroup exits (primes not a multiple of 8)
-  const int rem = l % per_prime;
-  const int jp = rem / nwg;  // transform index among those of prime p
-  const int sg = (rem % nwg) * NSUB + s;
+  // transform index among those of prime p
+  const int jp = BY_TRANSFORM ? npp - 1 - l / (kx * nwg) : (l / nwg) % npp;
+  const int sg = (l % nwg) * NSUB + s;
   const bool valid = sg < nsub_total;
   // transform jp of prime p: polynomial i of group grp, row r = i K + p
   const int pk = a.per_group / a.K;  // polynomials per group
