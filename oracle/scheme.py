@@ -206,15 +206,19 @@ def bgv_decode(mu, t: int, gamma: int) -> list[int]:
 
 # ---------------------------------------------------------------- the hot path
 
-def tensor(x: Ciphertext, y: Ciphertext):
+def _products(pairs, modulus: int, mapper):
+    """ring_mul of each (a, b) pair mod ``modulus``; ``mapper`` is ``map`` or a process
+    pool's map (the products are independent; the order of results is kept)."""
+    return list(mapper(ring.ring_mul, [p[0] for p in pairs], [p[1] for p in pairs],
+                       [modulus] * len(pairs)))
+
+
+def tensor(x: Ciphertext, y: Ciphertext, mapper=map):
     """d0 = c0 c0', d1 = c0 c1' + c1 c0', d2 = c1 c1', all in Z_(Q_l)[X]/(X^N+1)."""
     if (x.logN, x.logq, x.scheme, x.t) != (y.logN, y.logq, y.scheme, y.t):
         raise ValueError("operands must share N, logq, scheme and t")
     Q = 1 << x.logq
-    d0 = ring.ring_mul(x.c0, y.c0, Q)
-    d2 = ring.ring_mul(x.c1, y.c1, Q)
-    u = ring.ring_mul(x.c0, y.c1, Q)
-    w = ring.ring_mul(x.c1, y.c0, Q)
+    d0, d2, u, w = _products([(x.c0, y.c0), (x.c1, y.c1), (x.c0, y.c1), (x.c1, y.c0)], Q, mapper)
     d1 = [(u[i] + w[i]) % Q for i in range(len(u))]
     return d0, d1, d2
 
@@ -227,7 +231,7 @@ def divide_round(x: int, k: int, scheme: str, t: int) -> int:
     return (x >> k) + center(r * pow(1 << k, -1, t), t)
 
 
-def relinearize(d0, d1, d2, evk: EvalKey, logq: int, scheme: str, t: int):
+def relinearize(d0, d1, d2, evk: EvalKey, logq: int, scheme: str, t: int, mapper=map):
     """k_i = d2 * evk_i mod P Q_l (R3), c_i' = [d_i + R(k_i)]_(Q_l) with R the division of R4/R5."""
     if logq > evk.logQ:
         raise ValueError("ciphertext level above the key level")
@@ -235,17 +239,16 @@ def relinearize(d0, d1, d2, evk: EvalKey, logq: int, scheme: str, t: int):
     PQ = 1 << (evk.logP + logq)
     B = [x % PQ for x in evk.b]
     A = [x % PQ for x in evk.a]
-    k0 = ring.ring_mul(d2, B, PQ)
-    k1 = ring.ring_mul(d2, A, PQ)
+    k0, k1 = _products([(d2, B), (d2, A)], PQ, mapper)
     c0 = [(d0[i] + divide_round(k0[i], evk.logP, scheme, t)) % Q for i in range(len(d0))]
     c1 = [(d1[i] + divide_round(k1[i], evk.logP, scheme, t)) % Q for i in range(len(d1))]
     return c0, c1
 
 
-def mult(x: Ciphertext, y: Ciphertext, evk: EvalKey) -> Ciphertext:
+def mult(x: Ciphertext, y: Ciphertext, evk: EvalKey, mapper=map) -> Ciphertext:
     """Tensor product then relinearization; logp adds (CKKS), gamma multiplies (BGV)."""
-    d0, d1, d2 = tensor(x, y)
-    c0, c1 = relinearize(d0, d1, d2, evk, x.logq, x.scheme, x.t)
+    d0, d1, d2 = tensor(x, y, mapper)
+    c0, c1 = relinearize(d0, d1, d2, evk, x.logq, x.scheme, x.t, mapper)
     gamma = x.gamma * y.gamma % x.t if x.scheme == BGV else 1
     return Ciphertext(c0=c0, c1=c1, logN=x.logN, logq=x.logq, logp=x.logp + y.logp,
                       scheme=x.scheme, t=x.t, gamma=gamma)
@@ -268,9 +271,9 @@ def rescale(ct: Ciphertext, k: int) -> Ciphertext:
                       scheme=ct.scheme, t=ct.t, gamma=gamma)
 
 
-def mult_rescale(x: Ciphertext, y: Ciphertext, evk: EvalKey, k: int) -> Ciphertext:
+def mult_rescale(x: Ciphertext, y: Ciphertext, evk: EvalKey, k: int, mapper=map) -> Ciphertext:
     """HE-mult: tensor, relinearize, then rescale by k bits (R6)."""
-    return rescale(mult(x, y, evk), k)
+    return rescale(mult(x, y, evk, mapper), k)
 
 
 def mult_rescale_sampled(x: Ciphertext, y: Ciphertext, evk: EvalKey, k: int, idx):
