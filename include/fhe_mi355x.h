@@ -105,7 +105,10 @@ int fhe_ctx_reset_error(fhe_ctx* ctx);
  * pass does the products), 6 reconstruction (CRT),
  * 7 relinearization compose, 8 rescale, 9 fused row pass (last forward NTT row
  * pass + pointwise products + first inverse row pass, used by the HE-mult and the
- * ring multiply), 10 compose and rescale in one pass (HE-mult with rescale).  Errors: FHE_E_INVAL, FHE_E_STATE (not recording). */
+ * ring multiply), 10 compose and rescale in one pass (HE-mult with rescale),
+ * 11 coefficient-wise operations (add, sub, negate, moddown, addconst, multconst,
+ * the signed permutations of imult and the automorphisms).  Errors: FHE_E_INVAL,
+ * FHE_E_STATE (not recording). */
 int fhe_ctx_profile(fhe_ctx* ctx, int enable);
 int fhe_ctx_profile_read(fhe_ctx* ctx, int kernel, double* ms, double* work, long long* launches);
 
@@ -161,10 +164,12 @@ int fhe_ring_mul(fhe_ctx* ctx, int logN, int logq, const uint32_t* a, const uint
 /* Upload a relinearization key (b', a') (Section 6.2 "Cryptographic Key
  * Management": relinearization keys) given at modulus P * 2^logQ_key:
  * b_host, a_host are host uint32[L_PQ][N], L_PQ = ceil((logP + logQ_key) / 32).
- * The library keeps the limbs on the device and, per ciphertext level logq used
- * with it, the NTT form of the key reduced mod P * 2^logq (built on first use or by
- * fhe_evk_prepare).  *out is library-owned; release with fhe_evk_destroy.
- * scheme is FHE_CKKS or FHE_BGV; t (odd, 3 <= t < 2^31) is read for BGV only.
+ * The library keeps a host copy of the limbs and, per ciphertext level logq used
+ * with it, the NTT form of the key reduced mod P * 2^logq resident on the device
+ * (built on first use or by fhe_evk_prepare; 2 K_r N words, plus a second layout
+ * for odd logN).  *out is library-owned; release with fhe_evk_destroy.
+ * scheme is FHE_CKKS or FHE_BGV; t (odd, 3 <= t < 2^24, so that the t-corrected
+ * divisions' sums stay within 64 bits) is read for BGV only.
  * Errors: FHE_E_INVAL, FHE_E_RANGE (logQ_key > logQ_max or logP > logP_max),
  * FHE_E_NOMEM, FHE_E_DEVICE. */
 int fhe_evk_create(fhe_ctx* ctx, int scheme, uint32_t t, int logN, int logQ_key, int logP,
@@ -206,6 +211,131 @@ int fhe_mul_relin_rescale(fhe_ctx* ctx, fhe_evk* evk, int logN, int logq, int bi
                           const uint32_t* x0, const uint32_t* x1, const uint32_t* y0,
                           const uint32_t* y1, uint32_t* out0, uint32_t* out1, int cnum,
                           void* stream);
+
+/* ---------------------------------------------------------------- Galois automorphisms
+ * Section 2.5 permutes the slots with the automorphisms kappa_g: X -> X^g (g odd), and
+ * Section 6.2 ("Cryptographic Key Management", rotation and conjugation keys; the
+ * operation list's leftrotate and conjugate) switches the result back to the secret s
+ * with a key per g.  Readings (the paper gives no formulas; the CPU oracle's):
+ *   - kappa_g(a): coefficient i of a moves to position i g mod 2N, negated when that
+ *     position is >= N (X^N = -1), then taken mod 2^logq.
+ *   - A left rotation of the slots by r uses g = 5^r mod 2N; conjugation g = 2N - 1.
+ *   - The switching key for kappa_g is (b', a') over P 2^logQ_key,
+ *     b' = [-a' s + e' + P kappa_g(s)] (BGV: t e'), used mod P 2^logq at level logq.
+ *   - Key switch of (c0, c1): u = kappa_g(c1) in [0, 2^logq),
+ *       c0' = [kappa_g(c0) + R(u b')]_(2^logq),  c1' = [R(u a')]_(2^logq),
+ *     R the CKKS or BGV division by P of the notes at the top of this header. */
+
+/* Signed permutation kappa_g of `count` polynomials: out[c] = kappa_g(in[c]) mod 2^logq,
+ * in/out device uint32[count][L][N], L = ceil(logq / 32); out must not overlap in.
+ * Errors: FHE_E_INVAL (g even or g >= 2N, null, overlap), FHE_E_RANGE (logN, logq). */
+int fhe_automorphism(fhe_ctx* ctx, int logN, int logq, uint32_t g, const uint32_t* in, uint32_t* out, int count,
+                     void* stream);
+
+/* Upload a switching key for kappa_g (host uint32[L_PQ][N] limbs, as fhe_evk_create).
+ * The returned key works with fhe_key_switch and the fhe_ct rotation / conjugation
+ * calls only (the HE-mult entry points reject it with FHE_E_STATE); its limbs stay in
+ * host memory and the NTT form per level is built on the device on first use (or by
+ * fhe_evk_prepare).  Release with fhe_evk_destroy.  Errors: as fhe_evk_create, and
+ * FHE_E_INVAL for g even or g >= 2N. */
+int fhe_galois_key_create(fhe_ctx* ctx, int scheme, uint32_t t, int logN, int logQ_key, int logP, uint32_t g,
+                          const uint32_t* b_host, const uint32_t* a_host, fhe_evk** out);
+
+/* Key switch of cnum ciphertexts by the key's automorphism (see above): in0, in1,
+ * out0, out1 device uint32[cnum][L][N]; outputs must not overlap inputs.  Runs the
+ * signed permutation, then the relinearization half of the HE-mult pipeline (lift of
+ * u onto the relinearization primes, NTT, products with the resident key, inverse NTT,
+ * reconstruction, rounding division by P and addition).  Metadata is unchanged.
+ * Errors: FHE_E_INVAL, FHE_E_STATE (not a Galois key of this context), FHE_E_SHAPE
+ * (logN), FHE_E_RANGE (logq above the key level), FHE_E_NOMEM, FHE_E_DEVICE. */
+int fhe_key_switch(fhe_ctx* ctx, fhe_evk* key, int logN, int logq, const uint32_t* in0, const uint32_t* in1,
+                   uint32_t* out0, uint32_t* out1, int cnum, void* stream);
+
+/* ---------------------------------------------------------------- ciphertexts with metadata
+ * A CipherTensor (Section 6.1) of cnum ciphertexts with equal parameters, with the
+ * metadata of Section 6: logN, logq (the modulus 2^logq), logp (CKKS scale 2^logp),
+ * the scheme, and for BGV the plaintext modulus t and the message factor gamma (the
+ * ciphertext decrypts to gamma m mod t; 1 after encryption).  c0, c1 are caller-owned
+ * device buffers uint32[cnum][L][N], L = ceil(logq / 32).
+ * Every fhe_ct entry point reads all fields of its inputs; of its output it reads only
+ * c0 and c1 (the buffers it writes) and, on success, sets every other field.  For
+ * CKKS gamma is ignored and set to 1 on outputs.
+ * Pairwise mode: a second operand with the same cnum; broadcast mode (Section 6.1): a
+ * second operand (ciphertext or plaintext) with cnum = 1, applied to every ciphertext.
+ * Errors of every call: FHE_E_INVAL (null, bad field, bad argument, forbidden
+ * overlap of output and input), FHE_E_RANGE (logN outside [10, 16], logq beyond the
+ * context's logQ_max + logP_max or the key's level), FHE_E_SHAPE (operands that
+ * differ), plus the errors of the underlying computation. */
+typedef struct {
+  uint32_t* c0;
+  uint32_t* c1;
+  int32_t cnum;
+  int32_t logN, logq, logp, scheme;
+  uint32_t t, gamma;
+} fhe_ct;
+
+/* HE-mult (fhe_mul_relin) with metadata: x, y must share cnum, logN, logq, scheme and
+ * t, and match the key's logN, scheme and t.  out: logq = x.logq,
+ * logp = x.logp + y.logp, gamma = x.gamma y.gamma mod t (BGV).  Output buffers must not
+ * overlap the inputs. */
+int fhe_ct_mul_relin(fhe_ctx* ctx, fhe_evk* evk, const fhe_ct* x, const fhe_ct* y, fhe_ct* out, void* stream);
+
+/* fhe_ct_mul_relin then rescale by `bits` (0: none), fused as fhe_mul_relin_rescale:
+ * out.logq = x.logq - bits; CKKS logp = x.logp + y.logp - bits; BGV
+ * gamma = x.gamma y.gamma 2^-bits mod t. */
+int fhe_ct_mul_relin_rescale(fhe_ctx* ctx, fhe_evk* evk, const fhe_ct* x, const fhe_ct* y, int bits, fhe_ct* out,
+                             void* stream);
+
+/* rescaleBy (Section 6.2; Section 3.2 arbitrary bit counts): out = [R(x)]_(2^(logq-bits)),
+ * 1 <= bits < logq; out.logq = logq - bits; CKKS logp -= bits; BGV gamma *= 2^-bits mod
+ * t.  In place allowed (out buffers = x buffers). */
+int fhe_ct_rescale(fhe_ctx* ctx, const fhe_ct* x, int bits, fhe_ct* out, void* stream);
+
+/* moddownBy (Section 6.2): out = [x]_(2^(logq - bits)), 0 <= bits < logq, logq -= bits,
+ * logp and gamma kept (levels are matched this way before a multiplication).  In place
+ * allowed for cnum = 1 or an unchanged limb count. */
+int fhe_ct_moddown(fhe_ctx* ctx, const fhe_ct* x, int bits, fhe_ct* out, void* stream);
+
+/* add / sub (Section 6.2): out_i = [x_i +- y_(i or 0)]_(2^logq) per component, pairwise
+ * or broadcast.  x and y must agree in logN, logq, logp, scheme, t and gamma.  In place
+ * allowed (out = x or out = y). */
+int fhe_ct_add(fhe_ctx* ctx, const fhe_ct* x, const fhe_ct* y, fhe_ct* out, void* stream);
+int fhe_ct_sub(fhe_ctx* ctx, const fhe_ct* x, const fhe_ct* y, fhe_ct* out, void* stream);
+
+/* negate (Section 6.2): out = [-x]_(2^logq).  In place allowed. */
+int fhe_ct_negate(fhe_ctx* ctx, const fhe_ct* x, fhe_ct* out, void* stream);
+
+/* imult (Section 6.2, CKKS only): every slot times the imaginary unit, i.e. both
+ * components times the monomial X^(N/2) (every slot is an evaluation at a root
+ * zeta^r with r = 1 mod 4, where X^(N/2) is i).  out must not overlap x. */
+int fhe_ct_imult(fhe_ctx* ctx, const fhe_ct* x, fhe_ct* out, void* stream);
+
+/* multconst (Section 6.2, broadcast): out = [(-1)^negative k x]_(2^logq) for the integer
+ * constant k = sum_i k_host[i] 2^(32 i), 1 <= klimbs <= 8 (host array).  A real
+ * constant enters as k = round(c 2^logp_k): CKKS logp += logp_k (BGV keeps logp).  In
+ * place allowed. */
+int fhe_ct_multconst(fhe_ctx* ctx, const fhe_ct* x, const uint32_t* k_host, int klimbs, int negative, int logp_k,
+                     fhe_ct* out, void* stream);
+
+/* multconstvec (Section 6.2): out_i = [x_i m_(i or 0)]_(2^logq), a ring product with a
+ * plaintext polynomial per ciphertext (mcount = cnum, pairwise) or one for all
+ * (mcount = 1, broadcast); m: device uint32[mcount][L][N] in [0, 2^logq) (an encoded
+ * vector at scale 2^logp_m: CKKS logp += logp_m).  Exact, through the ring-product
+ * pipeline.  In place allowed. */
+int fhe_ct_multconstvec(fhe_ctx* ctx, const fhe_ct* x, const uint32_t* m, int mcount, int logp_m, fhe_ct* out,
+                        void* stream);
+
+/* addconst (Section 6.2): out_0 = [x_0 + m_(i or 0)]_(2^logq), out_1 = x_1, with m a
+ * plaintext polynomial already at the ciphertext's scale (CKKS) or already times gamma
+ * (BGV); m: device uint32[mcount][L][N], mcount = cnum or 1.  In place allowed. */
+int fhe_ct_addconst(fhe_ctx* ctx, const fhe_ct* x, const uint32_t* m, int mcount, fhe_ct* out, void* stream);
+
+/* Key switch by a Galois key (fhe_key_switch) with metadata (unchanged); leftrotate
+ * checks that the key's element is 5^r mod 2N, conjugate that it is 2N - 1
+ * (FHE_E_STATE otherwise).  out must not overlap x. */
+int fhe_ct_key_switch(fhe_ctx* ctx, fhe_evk* key, const fhe_ct* x, fhe_ct* out, void* stream);
+int fhe_ct_leftrotate(fhe_ctx* ctx, fhe_evk* key, int r, const fhe_ct* x, fhe_ct* out, void* stream);
+int fhe_ct_conjugate(fhe_ctx* ctx, fhe_evk* key, const fhe_ct* x, fhe_ct* out, void* stream);
 
 /* ---------------------------------------------------------------- batches
  * A batch of HE-mults of uneven ring degree and level (the CipherTensor of Section
@@ -299,21 +429,20 @@ int fhe_decrypt(fhe_ctx* ctx, int scheme, uint32_t t, uint32_t gamma, int logN, 
  * forms a batch from the oldest pending request and the other pending requests of
  * the same cell (key, logq, bits), up to `max_batch`, and launches it as one
  * CipherTensor pipeline (continuous batching; batches on different streams overlap
- * on the device).  Admission is by HBM footprint: the device scratch the server
- * holds (every stream's workspace and rescale staging, sized to the
- * batches it runs) never exceeds `hbm_budget` bytes.  A batch waits while it would
- * not fit, idle streams give their scratch back when the budget requires it, a
- * batch is cut to the size that fits, and a request that cannot fit even alone
- * completes with status FHE_E_NOMEM.  The caller's operand and output buffers and
- * the evaluation keys are not part of the budget.  Keys stay resident;
- * key levels are prepared on first use (call fhe_evk_prepare first to keep that
- * out of the loop).  Times are fhe_clock_ns() values. */
+ * on the device).  Admission is by HBM footprint: fhe_server_create reserves one
+ * device arena of `hbm_budget` bytes, and every running batch takes its scratch from
+ * it (the pipeline's scratch, linear in the batch size); a batch is cut to what the
+ * budget allows, waits while the arena has no room, and a request that cannot fit
+ * even alone completes with status FHE_E_NOMEM.  The scheduler allocates no device
+ * memory.  The caller's operand and output buffers and the evaluation keys are not
+ * part of the budget: the key level a request uses must already be resident
+ * (fhe_evk_prepare).  Times are fhe_clock_ns() values. */
 typedef struct fhe_server fhe_server;
 
 typedef struct {
   uint64_t ticket;   /* as returned by fhe_server_submit */
-  int status;        /* FHE_OK or an error code */
-  int batch;         /* size of the batch the request ran in */
+  int status;        /* FHE_OK or an error code (FHE_E_STATE: cancelled) */
+  int batch;         /* size of the batch the request ran in (0: never launched) */
   uint64_t t_arrive; /* arrival time given at submit */
   uint64_t t_start;  /* launch of its batch */
   uint64_t t_done;   /* completion of its batch as seen by the scheduler */
@@ -322,20 +451,32 @@ typedef struct {
 /* Monotonic clock in nanoseconds (the server's time base). */
 uint64_t fhe_clock_ns(void);
 
-/* Start a server on a context.  nstreams in [1, 16], max_batch in [1, 256]. */
+/* Start a server on a context.  nstreams in [1, 16], max_batch in [1, 256].  Reserves
+ * the arena (hbm_budget rounded down to 256 bytes; 0 reserves nothing and every
+ * request is rejected).  Errors: FHE_E_INVAL, FHE_E_NOMEM (the arena), FHE_E_DEVICE. */
 int fhe_server_create(fhe_ctx* ctx, size_t hbm_budget, int nstreams, int max_batch, fhe_server** out);
 
 /* Queue one request (job fields as in fhe_batch_plan; the buffers must stay valid
- * until the request is reported done).  arrival_ns = 0 means "now"; a time in the
- * future (fhe_clock_ns base) makes the request eligible only from then on, so an
- * arrival schedule can be queued ahead.  Latency is reported from arrival_ns. */
-int fhe_server_submit(fhe_server* srv, const fhe_job* job, uint64_t arrival_ns, uint64_t* ticket);
+ * until the request is reported done).  The request's inputs are read only after the
+ * work queued on `stream` (the caller's stream, NULL = default stream) before this
+ * call has completed: an event recorded there is waited for by the batch's stream.
+ * arrival_ns = 0 means "now"; a time in the future (fhe_clock_ns base) makes the request
+ * eligible only from then on, so an arrival schedule can be queued ahead.  Latency is
+ * reported from arrival_ns.  Builds the context's tables for the job's shape if this
+ * is the first request of that shape.  Errors: FHE_E_INVAL, FHE_E_RANGE, FHE_E_STATE
+ * (a Galois key, a key of another context, the key level not prepared, or the server
+ * stopping), FHE_E_DEVICE. */
+int fhe_server_submit(fhe_server* srv, const fhe_job* job, uint64_t arrival_ns, void* stream, uint64_t* ticket);
 
 /* Move up to `max` completed requests to `out` (host array); *n receives the count. */
 int fhe_server_poll(fhe_server* srv, fhe_done* out, int max, int* n);
 
 /* Block until every submitted request has completed. */
 int fhe_server_drain(fhe_server* srv);
+
+/* Requests not yet launched (queued or scheduled for later) complete at once with
+ * status FHE_E_STATE; batches already on the device run to completion. */
+int fhe_server_cancel(fhe_server* srv);
 
 /* Stop the scheduler after the pending work completes and release the server. */
 void fhe_server_destroy(fhe_server* srv);

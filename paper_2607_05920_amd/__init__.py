@@ -59,10 +59,28 @@ EXPORTS = {
     "fhe_decrypt": (_I, [_P, _I, _U, _U, _I, _I, _P, _P, _P, _P, _P]),
     "fhe_clock_ns": (ctypes.c_uint64, []),
     "fhe_server_create": (_I, [_P, ctypes.c_size_t, _I, _I, ctypes.POINTER(_P)]),
-    "fhe_server_submit": (_I, [_P, _P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]),
+    "fhe_server_submit": (_I, [_P, _P, ctypes.c_uint64, _P, ctypes.POINTER(ctypes.c_uint64)]),
+    "fhe_server_cancel": (_I, [_P]),
     "fhe_server_poll": (_I, [_P, _P, _I, ctypes.POINTER(_I)]),
     "fhe_server_drain": (_I, [_P]),
     "fhe_server_destroy": (None, [_P]),
+    "fhe_automorphism": (_I, [_P, _I, _I, _U, _P, _P, _I, _P]),
+    "fhe_galois_key_create": (_I, [_P, _I, _U, _I, _I, _I, _U, _P, _P, ctypes.POINTER(_P)]),
+    "fhe_key_switch": (_I, [_P, _P, _I, _I, _P, _P, _P, _P, _I, _P]),
+    "fhe_ct_mul_relin": (_I, [_P, _P, _P, _P, _P, _P]),
+    "fhe_ct_mul_relin_rescale": (_I, [_P, _P, _P, _P, _I, _P, _P]),
+    "fhe_ct_rescale": (_I, [_P, _P, _I, _P, _P]),
+    "fhe_ct_moddown": (_I, [_P, _P, _I, _P, _P]),
+    "fhe_ct_add": (_I, [_P, _P, _P, _P, _P]),
+    "fhe_ct_sub": (_I, [_P, _P, _P, _P, _P]),
+    "fhe_ct_negate": (_I, [_P, _P, _P, _P]),
+    "fhe_ct_imult": (_I, [_P, _P, _P, _P]),
+    "fhe_ct_multconst": (_I, [_P, _P, _P, _I, _I, _I, _P, _P]),
+    "fhe_ct_multconstvec": (_I, [_P, _P, _P, _I, _I, _P, _P]),
+    "fhe_ct_addconst": (_I, [_P, _P, _P, _I, _P, _P]),
+    "fhe_ct_key_switch": (_I, [_P, _P, _P, _P, _P]),
+    "fhe_ct_leftrotate": (_I, [_P, _P, _I, _P, _P, _P]),
+    "fhe_ct_conjugate": (_I, [_P, _P, _P, _P, _P]),
 }
 
 PLAN_GRAPH = 1
@@ -75,6 +93,13 @@ class Job(ctypes.Structure):
     """fhe_job: one HE-mult (+ optional rescale) of a batch; pointers are device addresses."""
     _fields_ = [("evk", _P), ("logq", _I), ("bits", _I), ("x0", _P), ("x1", _P), ("y0", _P), ("y1", _P),
                 ("out0", _P), ("out1", _P)]
+
+
+class CT(ctypes.Structure):
+    """fhe_ct: a CipherTensor's device buffers and metadata."""
+    _fields_ = [("c0", _P), ("c1", _P), ("cnum", ctypes.c_int32), ("logN", ctypes.c_int32),
+                ("logq", ctypes.c_int32), ("logp", ctypes.c_int32), ("scheme", ctypes.c_int32),
+                ("t", ctypes.c_uint32), ("gamma", ctypes.c_uint32)]
 
 
 class LibraryMissing(RuntimeError):
@@ -148,7 +173,7 @@ def _need(t, words: int, name: str):
 
 
 class Context:
-    """A library context on one device: prime, twiddle and Garner tables."""
+    """A library context on one device: prime, twiddle, lift and CRT tables."""
 
     def __init__(self, logQ_max: int, logP_max: int, device: int = 0):
         lib = load_library()
@@ -172,8 +197,8 @@ class Context:
     def handle(self):
         return self._h
 
-    KERNELS = ["lift", "ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "pointwise", "garner",
-               "compose", "rescale", "ntt_rows_fused", "compose_rescale"]
+    KERNELS = ["lift", "ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "pointwise", "crt",
+               "compose", "rescale", "ntt_rows_fused", "compose_rescale", "coeffwise"]
 
     def profile(self, enable: bool):
         _check("fhe_ctx_profile", load_library().fhe_ctx_profile(self._h, int(enable)))
@@ -286,10 +311,119 @@ class Context:
             _ptr(out1), cnum, _stream(stream)))
 
 
-class EvalKey:
-    """Relinearization key (b', a') at modulus P 2^logQ; host limb arrays uint32[L][N]."""
+def _ct_in(x: "Ciphertext") -> CT:
+    w = x.cnum * nlimbs(x.logq) << x.logN
+    _need(x.c0, w, "c0")
+    _need(x.c1, w, "c1")
+    return CT(_ptr(x.c0), _ptr(x.c1), x.cnum, x.logN, x.logq, x.logp, x.scheme, x.t, x.gamma)
 
-    def __init__(self, ctx: Context, scheme: int, t: int, logN: int, logQ: int, logP: int, b_limbs, a_limbs):
+
+def _ct_call(ctx: Context, fn: str, args, out, cnum: int, logN: int, logq_out: int, stream):
+    """Calls an fhe_ct entry point whose last two arguments are (out, stream) and
+    returns the output Ciphertext with the metadata the library wrote."""
+    o0, o1 = out
+    w = cnum * nlimbs(logq_out) << logN
+    _need(o0, w, "out c0")
+    _need(o1, w, "out c1")
+    o = CT(_ptr(o0), _ptr(o1), 0, 0, 0, 0, 0, 0, 0)
+    _check(fn, getattr(load_library(), fn)(ctx.handle, *args, ctypes.byref(o), _stream(stream)))
+    return Ciphertext(o0, o1, o.logN, o.logq, o.logp, o.scheme, o.t, o.gamma, o.cnum)
+
+
+def _ctx_ct_methods():
+    """Context methods over Ciphertext (fhe_ct) values: each takes the output buffers
+    ``out = (c0, c1)`` and returns the output Ciphertext with its metadata."""
+
+    def ct_mul_relin(self, evk, x, y, out, bits: int = 0, stream=None):
+        return _ct_call(self, "fhe_ct_mul_relin_rescale",
+                        (evk.handle, ctypes.byref(_ct_in(x)), ctypes.byref(_ct_in(y)), bits), out, x.cnum,
+                        x.logN, x.logq - bits, stream)
+
+    def ct_rescale(self, x, bits: int, out, stream=None):
+        return _ct_call(self, "fhe_ct_rescale", (ctypes.byref(_ct_in(x)), bits), out, x.cnum, x.logN,
+                        x.logq - bits, stream)
+
+    def ct_moddown(self, x, bits: int, out, stream=None):
+        return _ct_call(self, "fhe_ct_moddown", (ctypes.byref(_ct_in(x)), bits), out, x.cnum, x.logN,
+                        x.logq - bits, stream)
+
+    def ct_add(self, x, y, out, stream=None):
+        return _ct_call(self, "fhe_ct_add", (ctypes.byref(_ct_in(x)), ctypes.byref(_ct_in(y))), out, x.cnum,
+                        x.logN, x.logq, stream)
+
+    def ct_sub(self, x, y, out, stream=None):
+        return _ct_call(self, "fhe_ct_sub", (ctypes.byref(_ct_in(x)), ctypes.byref(_ct_in(y))), out, x.cnum,
+                        x.logN, x.logq, stream)
+
+    def ct_negate(self, x, out, stream=None):
+        return _ct_call(self, "fhe_ct_negate", (ctypes.byref(_ct_in(x)),), out, x.cnum, x.logN, x.logq, stream)
+
+    def ct_imult(self, x, out, stream=None):
+        return _ct_call(self, "fhe_ct_imult", (ctypes.byref(_ct_in(x)),), out, x.cnum, x.logN, x.logq, stream)
+
+    def ct_multconst(self, x, k: int, out, logp_k: int = 0, stream=None):
+        """k: a Python int, |k| < 2^256."""
+        import numpy as np
+        mag = abs(int(k))
+        kl = max(1, (mag.bit_length() + 31) // 32)
+        if kl > 8:
+            raise ValueError("constant beyond 256 bits")
+        arr = np.array([(mag >> (32 * i)) & 0xFFFFFFFF for i in range(kl)], dtype=np.uint32)
+        return _ct_call(self, "fhe_ct_multconst",
+                        (ctypes.byref(_ct_in(x)), arr.ctypes.data_as(_P), kl, int(k < 0), logp_k), out, x.cnum,
+                        x.logN, x.logq, stream)
+
+    def ct_multconstvec(self, x, m, mcount: int, out, logp_m: int = 0, stream=None):
+        _need(m, mcount * nlimbs(x.logq) << x.logN, "m")
+        return _ct_call(self, "fhe_ct_multconstvec", (ctypes.byref(_ct_in(x)), _ptr(m), mcount, logp_m), out,
+                        x.cnum, x.logN, x.logq, stream)
+
+    def ct_addconst(self, x, m, mcount: int, out, stream=None):
+        _need(m, mcount * nlimbs(x.logq) << x.logN, "m")
+        return _ct_call(self, "fhe_ct_addconst", (ctypes.byref(_ct_in(x)), _ptr(m), mcount), out, x.cnum,
+                        x.logN, x.logq, stream)
+
+    def ct_key_switch(self, key, x, out, stream=None):
+        return _ct_call(self, "fhe_ct_key_switch", (key.handle, ctypes.byref(_ct_in(x))), out, x.cnum, x.logN,
+                        x.logq, stream)
+
+    def ct_leftrotate(self, key, r: int, x, out, stream=None):
+        return _ct_call(self, "fhe_ct_leftrotate", (key.handle, r, ctypes.byref(_ct_in(x))), out, x.cnum,
+                        x.logN, x.logq, stream)
+
+    def ct_conjugate(self, key, x, out, stream=None):
+        return _ct_call(self, "fhe_ct_conjugate", (key.handle, ctypes.byref(_ct_in(x))), out, x.cnum, x.logN,
+                        x.logq, stream)
+
+    def automorphism(self, logN: int, logq: int, g: int, inp, out, count: int = 1, stream=None):
+        w = count * nlimbs(logq) << logN
+        _need(inp, w, "in")
+        _need(out, w, "out")
+        _check("fhe_automorphism", load_library().fhe_automorphism(self._h, logN, logq, g, _ptr(inp), _ptr(out),
+                                                                   count, _stream(stream)))
+
+    def key_switch(self, key, logq: int, in0, in1, out0, out1, cnum: int = 1, stream=None):
+        w = cnum * nlimbs(logq) << key.logN
+        for t, n in ((in0, "in0"), (in1, "in1"), (out0, "out0"), (out1, "out1")):
+            _need(t, w, n)
+        _check("fhe_key_switch", load_library().fhe_key_switch(self._h, key.handle, key.logN, logq, _ptr(in0),
+                                                               _ptr(in1), _ptr(out0), _ptr(out1), cnum,
+                                                               _stream(stream)))
+
+    for f in (ct_mul_relin, ct_rescale, ct_moddown, ct_add, ct_sub, ct_negate, ct_imult, ct_multconst,
+              ct_multconstvec, ct_addconst, ct_key_switch, ct_leftrotate, ct_conjugate, automorphism, key_switch):
+        setattr(Context, f.__name__, f)
+
+
+_ctx_ct_methods()
+
+
+class EvalKey:
+    """Relinearization key (b', a') at modulus P 2^logQ; host limb arrays uint32[L][N].
+    With ``g`` (odd), a Galois switching key for X -> X^g (fhe_galois_key_create)."""
+
+    def __init__(self, ctx: Context, scheme: int, t: int, logN: int, logQ: int, logP: int, b_limbs, a_limbs,
+                 g: int = 0):
         import numpy as np
         lib = load_library()
         L = nlimbs(logP + logQ)
@@ -298,11 +432,15 @@ class EvalKey:
         if b.shape != (L, 1 << logN) or a.shape != (L, 1 << logN):
             raise ValueError(f"key limbs must be uint32[{L}][{1 << logN}]")
         h = ctypes.c_void_p()
-        _check("fhe_evk_create", lib.fhe_evk_create(ctx.handle, scheme, t, logN, logQ, logP,
-                                                    b.ctypes.data_as(ctypes.c_void_p),
-                                                    a.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)))
+        bp, ap = b.ctypes.data_as(ctypes.c_void_p), a.ctypes.data_as(ctypes.c_void_p)
+        if g:
+            _check("fhe_galois_key_create", lib.fhe_galois_key_create(ctx.handle, scheme, t, logN, logQ, logP, g,
+                                                                      bp, ap, ctypes.byref(h)))
+        else:
+            _check("fhe_evk_create", lib.fhe_evk_create(ctx.handle, scheme, t, logN, logQ, logP, bp, ap,
+                                                        ctypes.byref(h)))
         self._h = h
-        self.ctx, self.scheme, self.t = ctx, scheme, t
+        self.ctx, self.scheme, self.t, self.g = ctx, scheme, t, g
         self.logN, self.logQ, self.logP = logN, logQ, logP
 
     @property
@@ -389,13 +527,18 @@ class Server:
         self._h = h
         self.ctx = ctx
 
-    def submit(self, job, arrival_ns: int = 0) -> int:
+    def submit(self, job, arrival_ns: int = 0, stream=None) -> int:
+        """Queue a request; its inputs are read after the work queued so far on `stream`
+        (default: torch's current stream)."""
         evk, logq, bits, x0, x1, y0, y1, o0, o1 = job
         j = Job(evk.handle.value, logq, bits, _ptr(x0), _ptr(x1), _ptr(y0), _ptr(y1), _ptr(o0), _ptr(o1))
         t = ctypes.c_uint64()
         _check("fhe_server_submit", load_library().fhe_server_submit(self._h, ctypes.byref(j), arrival_ns,
-                                                                     ctypes.byref(t)))
+                                                                     _stream(stream), ctypes.byref(t)))
         return t.value
+
+    def cancel(self):
+        _check("fhe_server_cancel", load_library().fhe_server_cancel(self._h))
 
     def poll(self, max_n: int = 1024):
         buf = (Done * max_n)()
@@ -472,7 +615,8 @@ def to_host(t):
 
 @dataclass
 class Ciphertext:
-    """Device ciphertext batch: c0, c1 of shape [cnum][L][N] plus metadata."""
+    """Device CipherTensor: c0, c1 int32 CUDA tensors holding uint32[cnum][L][N], plus
+    the metadata of fhe_ct."""
     c0: object
     c1: object
     logN: int
@@ -481,3 +625,4 @@ class Ciphertext:
     scheme: int = CKKS
     t: int = 0
     gamma: int = 1
+    cnum: int = 1

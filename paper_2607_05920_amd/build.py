@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfhe_mi355x.so")
-SOURCES = ["api.hip", "kernels.hip", "encode.cpp"]
+SOURCES = ["api.hip", "kernels.hip", "ops.hip", "encode.cpp"]
 
 
 def hipcc() -> str:
@@ -22,7 +22,7 @@ def build(verbose: bool = False) -> str:
         hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
         # packed FP32 instructions are kept out of every code object
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-        # the register-resident Garner kernels are fully unrolled straight-line code
+        # the reconstruction and lift kernels unroll their k-block and tile loops fully
         "-mllvm", "-pragma-unroll-threshold=1000000",
         "-Wno-unused-result", "-Wno-unused-value", "-Wno-unused-command-line-argument",
         "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),

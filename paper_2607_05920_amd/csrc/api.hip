@@ -20,6 +20,7 @@
 
 #include "fhe_internal.h"
 #include "fhe_mi355x.h"
+#include "srv_core.h"
 
 using namespace fhe;
 
@@ -295,6 +296,7 @@ struct fhe_evk {
   fhe_ctx* ctx = nullptr;
   int scheme = 0;
   uint32_t t = 0;
+  uint32_t g = 0;  // 0: relinearization key (of s^2); odd g: switching key of kappa_g(s)
   int logN = 0, logQ = 0, logP = 0;
   std::vector<uint32_t> hb, ha;  // host limbs [L_PQ][N]
   // per logq: [2][K_r][N] in NTT form, each row of the fused pass transposed into its
@@ -768,20 +770,94 @@ PipeSize pipe_size(const fhe_ctx* c, const fhe_evk* k, int logN, int logq, int c
   return z;
 }
 
+// The relinearization half of the HE-mult, shared with the Galois key switch: per
+// ciphertext c, Dl + 3 c L N holds d0, d1, d2 (uint32[3][L][N]).  Lift d2 onto Kr
+// primes, NTT, products with the resident key, iNTT, CRT (k0, k1 mod 2^(logP+logq));
+// c_i = [d_i + R(k_i)]_(2^logq), rescaled in the same pass if bits > 0.  With d1_zero
+// slot 1 is not read and d1 is taken as zero (the key switch).
+int relin_part(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, const PipeIO& io, int cnum, hipStream_t st,
+               uint32_t* Dl, uint32_t* Rr, uint32_t* Rk, uint32_t* Kl, const Tuning& tu, bool d1_zero) {
+  const int N = 1 << logN;
+  const PipeSize z = pipe_size(c, k, logN, logq, cnum);
+  if (z.Kt < 0 || z.Kr < 0) return FHE_E_RANGE;
+  const int Kr = z.Kr, L = z.L, LK = z.LK;
+  const int logP = k->logP;
+  const int rows_log = logN - ntt_split_cols(logN, tu);  // the fused pass's row length
+  const uint32_t* evk_ntt = rows_log == logN / 2 ? k->ntt.at(logq) : k->ntt_alt.at(logq);
+  hipError_t e = hipSuccess;
+  const int er = logN + 2 * logq + logP;  // |k_i| < 2^er
+  const long long NN = N;
+  const long long polyw = (long long)L * NN;
+  // 6. lift d2 onto Kr primes; 7. forward NTT
+  e = launch_lift(lift_args(c, Dl + 2 * polyw, Rr, 3 * polyw, (long long)Kr * NN, N, L, Kr), cnum, st, tu);
+  if (e == hipSuccess)
+    e = launch_ntt_cols(ntt_args(c, Rr, logN, Kr, Kr, (long long)Kr * NN, false, nullptr), cnum * Kr, false, st,
+                        tu);
+  // 8. forward row pass, products with the resident key into Rk[c][0..1][Kr][N],
+  // first inverse row pass
+  if (e == hipSuccess) {
+    RowsArgs ra = rows_args(c, logN, Kr, cnum);
+    ra.data = Rr;
+    ra.group_stride = (long long)Kr * NN;
+    ra.key = evk_ntt;
+    ra.out = Rk;
+    ra.out_stride = 2LL * Kr * NN;
+    e = launch_rows_fused(ra, ROWS_RELIN, st, tu);
+  }
+  // 9. inverse NTT column pass; 10. CRT -> k0, k1 mod 2^(logP + logq)
+  if (e == hipSuccess)
+    e = launch_ntt_cols(ntt_args(c, Rk, logN, Kr, 2 * Kr, 2LL * Kr * NN, true, nullptr), cnum * 2 * Kr, true, st,
+                        tu);  // the factor is in the prepared key
+  if (e == hipSuccess)
+    e = run_crt(c, Rk, 2, 2LL * Kr * NN, (long long)Kr * NN, Kl, (long long)LK * NN, N, Kr, er, logP + logq,
+                cnum * 2, st);
+  // 11. c_i = [d_i + R(k_i)]_(2^logq), to the outputs or (rescale follows) the staging area
+  const uint32_t* pwt = nullptr;
+  if (e == hipSuccess && k->scheme == FHE_BGV) pwt = pow_table(c, k->t, &e);
+  if (e == hipSuccess) {
+    ComposeArgs ca{};
+    ca.k = Kl;
+    ca.kstride = (long long)LK * NN;
+    ca.d = Dl;
+    ca.dstride = polyw;
+    ca.d1_zero = d1_zero ? 1 : 0;
+    if (io.outs) {
+      ca.out0s = io.outs;
+      ca.out1s = io.outs + cnum;
+    } else {
+      ca.out0 = io.out0;
+      ca.out1 = io.out1;
+      ca.ostride = (long long)((logq - bits + 31) / 32) * NN;  // polyw when there is no rescale
+    }
+    ca.N = N;
+    ca.L = L;
+    ca.LK = LK;
+    ca.logq = logq;
+    ca.logP = logP;
+    ca.scheme = k->scheme;
+    if (k->scheme == FHE_BGV) {
+      ca.t = k->t;
+      ca.invP = (uint32_t)invmod(powmod(2, logP, k->t), k->t);
+      ca.pw = pwt;
+    }
+    // 12. with a rescale, both in one pass: the relinearized c_i is never stored
+    ca.bits = bits;
+    if (bits > 0 && k->scheme == FHE_BGV) ca.invB = (uint32_t)invmod(powmod(2, bits, k->t), k->t);
+    e = bits > 0 ? launch_compose_rescale(ca, cnum, st) : launch_compose(ca, cnum, st);
+  }
+  return set_sticky(c, e);
+}
+
 // The HE-mult pipeline: lift, NTT, tensor products, iNTT, CRT (d0, d1, d2 mod
-// 2^logq); lift d2, NTT, products with the resident key, iNTT, CRT (k0, k1 mod
-// 2^(logP+logq)); c_i = [d_i + R(k_i)]_(2^logq), rescaled in the same pass if bits > 0.
+// 2^logq); then the relinearization half (relin_part).
 int pipeline(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, const PipeIO& io, int cnum, hipStream_t st,
              uint32_t* ws, const Tuning& tu) {
   const int N = 1 << logN;
   const PipeSize z = pipe_size(c, k, logN, logq, cnum);
   if (z.Kt < 0 || z.Kr < 0) return FHE_E_RANGE;
-  const int Kt = z.Kt, Kr = z.Kr, L = z.L, LK = z.LK;
-  const int logP = k->logP;
-  const int rows_log = logN - ntt_split_cols(logN, tu);  // the fused pass's row length
-  const uint32_t* evk_ntt = rows_log == logN / 2 ? k->ntt.at(logq) : k->ntt_alt.at(logq);
+  const int Kt = z.Kt, Kr = z.Kr, L = z.L;
   hipError_t e = hipSuccess;
-  const int et = 2 * logq + logN + 1, er = logN + 2 * logq + logP;  // |d_i| < 2^et, |k_i| < 2^er
+  const int et = 2 * logq + logN + 1;  // |d_i| < 2^et
   const uint2* sct = crt_scale(c, logN, Kt, &e);
   if (!sct) return set_sticky(c, e);
   const long long NN = N;
@@ -819,64 +895,8 @@ int pipeline(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, const PipeIO&
   // 5. CRT -> d0, d1, d2 mod 2^logq: Dl[c][i][L][N]
   if (e == hipSuccess)
     e = run_crt(c, Rt, 3, 4LL * Kt * NN, (long long)Kt * NN, Dl, polyw, N, Kt, et, logq, cnum * 3, st);
-  // 6. lift d2 onto Kr primes; 7. forward NTT
-  if (e == hipSuccess)
-    e = launch_lift(lift_args(c, Dl + 2 * polyw, Rr, 3 * polyw, (long long)Kr * NN, N, L, Kr), cnum, st, tu);
-  if (e == hipSuccess)
-    e = launch_ntt_cols(ntt_args(c, Rr, logN, Kr, Kr, (long long)Kr * NN, false, nullptr), cnum * Kr, false, st,
-                        tu);
-  // 8. forward row pass, products with the resident key into Rk[c][0..1][Kr][N],
-  // first inverse row pass
-  if (e == hipSuccess) {
-    RowsArgs ra = rows_args(c, logN, Kr, cnum);
-    ra.data = Rr;
-    ra.group_stride = (long long)Kr * NN;
-    ra.key = evk_ntt;
-    ra.out = Rk;
-    ra.out_stride = 2LL * Kr * NN;
-    e = launch_rows_fused(ra, ROWS_RELIN, st, tu);
-  }
-  // 9. inverse NTT column pass; 10. CRT -> k0, k1 mod 2^(logP + logq)
-  if (e == hipSuccess)
-    e = launch_ntt_cols(ntt_args(c, Rk, logN, Kr, 2 * Kr, 2LL * Kr * NN, true, nullptr), cnum * 2 * Kr, true, st,
-                        tu);  // the factor is in the prepared key
-  if (e == hipSuccess)
-    e = run_crt(c, Rk, 2, 2LL * Kr * NN, (long long)Kr * NN, Kl, (long long)LK * NN, N, Kr, er, logP + logq,
-                cnum * 2, st);
-  // 11. c_i = [d_i + R(k_i)]_(2^logq), to the outputs or (rescale follows) the staging area
-  const uint32_t* pwt = nullptr;
-  if (e == hipSuccess && k->scheme == FHE_BGV) pwt = pow_table(c, k->t, &e);
-  if (e == hipSuccess) {
-    ComposeArgs ca{};
-    ca.k = Kl;
-    ca.kstride = (long long)LK * NN;
-    ca.d = Dl;
-    ca.dstride = polyw;
-    if (io.outs) {
-      ca.out0s = io.outs;
-      ca.out1s = io.outs + cnum;
-    } else {
-      ca.out0 = io.out0;
-      ca.out1 = io.out1;
-      ca.ostride = (long long)((logq - bits + 31) / 32) * NN;  // polyw when there is no rescale
-    }
-    ca.N = N;
-    ca.L = L;
-    ca.LK = LK;
-    ca.logq = logq;
-    ca.logP = logP;
-    ca.scheme = k->scheme;
-    if (k->scheme == FHE_BGV) {
-      ca.t = k->t;
-      ca.invP = (uint32_t)invmod(powmod(2, logP, k->t), k->t);
-      ca.pw = pwt;
-    }
-    // 12. with a rescale, both in one pass: the relinearized c_i is never stored
-    ca.bits = bits;
-    if (bits > 0 && k->scheme == FHE_BGV) ca.invB = (uint32_t)invmod(powmod(2, bits, k->t), k->t);
-    e = bits > 0 ? launch_compose_rescale(ca, cnum, st) : launch_compose(ca, cnum, st);
-  }
-  return set_sticky(c, e);
+  if (e != hipSuccess) return set_sticky(c, e);
+  return relin_part(c, k, logN, logq, bits, io, cnum, st, Dl, Rr, Rk, Kl, tu, false);
 }
 
 // Per-op entry: scratch from the stream's slots, key prepared for the level.
@@ -1039,257 +1059,112 @@ uint64_t now_ns() {
       .count();
 }
 
-struct SrvReq {
-  uint64_t ticket = 0, t_arrive = 0;
+// A served request: the job and the event recorded on the submitter's stream after the
+// work that writes its inputs (the batch's stream waits for it).
+struct SrvJob {
   fhe_job job{};
+  hipEvent_t ready = nullptr;
 };
 
-// Orders scheduled arrivals earliest first (ties by ticket).
-struct SrvLater {
-  bool operator()(const SrvReq& a, const SrvReq& b) const {
-    return a.t_arrive != b.t_arrive ? a.t_arrive > b.t_arrive : a.ticket > b.ticket;
+// The HIP side of the request loop (the executor of SrvCore): one non-blocking stream
+// per slot, scratch carved from one arena allocated at creation, pointer arrays staged
+// through pinned host memory.  The scheduler thread calls launch and poll; nothing on
+// that path allocates device memory.
+struct SrvExec {
+  using Job = SrvJob;
+  using Cell = std::tuple<const fhe_evk*, int, int>;  // (key, logq, rescale bits)
+  struct Slot {
+    hipStream_t st = nullptr;
+    hipEvent_t done = nullptr;
+    const uint32_t** hptr = nullptr;  // pinned host staging of the pointer arrays
+    uint32_t** dptr = nullptr;        // device pointer arrays (6 max_batch)
+  };
+  fhe_ctx* ctx = nullptr;
+  uint8_t* arena = nullptr;
+  std::vector<Slot> slots;
+  std::mutex evm;                  // guards the pool of ready events
+  std::vector<hipEvent_t> events;  // recycled ready events
+
+  Cell cell_of(const Job& j) const { return Cell(j.job.evk, j.job.logq, j.job.bits); }
+  // Scratch bytes per request: the pipeline's scratch is linear in the batch size.
+  size_t unit_bytes(const Job& j) const {
+    return (size_t)pipe_size(ctx, j.job.evk, j.job.evk->logN, j.job.logq, 1).main_words * 4;
+  }
+  uint64_t now() { return now_ns(); }
+
+  hipEvent_t take_event() {
+    std::lock_guard<std::mutex> lk(evm);
+    if (!events.empty()) {
+      hipEvent_t e = events.back();
+      events.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    return hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess ? e : nullptr;
+  }
+  void give_event(hipEvent_t e) {
+    if (!e) return;
+    std::lock_guard<std::mutex> lk(evm);
+    events.push_back(e);
+  }
+
+  int launch(int s, const std::vector<const Job*>& batch, size_t off) {
+    fhe_ctx* c = ctx;
+    Slot& sl = slots[s];
+    const int cnum = (int)batch.size();
+    const fhe_job& j0 = batch[0]->job;
+    std::lock_guard<std::recursive_mutex> g(c->mu);
+    hipSetDevice(c->device);
+    hipError_t e = hipSuccess;
+    // the inputs are ready once the submitters' streams reached their events; a wait
+    // holds the event's state when it is queued, so the event can be reused right after
+    for (const Job* j : batch) {
+      if (j->ready && e == hipSuccess && c->sticky == FHE_OK) e = hipStreamWaitEvent(sl.st, j->ready, 0);
+      give_event(j->ready);
+    }
+    if (c->sticky != FHE_OK) return c->sticky;
+    if (e != hipSuccess) return set_sticky(c, e);
+    // the previous batch of this slot has completed, so its staging may be rewritten
+    for (int m = 0; m < cnum; ++m) {
+      const fhe_job& j = batch[m]->job;
+      sl.hptr[m] = j.x0;
+      sl.hptr[cnum + m] = j.x1;
+      sl.hptr[2 * cnum + m] = j.y0;
+      sl.hptr[3 * cnum + m] = j.y1;
+      sl.hptr[4 * cnum + m] = j.out0;
+      sl.hptr[5 * cnum + m] = j.out1;
+    }
+    e = hipMemcpyAsync(sl.dptr, sl.hptr, 6 * (size_t)cnum * sizeof(void*), hipMemcpyHostToDevice, sl.st);
+    if (e != hipSuccess) return set_sticky(c, e);
+    PipeIO io;
+    io.ins = sl.dptr;
+    io.outs = sl.dptr + 4LL * cnum;
+    const int rc = pipeline(c, j0.evk, j0.evk->logN, j0.logq, j0.bits, io, cnum, sl.st, (uint32_t*)(arena + off),
+                            Tuning());
+    if (rc != FHE_OK) return rc;
+    return set_sticky(c, hipEventRecord(sl.done, sl.st));
+  }
+
+  // A request completed without a launch (rejected or cancelled): its event goes back.
+  void discard(const Job& j) { give_event(j.ready); }
+
+  int poll(int s) {
+    const hipError_t e = hipEventQuery(slots[s].done);
+    if (e == hipSuccess) return 1;
+    if (e == hipErrorNotReady) return 0;
+    std::lock_guard<std::recursive_mutex> g(ctx->mu);
+    return set_sticky(ctx, e);
   }
 };
-
-// Scratch words one batch needs.
-struct SrvNeed {
-  long long main = 0;
-};
-
-// One worker stream with its own scratch and pointer staging.
-struct SrvSlot {
-  hipStream_t st = nullptr;
-  hipEvent_t done = nullptr;
-  bool busy = false;
-  std::vector<SrvReq> reqs;
-  uint64_t t_start = 0;
-  uint32_t* ws = nullptr;
-  long long ws_words = 0;
-  const uint32_t** hptr = nullptr;  // pinned host staging of the pointer arrays
-  uint32_t** dptr = nullptr;        // device pointer arrays (6 max_batch)
-};
-
-// Grows a device buffer to exactly `need` words when it holds fewer.
-hipError_t grow(uint32_t** p, long long* have, long long need, hipStream_t st) {
-  if (*have >= need) return hipSuccess;
-  if (*p) {
-    hipStreamSynchronize(st);
-    hipFree(*p);
-    *p = nullptr;
-    *have = 0;
-  }
-  hipError_t e = hipMalloc((void**)p, (size_t)std::max(need, 1LL) * 4);
-  if (e == hipSuccess) *have = need;
-  return e;
-}
-
-// Requests of one cell (key, logq, rescale bits) run together in one pipeline.
-typedef std::tuple<const fhe_evk*, int, int> SrvCell;
-
-SrvCell cell_of(const fhe_job& j) { return SrvCell(j.evk, j.logq, j.bits); }
-
-SrvNeed batch_need(const fhe_ctx* c, const fhe_job& j, int cnum) {
-  const PipeSize z = pipe_size(c, j.evk, j.evk->logN, j.logq, cnum);
-  SrvNeed n;
-  n.main = z.main_words;
-  return n;
-}
-
-size_t need_bytes(const SrvNeed& n) { return (size_t)n.main * 4; }
-
-size_t slot_held(const SrvSlot& s) { return (size_t)s.ws_words * 4; }
-
-// Bytes the slot holds once grown for `n`.
-size_t slot_after(const SrvSlot& s, const SrvNeed& n) {
-  return (size_t)std::max(s.ws_words, n.main) * 4;
-}
-
-// Frees an idle slot's scratch (its last batch has completed).
-void slot_release(SrvSlot& s) {
-  hipStreamSynchronize(s.st);
-  if (s.ws) hipFree(s.ws), s.ws = nullptr;
-  s.ws_words = 0;
-}
 
 }  // namespace
 
 struct fhe_server {
-  fhe_ctx* ctx = nullptr;
-  size_t budget = 0;
-  int max_batch = 1;
-  std::vector<SrvSlot> slots;
-  std::map<SrvCell, std::deque<SrvReq>> queues;  // arrived requests per cell, in arrival order
-  size_t npending = 0;
-  std::priority_queue<SrvReq, std::vector<SrvReq>, SrvLater> future;  // scheduled arrivals
-  std::vector<fhe_done> done;
-  std::mutex m;
-  std::condition_variable cv;
-  std::thread th;
-  bool stop = false;
-  uint64_t next_ticket = 1, submitted = 0, finished = 0;
+  SrvExec ex;
+  SrvCore<SrvExec>* core = nullptr;
 };
 
 namespace {
-
-// Launches `reqs` (one cell) on a slot.  Called by the scheduler thread (the only
-// thread that touches slot buffers) without the server lock.
-int srv_launch(fhe_server* sv, SrvSlot& sl, std::vector<SrvReq>& reqs, const SrvNeed& need) {
-  fhe_ctx* c = sv->ctx;
-  const int cnum = (int)reqs.size();
-  const fhe_job& j0 = reqs[0].job;
-  std::lock_guard<std::recursive_mutex> g(c->mu);
-  if (c->sticky != FHE_OK) return c->sticky;
-  hipSetDevice(c->device);
-  int rc = evk_prepare_locked(j0.evk, j0.logq, sl.st);
-  if (rc != FHE_OK) return rc;
-  hipError_t e = grow(&sl.ws, &sl.ws_words, need.main, sl.st);
-  if (e != hipSuccess) return set_sticky(c, e);
-  // the previous batch of this slot has completed, so its staging may be rewritten
-  for (int m = 0; m < cnum; ++m) {
-    const fhe_job& j = reqs[m].job;
-    sl.hptr[m] = j.x0;
-    sl.hptr[cnum + m] = j.x1;
-    sl.hptr[2 * cnum + m] = j.y0;
-    sl.hptr[3 * cnum + m] = j.y1;
-    sl.hptr[4 * cnum + m] = j.out0;
-    sl.hptr[5 * cnum + m] = j.out1;
-  }
-  e = hipMemcpyAsync(sl.dptr, sl.hptr, 6 * (size_t)cnum * sizeof(void*), hipMemcpyHostToDevice, sl.st);
-  if (e != hipSuccess) return set_sticky(c, e);
-  PipeIO io;
-  io.ins = sl.dptr;
-  io.outs = sl.dptr + 4LL * cnum;
-  rc = pipeline(c, j0.evk, j0.evk->logN, j0.logq, j0.bits, io, cnum, sl.st, sl.ws, Tuning());
-  if (rc != FHE_OK) return rc;
-  return set_sticky(c, hipEventRecord(sl.done, sl.st));
-}
-
-void srv_finish(fhe_server* sv, const std::vector<SrvReq>& reqs, int status, uint64_t t0, uint64_t t1) {
-  for (const SrvReq& r : reqs) {
-    fhe_done d;
-    d.ticket = r.ticket;
-    d.status = status;
-    d.batch = (int)reqs.size();
-    d.t_arrive = r.t_arrive;
-    d.t_start = t0;
-    d.t_done = t1;
-    sv->done.push_back(d);
-  }
-  sv->finished += reqs.size();
-}
-
-// Picks an idle slot for a batch needing `need` and makes room for it within the
-// budget, freeing other idle slots' scratch (largest first) only when it must.
-// Returns null when the batch has to wait for running batches to complete.
-SrvSlot* srv_place(fhe_server* sv, const SrvNeed& need) {
-  SrvSlot* best = nullptr;
-  size_t best_grow = SIZE_MAX, best_held = SIZE_MAX, held = 0;
-  for (SrvSlot& sl : sv->slots) {
-    held += slot_held(sl);
-    if (sl.busy) continue;
-    const size_t g = slot_after(sl, need) - slot_held(sl);
-    if (g < best_grow || (g == best_grow && slot_held(sl) < best_held)) {
-      best = &sl;
-      best_grow = g;
-      best_held = slot_held(sl);
-    }
-  }
-  if (!best) return nullptr;
-  size_t after = held + best_grow;
-  while (after > sv->budget) {
-    SrvSlot* v = nullptr;
-    for (SrvSlot& sl : sv->slots)
-      if (!sl.busy && &sl != best && slot_held(sl) > 0 && (!v || slot_held(sl) > slot_held(*v))) v = &sl;
-    if (!v) break;
-    after -= slot_held(*v);
-    slot_release(*v);
-  }
-  if (after > sv->budget && after - slot_after(*best, need) + need_bytes(need) <= sv->budget) {
-    // the chosen slot's own buffers are oversized for this batch: refit them exactly
-    after = after - slot_after(*best, need) + need_bytes(need);
-    slot_release(*best);
-  }
-  return after <= sv->budget ? best : nullptr;
-}
-
-void srv_loop(fhe_server* sv) {
-  hipSetDevice(sv->ctx->device);
-  std::unique_lock<std::mutex> lk(sv->m);
-  for (;;) {
-    bool progress = false;
-    // completions
-    for (SrvSlot& sl : sv->slots) {
-      if (sl.busy && hipEventQuery(sl.done) == hipSuccess) {
-        srv_finish(sv, sl.reqs, FHE_OK, sl.t_start, now_ns());
-        sl.busy = false;
-        sl.reqs.clear();
-        progress = true;
-      }
-    }
-    // scheduled arrivals that are due join the queue in arrival order
-    uint64_t now = now_ns();
-    while (!sv->future.empty() && sv->future.top().t_arrive <= now) {
-      sv->queues[cell_of(sv->future.top().job)].push_back(sv->future.top());
-      ++sv->npending;
-      sv->future.pop();
-    }
-    const uint64_t next_arrival = sv->future.empty() ? UINT64_MAX : sv->future.top().t_arrive;
-    // admissions: the oldest request first, batched with the requests of its cell
-    while (sv->npending > 0) {
-      std::deque<SrvReq>* q = nullptr;
-      for (auto& kv : sv->queues) {
-        if (kv.second.empty()) continue;
-        const SrvReq& f = kv.second.front();
-        if (!q || f.t_arrive < q->front().t_arrive ||
-            (f.t_arrive == q->front().t_arrive && f.ticket < q->front().ticket))
-          q = &kv.second;
-      }
-      const fhe_job head = q->front().job;
-      int take = std::min((int)q->size(), sv->max_batch);
-      SrvNeed need = batch_need(sv->ctx, head, take);
-      while (take > 1 && need_bytes(need) > sv->budget) need = batch_need(sv->ctx, head, --take);
-      if (need_bytes(need) > sv->budget) {  // cannot run even alone
-        std::vector<SrvReq> one{q->front()};
-        q->pop_front();
-        --sv->npending;
-        const uint64_t t = now_ns();
-        srv_finish(sv, one, FHE_E_NOMEM, t, t);
-        progress = true;
-        continue;
-      }
-      SrvSlot* sl = srv_place(sv, need);
-      if (!sl) break;  // wait for a slot or for memory
-      std::vector<SrvReq> batch(q->begin(), q->begin() + take);
-      q->erase(q->begin(), q->begin() + take);
-      sv->npending -= take;
-      sl->busy = true;
-      sl->t_start = now_ns();
-      lk.unlock();
-      const int rc = srv_launch(sv, *sl, batch, need);
-      lk.lock();
-      if (rc != FHE_OK) {
-        srv_finish(sv, batch, rc, sl->t_start, now_ns());
-        sl->busy = false;
-      } else {
-        sl->reqs = std::move(batch);
-      }
-      progress = true;
-      now = now_ns();
-    }
-    bool busy = false;
-    for (SrvSlot& sl : sv->slots) busy = busy || sl.busy;
-    if (sv->stop && sv->npending == 0 && sv->future.empty() && !busy) break;
-    if (progress) {
-      sv->cv.notify_all();
-    } else {
-      // sleep until a completion may be due, the next scheduled arrival, or a submit
-      uint64_t wait = busy ? 20000 : 500000;
-      if (next_arrival != UINT64_MAX) wait = std::min(wait, next_arrival > now ? next_arrival - now : 0);
-      if (wait > 0) sv->cv.wait_for(lk, std::chrono::nanoseconds(wait));
-    }
-  }
-  sv->cv.notify_all();
-}
 
 // c = a b in Z_(2^logq)[X]/(X^N + 1) for cnum pairs (lift, NTT, pointwise, iNTT,
 // CRT reconstruction); the caller holds the context lock and has checked the arguments.
@@ -1317,6 +1192,8 @@ int ring_mul_locked(fhe_ctx* c, int logN, int logq, const uint32_t* a, const uin
     ra.data = Ra;
     ra.data2 = Rb;
     ra.group_stride = KN;
+    ra.data2_stride = KN;
+    ra.data2_groups = cnum;
     e = launch_rows_fused(ra, ROWS_RING, st);
   }
   if (e == hipSuccess) e = launch_ntt_cols(ntt_args(c, Ra, logN, K, K, KN, true, sc), cnum * K, true, st);
@@ -1327,6 +1204,129 @@ int ring_mul_locked(fhe_ctx* c, int logN, int logq, const uint32_t* a, const uin
 bool valid_t(int scheme, uint32_t t) {
   if (scheme == FHE_CKKS) return true;
   return scheme == FHE_BGV && t >= 3 && (t & 1) && t < (1u << 24);
+}
+
+uint32_t top_mask(int logq) { return (logq & 31) ? (1u << (logq & 31)) - 1u : 0xFFFFFFFFu; }
+
+// Key switch of cnum ciphertexts by the automorphism kappa_g of a Galois key (Section
+// 2.5): u = kappa_g(c1), c0' = [kappa_g(c0) + R(u b')]_(2^logq), c1' = [R(u a')].  The
+// signed permutation writes kappa_g(c0) and kappa_g(c1) into slots 0 and 2 of the
+// relinearization half's limb area; slot 1 (d1) is taken as zero.
+int key_switch_locked(fhe_ctx* c, fhe_evk* k, int logN, int logq, const uint32_t* in0, const uint32_t* in1,
+                      uint32_t* out0, uint32_t* out1, int cnum, hipStream_t st) {
+  int rc = evk_prepare_locked(k, logq, st);
+  if (rc != FHE_OK) return rc;
+  const PipeSize z = pipe_size(c, k, logN, logq, cnum);
+  if (z.Kt < 0 || z.Kr < 0) return FHE_E_RANGE;
+  const long long NN = 1LL << logN;
+  const long long polyw = (long long)z.L * NN;
+  const long long words = (long long)cnum * NN * (3LL * z.L + 3LL * z.Kr + 2LL * z.LK);
+  hipError_t e = hipSuccess;
+  uint32_t* ws = (uint32_t*)scratch(c, st, 0, (size_t)words * 4, &e);
+  if (!ws) return set_sticky(c, e);
+  uint32_t* Dl = ws;                                  // [cnum][3][L][N]
+  uint32_t* Rr = Dl + (long long)cnum * 3 * polyw;    // [cnum][Kr][N]
+  uint32_t* Rk = Rr + (long long)cnum * z.Kr * NN;    // [cnum][2][Kr][N]
+  uint32_t* Kl = Rk + (long long)cnum * 2 * z.Kr * NN;  // [cnum][2][LK][N]
+  PermArgs pa{};
+  pa.in0 = in0;
+  pa.in1 = in1;
+  pa.out0 = Dl;
+  pa.out1 = Dl + 2 * polyw;
+  pa.istride = polyw;
+  pa.ostride = 3 * polyw;
+  pa.logN = logN;
+  pa.L = z.L;
+  pa.topmask = top_mask(logq);
+  pa.mul = (uint32_t)invmod(k->g, 2ull << logN);
+  pa.add = 0;
+  e = launch_signed_perm(pa, cnum, st);
+  if (e != hipSuccess) return set_sticky(c, e);
+  PipeIO io;
+  io.out0 = out0;
+  io.out1 = out1;
+  return relin_part(c, k, logN, logq, 0, io, cnum, st, Dl, Rr, Rk, Kl, Tuning(), true);
+}
+
+// out_i = m * x_i in Z_(2^logq)[X]/(X^N+1) for both components of cnum ciphertexts,
+// with m_c = m + (c mod mcount) L N (mcount = cnum: pairwise; 1: broadcast).  One ring
+// product pipeline: the components and the plaintexts are lifted and transformed
+// together, the fused row pass multiplies component group g by plaintext g mod mcount.
+int plain_mul_locked(fhe_ctx* c, int logN, int logq, const uint32_t* x0, const uint32_t* x1, const uint32_t* m,
+                     int mcount, uint32_t* out0, uint32_t* out1, int cnum, hipStream_t st) {
+  const int N = 1 << logN;
+  const int L = (logq + 31) / 32;
+  const int eb = 2 * logq + logN;
+  const int K = primes_for_e(c, eb);
+  if (K < 0) return FHE_E_RANGE;
+  hipError_t e = hipSuccess;
+  const uint2* sc = crt_scale(c, logN, K, &e);
+  if (!sc) return set_sticky(c, e);
+  const long long KN = (long long)K * N, LN = (long long)L * N;
+  uint32_t* R = (uint32_t*)scratch(c, st, 0, (size_t)(2LL * cnum + mcount) * KN * 4, &e);
+  if (!R) return set_sticky(c, e);
+  uint32_t* Rm = R + 2LL * cnum * KN;
+  e = launch_lift(lift_args(c, x0, R, LN, KN, N, L, K), cnum, st);
+  if (e == hipSuccess) e = launch_lift(lift_args(c, x1, R + cnum * KN, LN, KN, N, L, K), cnum, st);
+  if (e == hipSuccess) e = launch_lift(lift_args(c, m, Rm, LN, KN, N, L, K), mcount, st);
+  if (e == hipSuccess)
+    e = launch_ntt_cols(ntt_args(c, R, logN, K, K, KN, false, nullptr), (2 * cnum + mcount) * K, false, st);
+  if (e == hipSuccess) {
+    RowsArgs ra = rows_args(c, logN, K, 2 * cnum);
+    ra.data = R;
+    ra.data2 = Rm;
+    ra.group_stride = KN;
+    ra.data2_stride = mcount > 1 ? KN : 0;
+    ra.data2_groups = mcount > 1 ? mcount : 1;
+    e = launch_rows_fused(ra, ROWS_RING, st);
+  }
+  if (e == hipSuccess) e = launch_ntt_cols(ntt_args(c, R, logN, K, K, KN, true, sc), 2 * cnum * K, true, st);
+  if (e == hipSuccess) e = run_crt(c, R, 1, KN, 0, out0, LN, N, K, eb, logq, cnum, st);
+  if (e == hipSuccess) e = run_crt(c, R + cnum * KN, 1, KN, 0, out1, LN, N, K, eb, logq, cnum, st);
+  return set_sticky(c, e);
+}
+
+// ---------------------------------------------------------------- fhe_ct checks
+
+bool ct_valid(const fhe_ctx* c, const fhe_ct* x) {
+  if (!x || !x->c0 || !x->c1 || x->cnum < 0 || x->logq < 1) return false;
+  if (x->scheme != FHE_CKKS && x->scheme != FHE_BGV) return false;
+  if (!valid_t(x->scheme, x->t)) return false;
+  if (x->scheme == FHE_BGV && (x->gamma == 0 || x->gamma >= x->t || std::gcd((uint64_t)x->gamma, (uint64_t)x->t) != 1))
+    return false;
+  (void)c;
+  return true;
+}
+
+// Argument checks shared by the fhe_ct entry points: status, or FHE_OK.
+int ct_check(const fhe_ctx* c, const fhe_ct* x, const fhe_ct* out) {
+  if (!c || !ct_valid(c, x) || !out || !out->c0 || !out->c1) return FHE_E_INVAL;
+  if (check_logN(x->logN) != FHE_OK || x->logq > c->logQ_max + c->logP_max) return FHE_E_RANGE;
+  return FHE_OK;
+}
+
+// Same ring, level, scheme and t (and, with scale, the same logp and gamma).
+bool ct_same(const fhe_ct* x, const fhe_ct* y, bool scale) {
+  if (x->logN != y->logN || x->logq != y->logq || x->scheme != y->scheme || x->t != y->t) return false;
+  return !scale || (x->logp == y->logp && x->gamma == y->gamma);
+}
+
+void ct_meta(fhe_ct* o, const fhe_ct* x, int logq, int logp, uint32_t gamma) {
+  o->cnum = x->cnum;
+  o->logN = x->logN;
+  o->logq = logq;
+  o->logp = logp;
+  o->scheme = x->scheme;
+  o->t = x->t;
+  o->gamma = x->scheme == FHE_BGV ? gamma : 1u;
+}
+
+// Buffers [cnum][L][N] of a and b overlap (either component).
+bool ct_overlap(const fhe_ct* a, int La, const fhe_ct* b, int Lb) {
+  const size_t na = (size_t)a->cnum * La << a->logN, nb = (size_t)b->cnum * Lb << b->logN;
+  auto ov = [](const uint32_t* p, size_t n, const uint32_t* q, size_t m) { return p < q + m && q < p + n; };
+  return ov(a->c0, na, b->c0, nb) || ov(a->c0, na, b->c1, nb) || ov(a->c1, na, b->c0, nb) ||
+         ov(a->c1, na, b->c1, nb);
 }
 
 }  // namespace
@@ -1707,7 +1707,7 @@ void fhe_evk_destroy(fhe_evk* k) {
 int fhe_mul_relin(fhe_ctx* c, fhe_evk* k, int logN, int logq, const uint32_t* x0, const uint32_t* x1,
                   const uint32_t* y0, const uint32_t* y1, uint32_t* out0, uint32_t* out1, int cnum, void* stream) {
   if (!c || !k || !x0 || !x1 || !y0 || !y1 || !out0 || !out1 || cnum < 0 || logq < 1) return FHE_E_INVAL;
-  if (k->ctx != c) return FHE_E_STATE;
+  if (k->ctx != c || k->g != 0) return FHE_E_STATE;
   if (logN != k->logN) return FHE_E_SHAPE;
   if (logq > k->logQ) return FHE_E_RANGE;
   if (cnum == 0) return FHE_OK;
@@ -1748,7 +1748,7 @@ int fhe_mul_relin_rescale(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, 
                           uint32_t* out1, int cnum, void* stream) {
   if (!c || !k || !x0 || !x1 || !y0 || !y1 || !out0 || !out1 || cnum < 0 || logq < 2) return FHE_E_INVAL;
   if (bits < 1 || bits >= logq) return FHE_E_INVAL;
-  if (k->ctx != c) return FHE_E_STATE;
+  if (k->ctx != c || k->g != 0) return FHE_E_STATE;
   if (logN != k->logN) return FHE_E_SHAPE;
   if (logq > k->logQ) return FHE_E_RANGE;
   if (cnum == 0) return FHE_OK;
@@ -1773,7 +1773,7 @@ int fhe_batch_plan(fhe_ctx* c, const fhe_job* jobs, int njobs, int flags, void* 
   for (int i = 0; i < njobs; ++i) {
     const fhe_job& j = jobs[i];
     if (!j.evk || !j.x0 || !j.x1 || !j.y0 || !j.y1 || !j.out0 || !j.out1) return FHE_E_INVAL;
-    if (j.evk->ctx != c) return FHE_E_STATE;
+    if (j.evk->ctx != c || j.evk->g != 0) return FHE_E_STATE;
     if (j.logq < 1 || j.logq > j.evk->logQ) return FHE_E_RANGE;
     if (j.bits < 0 || j.bits >= j.logq) return FHE_E_INVAL;
   }
@@ -1949,86 +1949,418 @@ int fhe_server_create(fhe_ctx* c, size_t hbm_budget, int nstreams, int max_batch
   hipSetDevice(c->device);
   fhe_server* sv = new (std::nothrow) fhe_server();
   if (!sv) return FHE_E_NOMEM;
-  sv->ctx = c;
-  sv->budget = hbm_budget;
-  sv->max_batch = max_batch;
-  sv->slots.resize(nstreams);
+  SrvExec& ex = sv->ex;
+  ex.ctx = c;
+  ex.slots.resize(nstreams);
   hipError_t e = hipSuccess;
-  for (SrvSlot& sl : sv->slots) {
+  const size_t arena = hbm_budget & ~(size_t)255;
+  if (arena) e = hipMalloc((void**)&ex.arena, arena);
+  for (SrvExec::Slot& sl : ex.slots) {
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipHostMalloc((void**)&sl.hptr, 6 * (size_t)max_batch * sizeof(void*), 0);
     if (e == hipSuccess) e = hipMalloc((void**)&sl.dptr, 6 * (size_t)max_batch * sizeof(void*));
   }
-  if (e != hipSuccess) {
-    sv->stop = true;
+  if (e == hipSuccess) sv->core = new (std::nothrow) SrvCore<SrvExec>(ex, arena, nstreams, max_batch);
+  if (e != hipSuccess || !sv->core) {
+    if (e == hipSuccess) e = hipErrorOutOfMemory;
+    note("fhe_server_create", e);
     fhe_server_destroy(sv);
     return status_of(e);
   }
-  sv->th = std::thread(srv_loop, sv);
+  sv->core->start();
   *out = sv;
   return FHE_OK;
 }
 
-int fhe_server_submit(fhe_server* sv, const fhe_job* j, uint64_t arrival_ns, uint64_t* ticket) {
+int fhe_server_submit(fhe_server* sv, const fhe_job* j, uint64_t arrival_ns, void* stream, uint64_t* ticket) {
   if (!sv || !j || !ticket) return FHE_E_INVAL;
   if (!j->evk || !j->x0 || !j->x1 || !j->y0 || !j->y1 || !j->out0 || !j->out1) return FHE_E_INVAL;
-  if (j->evk->ctx != sv->ctx) return FHE_E_STATE;
+  fhe_ctx* c = sv->ex.ctx;
+  if (j->evk->ctx != c || j->evk->g != 0) return FHE_E_STATE;
   if (j->logq < 1 || j->logq > j->evk->logQ) return FHE_E_RANGE;
   if (j->bits < 0 || j->bits >= j->logq) return FHE_E_INVAL;
-  std::lock_guard<std::mutex> lk(sv->m);
-  if (sv->stop) return FHE_E_STATE;
-  SrvReq r;
-  r.ticket = sv->next_ticket++;
-  r.t_arrive = arrival_ns ? arrival_ns : now_ns();
-  r.job = *j;
-  if (r.t_arrive > now_ns()) {
-    sv->future.push(r);
-  } else {
-    sv->queues[cell_of(r.job)].push_back(r);
-    ++sv->npending;
+  SrvJob sj;
+  sj.job = *j;
+  {
+    // the key level must be resident already; the context's tables for this shape are
+    // built here, outside the scheduler (nothing on its path allocates)
+    std::lock_guard<std::recursive_mutex> g(c->mu);
+    if (c->sticky != FHE_OK) return c->sticky;
+    if (!j->evk->ntt.count(j->logq)) return FHE_E_STATE;
+    hipSetDevice(c->device);
+    hipError_t e = hipSuccess;
+    if (!tables_prewarm(c, j->evk, j->evk->logN, j->logq, &e)) return set_sticky(c, e);
+    if (j->evk->scheme == FHE_BGV && !pow_table(c, j->evk->t, &e)) return set_sticky(c, e);
+    sj.ready = sv->ex.take_event();
+    if (!sj.ready) return FHE_E_NOMEM;
+    e = hipEventRecord(sj.ready, (hipStream_t)stream);
+    if (e != hipSuccess) {
+      sv->ex.give_event(sj.ready);
+      return set_sticky(c, e);
+    }
   }
-  ++sv->submitted;
-  *ticket = r.ticket;
-  sv->cv.notify_all();
+  const uint64_t t = sv->core->submit(sj, arrival_ns);
+  if (!t) {
+    sv->ex.give_event(sj.ready);
+    return FHE_E_STATE;
+  }
+  *ticket = t;
   return FHE_OK;
 }
 
 int fhe_server_poll(fhe_server* sv, fhe_done* out, int max, int* n) {
   if (!sv || !n || max < 0 || (max > 0 && !out)) return FHE_E_INVAL;
-  std::lock_guard<std::mutex> lk(sv->m);
-  const int k = std::min(max, (int)sv->done.size());
-  for (int i = 0; i < k; ++i) out[i] = sv->done[i];
-  sv->done.erase(sv->done.begin(), sv->done.begin() + k);
-  *n = k;
+  static_assert(sizeof(fhe_done) == sizeof(SrvDone), "fhe_done and SrvDone share a layout");
+  *n = sv->core->poll(reinterpret_cast<SrvDone*>(out), max);
   return FHE_OK;
 }
 
 int fhe_server_drain(fhe_server* sv) {
   if (!sv) return FHE_E_INVAL;
-  std::unique_lock<std::mutex> lk(sv->m);
-  sv->cv.wait(lk, [&] { return sv->finished == sv->submitted; });
+  sv->core->drain();
+  return FHE_OK;
+}
+
+int fhe_server_cancel(fhe_server* sv) {
+  if (!sv) return FHE_E_INVAL;
+  sv->core->cancel();
   return FHE_OK;
 }
 
 void fhe_server_destroy(fhe_server* sv) {
   if (!sv) return;
-  {
-    std::lock_guard<std::mutex> lk(sv->m);
-    sv->stop = true;
-    sv->cv.notify_all();
-  }
-  if (sv->th.joinable()) sv->th.join();
-  hipSetDevice(sv->ctx->device);
-  for (SrvSlot& sl : sv->slots) {
+  if (sv->core) sv->core->stop();  // once every submitted request has completed
+  delete sv->core;
+  SrvExec& ex = sv->ex;
+  hipSetDevice(ex.ctx->device);
+  for (SrvExec::Slot& sl : ex.slots) {
     if (sl.st) hipStreamSynchronize(sl.st);
-    for (void* p : {(void*)sl.ws, (void*)sl.dptr})
-      if (p) hipFree(p);
+    if (sl.dptr) hipFree(sl.dptr);
     if (sl.hptr) hipHostFree(sl.hptr);
     if (sl.done) hipEventDestroy(sl.done);
     if (sl.st) hipStreamDestroy(sl.st);
   }
+  if (ex.arena) hipFree(ex.arena);
+  for (hipEvent_t e : ex.events) hipEventDestroy(e);
   delete sv;
+}
+
+// ---------------------------------------------------------------- Galois keys and automorphisms
+
+int fhe_galois_key_create(fhe_ctx* c, int scheme, uint32_t t, int logN, int logQ_key, int logP, uint32_t g,
+                          const uint32_t* b_host, const uint32_t* a_host, fhe_evk** out) {
+  if (!out) return FHE_E_INVAL;
+  *out = nullptr;
+  if (check_logN(logN) == FHE_OK && ((g & 1u) == 0 || g >= (2u << logN))) return FHE_E_INVAL;
+  fhe_evk* k = nullptr;
+  const int rc = fhe_evk_create(c, scheme, t, logN, logQ_key, logP, b_host, a_host, &k);
+  if (rc != FHE_OK) return rc;
+  k->g = g;
+  *out = k;
+  return FHE_OK;
+}
+
+int fhe_automorphism(fhe_ctx* c, int logN, int logq, uint32_t g, const uint32_t* in, uint32_t* out, int count,
+                     void* stream) {
+  if (!c || !in || !out || count < 0 || logq < 1) return FHE_E_INVAL;
+  if (check_logN(logN) != FHE_OK || logq > c->logQ_max + c->logP_max) return FHE_E_RANGE;
+  if ((g & 1u) == 0 || g >= (2u << logN)) return FHE_E_INVAL;
+  const int L = (logq + 31) / 32;
+  const size_t n = (size_t)count * L << logN;
+  if (count > 0 && in < out + n && out < in + n) return FHE_E_INVAL;
+  if (count == 0) return FHE_OK;
+  std::lock_guard<std::recursive_mutex> lg(c->mu);
+  if (c->sticky != FHE_OK) return c->sticky;
+  hipSetDevice(c->device);
+  RecGuard rg(c);
+  // count polynomials as (count + 1) / 2 "ciphertexts" of two components; an odd
+  // count's last one runs alone
+  const long long LN = (long long)L << logN;
+  PermArgs pa{};
+  pa.in0 = in;
+  pa.in1 = in + LN;
+  pa.out0 = out;
+  pa.out1 = out + LN;
+  pa.istride = 2 * LN;
+  pa.ostride = 2 * LN;
+  pa.logN = logN;
+  pa.L = L;
+  pa.topmask = top_mask(logq);
+  pa.mul = (uint32_t)invmod(g, 2ull << logN);
+  hipError_t e = launch_signed_perm(pa, count / 2, (hipStream_t)stream);
+  if (e == hipSuccess && (count & 1)) {
+    PermArgs p1 = pa;
+    p1.in0 = p1.in1 = in + (long long)(count - 1) * LN;
+    p1.out0 = p1.out1 = out + (long long)(count - 1) * LN;
+    e = launch_signed_perm(p1, 1, (hipStream_t)stream);  // writes the same values twice
+  }
+  return set_sticky(c, e);
+}
+
+int fhe_key_switch(fhe_ctx* c, fhe_evk* k, int logN, int logq, const uint32_t* in0, const uint32_t* in1,
+                   uint32_t* out0, uint32_t* out1, int cnum, void* stream) {
+  if (!c || !k || !in0 || !in1 || !out0 || !out1 || cnum < 0 || logq < 1) return FHE_E_INVAL;
+  if (k->ctx != c || k->g == 0) return FHE_E_STATE;
+  if (logN != k->logN) return FHE_E_SHAPE;
+  if (logq > k->logQ) return FHE_E_RANGE;
+  if (cnum == 0) return FHE_OK;
+  std::lock_guard<std::recursive_mutex> lg(c->mu);
+  if (c->sticky != FHE_OK) return c->sticky;
+  hipSetDevice(c->device);
+  RecGuard rg(c);
+  return key_switch_locked(c, k, logN, logq, in0, in1, out0, out1, cnum, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------- ciphertexts with metadata
+
+int fhe_ct_mul_relin_rescale(fhe_ctx* c, fhe_evk* k, const fhe_ct* x, const fhe_ct* y, int bits, fhe_ct* out,
+                             void* stream) {
+  int rc = ct_check(c, x, out);
+  if (rc != FHE_OK) return rc;
+  if (!k || !ct_valid(c, y) || bits < 0 || bits >= x->logq) return FHE_E_INVAL;
+  if (k->ctx != c || k->g != 0) return FHE_E_STATE;
+  if (!ct_same(x, y, false) || x->cnum != y->cnum || x->logN != k->logN || x->scheme != k->scheme ||
+      (x->scheme == FHE_BGV && x->t != k->t))
+    return FHE_E_SHAPE;
+  if (x->logq > k->logQ) return FHE_E_RANGE;
+  const int L = (x->logq + 31) / 32, Lo = (x->logq - bits + 31) / 32;
+  if (ct_overlap(out, Lo, x, L) || ct_overlap(out, Lo, y, L)) return FHE_E_INVAL;
+  if (x->cnum > 0) {
+    rc = bits > 0 ? fhe_mul_relin_rescale(c, k, x->logN, x->logq, bits, x->c0, x->c1, y->c0, y->c1, out->c0,
+                                          out->c1, x->cnum, stream)
+                  : fhe_mul_relin(c, k, x->logN, x->logq, x->c0, x->c1, y->c0, y->c1, out->c0, out->c1, x->cnum,
+                                  stream);
+    if (rc != FHE_OK) return rc;
+  }
+  // mult: logp adds, gamma multiplies; rescale: logq and (CKKS) logp drop by bits,
+  // (BGV) gamma picks up 2^-bits mod t
+  uint32_t gamma = 1;
+  if (x->scheme == FHE_BGV) {
+    gamma = (uint32_t)((uint64_t)x->gamma * y->gamma % x->t);
+    if (bits > 0) gamma = (uint32_t)((uint64_t)gamma * invmod(powmod(2, bits, x->t), x->t) % x->t);
+  }
+  const int logp = x->logp + y->logp - (x->scheme == FHE_CKKS ? bits : 0);
+  ct_meta(out, x, x->logq - bits, logp, gamma);
+  return FHE_OK;
+}
+
+int fhe_ct_mul_relin(fhe_ctx* c, fhe_evk* k, const fhe_ct* x, const fhe_ct* y, fhe_ct* out, void* stream) {
+  return fhe_ct_mul_relin_rescale(c, k, x, y, 0, out, stream);
+}
+
+int fhe_ct_rescale(fhe_ctx* c, const fhe_ct* x, int bits, fhe_ct* out, void* stream) {
+  int rc = ct_check(c, x, out);
+  if (rc != FHE_OK) return rc;
+  if (bits < 1 || bits >= x->logq) return FHE_E_INVAL;
+  if (x->cnum > 0) {
+    rc = fhe_rescale(c, x->scheme, x->t, x->logN, x->logq, bits, x->c0, x->c1, out->c0, out->c1, x->cnum, stream);
+    if (rc != FHE_OK) return rc;
+  }
+  uint32_t gamma = 1;
+  if (x->scheme == FHE_BGV) gamma = (uint32_t)((uint64_t)x->gamma * invmod(powmod(2, bits, x->t), x->t) % x->t);
+  ct_meta(out, x, x->logq - bits, x->scheme == FHE_CKKS ? x->logp - bits : x->logp, gamma);
+  return FHE_OK;
+}
+
+// Coefficient-wise sum with signs (add, sub, negate, addconst, moddown) on the context.
+static int ct_limb_sum(fhe_ctx* c, const fhe_ct* x, const uint32_t* y0, const uint32_t* y1, long long ystride,
+                       int negx, int negy, int logq_out, fhe_ct* out, void* stream) {
+  if (x->cnum == 0) return FHE_OK;
+  std::lock_guard<std::recursive_mutex> lg(c->mu);
+  if (c->sticky != FHE_OK) return c->sticky;
+  hipSetDevice(c->device);
+  RecGuard rg(c);
+  const int L = (x->logq + 31) / 32, Lo = (logq_out + 31) / 32;
+  LimbSumArgs a{};
+  a.x0 = x->c0;
+  a.x1 = x->c1;
+  a.y0 = y0;
+  a.y1 = y1;
+  a.out0 = out->c0;
+  a.out1 = out->c1;
+  a.xstride = (long long)L << x->logN;
+  a.ystride = ystride;
+  a.ostride = (long long)Lo << x->logN;
+  a.N = 1 << x->logN;
+  a.L = Lo;
+  a.topmask = top_mask(logq_out);
+  a.negx = negx;
+  a.negy = negy;
+  return set_sticky(c, launch_limb_sum(a, x->cnum, (hipStream_t)stream));
+}
+
+// In place is allowed when the output is the input itself; partial overlaps are not.
+static bool ct_alias_ok(const fhe_ct* out, int Lo, const fhe_ct* x, int L) {
+  if (out->c0 == x->c0 && out->c1 == x->c1 && Lo == L) return true;
+  return !ct_overlap(out, Lo, x, L);
+}
+
+static int ct_add_sub(fhe_ctx* c, const fhe_ct* x, const fhe_ct* y, fhe_ct* out, int sub, void* stream) {
+  int rc = ct_check(c, x, out);
+  if (rc != FHE_OK) return rc;
+  if (!ct_valid(c, y)) return FHE_E_INVAL;
+  if (!ct_same(x, y, true) || !(y->cnum == x->cnum || y->cnum == 1)) return FHE_E_SHAPE;
+  const int L = (x->logq + 31) / 32;
+  if (!ct_alias_ok(out, L, x, L) || !ct_alias_ok(out, L, y, L)) return FHE_E_INVAL;
+  const long long ystride = y->cnum == x->cnum ? (long long)L << x->logN : 0;  // 1: broadcast
+  rc = ct_limb_sum(c, x, y->c0, y->c1, ystride, 0, sub, x->logq, out, stream);
+  if (rc == FHE_OK) ct_meta(out, x, x->logq, x->logp, x->gamma);
+  return rc;
+}
+
+int fhe_ct_add(fhe_ctx* c, const fhe_ct* x, const fhe_ct* y, fhe_ct* out, void* stream) {
+  return ct_add_sub(c, x, y, out, 0, stream);
+}
+
+int fhe_ct_sub(fhe_ctx* c, const fhe_ct* x, const fhe_ct* y, fhe_ct* out, void* stream) {
+  return ct_add_sub(c, x, y, out, 1, stream);
+}
+
+int fhe_ct_negate(fhe_ctx* c, const fhe_ct* x, fhe_ct* out, void* stream) {
+  int rc = ct_check(c, x, out);
+  if (rc != FHE_OK) return rc;
+  const int L = (x->logq + 31) / 32;
+  if (!ct_alias_ok(out, L, x, L)) return FHE_E_INVAL;
+  rc = ct_limb_sum(c, x, nullptr, nullptr, 0, 1, 0, x->logq, out, stream);
+  if (rc == FHE_OK) ct_meta(out, x, x->logq, x->logp, x->gamma);
+  return rc;
+}
+
+int fhe_ct_moddown(fhe_ctx* c, const fhe_ct* x, int bits, fhe_ct* out, void* stream) {
+  int rc = ct_check(c, x, out);
+  if (rc != FHE_OK) return rc;
+  if (bits < 0 || bits >= x->logq) return FHE_E_INVAL;
+  const int L = (x->logq + 31) / 32, Lo = (x->logq - bits + 31) / 32;
+  if (!(out->c0 == x->c0 && out->c1 == x->c1 && (x->cnum <= 1 || Lo == L)) && ct_overlap(out, Lo, x, L))
+    return FHE_E_INVAL;
+  rc = ct_limb_sum(c, x, nullptr, nullptr, 0, 0, 0, x->logq - bits, out, stream);
+  if (rc == FHE_OK) ct_meta(out, x, x->logq - bits, x->logp, x->gamma);
+  return rc;
+}
+
+int fhe_ct_addconst(fhe_ctx* c, const fhe_ct* x, const uint32_t* m, int mcount, fhe_ct* out, void* stream) {
+  int rc = ct_check(c, x, out);
+  if (rc != FHE_OK) return rc;
+  if (!m || !(mcount == 1 || mcount == x->cnum)) return FHE_E_INVAL;
+  const int L = (x->logq + 31) / 32;
+  if (!ct_alias_ok(out, L, x, L)) return FHE_E_INVAL;
+  const long long ystride = mcount > 1 ? (long long)L << x->logN : 0;
+  rc = ct_limb_sum(c, x, m, nullptr, ystride, 0, 0, x->logq, out, stream);
+  if (rc == FHE_OK) ct_meta(out, x, x->logq, x->logp, x->gamma);
+  return rc;
+}
+
+int fhe_ct_imult(fhe_ctx* c, const fhe_ct* x, fhe_ct* out, void* stream) {
+  int rc = ct_check(c, x, out);
+  if (rc != FHE_OK) return rc;
+  if (x->scheme != FHE_CKKS) return FHE_E_INVAL;
+  const int L = (x->logq + 31) / 32;
+  if (ct_overlap(out, L, x, L)) return FHE_E_INVAL;
+  if (x->cnum > 0) {
+    std::lock_guard<std::recursive_mutex> lg(c->mu);
+    if (c->sticky != FHE_OK) return c->sticky;
+    hipSetDevice(c->device);
+    RecGuard rg(c);
+    // X^(N/2): output position k takes input k - N/2 (mod 2N, negated below zero)
+    PermArgs pa{};
+    pa.in0 = x->c0;
+    pa.in1 = x->c1;
+    pa.out0 = out->c0;
+    pa.out1 = out->c1;
+    pa.istride = pa.ostride = (long long)L << x->logN;
+    pa.logN = x->logN;
+    pa.L = L;
+    pa.topmask = top_mask(x->logq);
+    pa.mul = 1;
+    pa.add = (2u << x->logN) - (1u << (x->logN - 1));
+    rc = set_sticky(c, launch_signed_perm(pa, x->cnum, (hipStream_t)stream));
+    if (rc != FHE_OK) return rc;
+  }
+  ct_meta(out, x, x->logq, x->logp, x->gamma);
+  return FHE_OK;
+}
+
+int fhe_ct_multconst(fhe_ctx* c, const fhe_ct* x, const uint32_t* k_host, int klimbs, int negative, int logp_k,
+                     fhe_ct* out, void* stream) {
+  int rc = ct_check(c, x, out);
+  if (rc != FHE_OK) return rc;
+  if (!k_host || klimbs < 1 || klimbs > kConstMaxLimbs || logp_k < 0) return FHE_E_INVAL;
+  const int L = (x->logq + 31) / 32;
+  if (!ct_alias_ok(out, L, x, L)) return FHE_E_INVAL;
+  if (x->cnum > 0) {
+    std::lock_guard<std::recursive_mutex> lg(c->mu);
+    if (c->sticky != FHE_OK) return c->sticky;
+    hipSetDevice(c->device);
+    RecGuard rg(c);
+    ConstMulArgs a{};
+    a.in0 = x->c0;
+    a.in1 = x->c1;
+    a.out0 = out->c0;
+    a.out1 = out->c1;
+    a.istride = a.ostride = (long long)L << x->logN;
+    a.N = 1 << x->logN;
+    a.L = L;
+    a.topmask = top_mask(x->logq);
+    for (int i = 0; i < klimbs; ++i) a.k[i] = k_host[i];
+    a.klimbs = klimbs;
+    a.neg = negative ? 1 : 0;
+    rc = set_sticky(c, launch_const_mul(a, x->cnum, (hipStream_t)stream));
+    if (rc != FHE_OK) return rc;
+  }
+  ct_meta(out, x, x->logq, x->scheme == FHE_CKKS ? x->logp + logp_k : x->logp, x->gamma);
+  return FHE_OK;
+}
+
+int fhe_ct_multconstvec(fhe_ctx* c, const fhe_ct* x, const uint32_t* m, int mcount, int logp_m, fhe_ct* out,
+                        void* stream) {
+  int rc = ct_check(c, x, out);
+  if (rc != FHE_OK) return rc;
+  if (!m || !(mcount == 1 || mcount == x->cnum) || logp_m < 0) return FHE_E_INVAL;
+  const int L = (x->logq + 31) / 32;
+  if (!ct_alias_ok(out, L, x, L)) return FHE_E_INVAL;
+  if (x->cnum > 0) {
+    std::lock_guard<std::recursive_mutex> lg(c->mu);
+    if (c->sticky != FHE_OK) return c->sticky;
+    hipSetDevice(c->device);
+    RecGuard rg(c);
+    rc = plain_mul_locked(c, x->logN, x->logq, x->c0, x->c1, m, mcount, out->c0, out->c1, x->cnum,
+                          (hipStream_t)stream);
+    if (rc != FHE_OK) return rc;
+  }
+  ct_meta(out, x, x->logq, x->scheme == FHE_CKKS ? x->logp + logp_m : x->logp, x->gamma);
+  return FHE_OK;
+}
+
+int fhe_ct_key_switch(fhe_ctx* c, fhe_evk* k, const fhe_ct* x, fhe_ct* out, void* stream) {
+  int rc = ct_check(c, x, out);
+  if (rc != FHE_OK) return rc;
+  if (!k) return FHE_E_INVAL;
+  if (k->ctx != c || k->g == 0) return FHE_E_STATE;
+  if (x->logN != k->logN || x->scheme != k->scheme || (x->scheme == FHE_BGV && x->t != k->t)) return FHE_E_SHAPE;
+  if (x->logq > k->logQ) return FHE_E_RANGE;
+  const int L = (x->logq + 31) / 32;
+  if (ct_overlap(out, L, x, L)) return FHE_E_INVAL;
+  if (x->cnum > 0) {
+    rc = fhe_key_switch(c, k, x->logN, x->logq, x->c0, x->c1, out->c0, out->c1, x->cnum, stream);
+    if (rc != FHE_OK) return rc;
+  }
+  ct_meta(out, x, x->logq, x->logp, x->gamma);
+  return FHE_OK;
+}
+
+int fhe_ct_leftrotate(fhe_ctx* c, fhe_evk* k, int r, const fhe_ct* x, fhe_ct* out, void* stream) {
+  if (!k || !x || r < 0) return FHE_E_INVAL;
+  if (check_logN(x->logN) != FHE_OK) return FHE_E_RANGE;
+  if (k->g != (uint32_t)powmod(5, (uint64_t)r, 2ull << x->logN)) return FHE_E_STATE;
+  return fhe_ct_key_switch(c, k, x, out, stream);
+}
+
+int fhe_ct_conjugate(fhe_ctx* c, fhe_evk* k, const fhe_ct* x, fhe_ct* out, void* stream) {
+  if (!k || !x) return FHE_E_INVAL;
+  if (check_logN(x->logN) != FHE_OK) return FHE_E_RANGE;
+  if (k->g != (2u << x->logN) - 1u) return FHE_E_STATE;
+  return fhe_ct_key_switch(c, k, x, out, stream);
 }
 
 }  // extern "C"

@@ -39,8 +39,10 @@ struct NttArgs {
 enum { ROWS_TENSOR = 0, ROWS_RELIN = 1, ROWS_RING = 2 };
 struct RowsArgs {
   uint32_t* data = nullptr;        // group c at data + c group_stride: tensor [4][K][N]; relin [K][N]; ring a [K][N]
-  const uint32_t* data2 = nullptr; // ring: b, group c at data2 + c group_stride
+  const uint32_t* data2 = nullptr; // ring: b, group c at data2 + (c % data2_groups) data2_stride
   long long group_stride = 0;
+  long long data2_stride = 0;      // ring: 0 gives every group the same b (broadcast)
+  int data2_groups = 1;            // ring: groups of b (c and c + data2_groups share one)
   const uint32_t* key = nullptr;   // relin: the key's [2][K][N] in NTT form
   uint32_t* out = nullptr;         // relin: group c at out + c out_stride, [2][K][N]
   long long out_stride = 0;
@@ -107,6 +109,7 @@ struct ComposeArgs {
   const uint32_t* pw = nullptr; // BGV: pw[l] = 2^(32 l) mod t
   int bits = 0;              // compose + rescale: rescale bits (outputs hold logq - bits bits)
   uint32_t invB = 0;         // BGV: 2^-bits mod t
+  int d1_zero = 0;           // key switch: d_1 is zero (slot 1 is not read)
 };
 
 struct RescaleArgs {
@@ -122,6 +125,50 @@ struct RescaleArgs {
   const uint32_t* pw = nullptr;
 };
 
+// Coefficient-wise sums: polynomial z = 2 c + i (ciphertext c, component i) of
+// x at (i ? x1 : x0) + c xstride, likewise y (null component: zero) and out.
+// out = [(-1)^negx x + (-1)^negy y]_(2^logq), L limbs, the top one masked.
+struct LimbSumArgs {
+  const uint32_t* x0 = nullptr;
+  const uint32_t* x1 = nullptr;
+  const uint32_t* y0 = nullptr;
+  const uint32_t* y1 = nullptr;
+  uint32_t* out0 = nullptr;
+  uint32_t* out1 = nullptr;
+  long long xstride = 0, ystride = 0, ostride = 0;  // ystride 0: one y for every ciphertext
+  int N = 0, L = 0;
+  uint32_t topmask = 0xFFFFFFFFu;
+  int negx = 0, negy = 0;
+};
+
+// Signed permutation: out[k] = +-in[i mod N] with i = (k mul + add) mod 2N, negated
+// when i >= N (automorphism: mul = g^-1 mod 2N, add = 0; monomial X^s: mul = 1,
+// add = 2N - s).  Components and strides as in LimbSumArgs.
+struct PermArgs {
+  const uint32_t* in0 = nullptr;
+  const uint32_t* in1 = nullptr;
+  uint32_t* out0 = nullptr;
+  uint32_t* out1 = nullptr;
+  long long istride = 0, ostride = 0;
+  int logN = 0, L = 0;
+  uint32_t topmask = 0xFFFFFFFFu;
+  uint32_t mul = 1, add = 0;
+};
+
+// out = [(-1)^neg in k]_(2^logq) for an integer constant k of klimbs limbs.
+constexpr int kConstMaxLimbs = 8;
+struct ConstMulArgs {
+  const uint32_t* in0 = nullptr;
+  const uint32_t* in1 = nullptr;
+  uint32_t* out0 = nullptr;
+  uint32_t* out1 = nullptr;
+  long long istride = 0, ostride = 0;
+  int N = 0, L = 0;
+  uint32_t topmask = 0xFFFFFFFFu;
+  uint32_t k[kConstMaxLimbs] = {};
+  int klimbs = 0, neg = 0;
+};
+
 // Optional per-kernel timing: when a recorder is installed, every launcher records
 // a HIP event pair around its kernel on the launch stream.
 enum KernelId {
@@ -131,11 +178,12 @@ enum KernelId {
   KID_NTT_INV_ROWS,
   KID_NTT_INV_COLS,
   KID_POINTWISE,
-  KID_GARNER,
+  KID_CRT,
   KID_COMPOSE,
   KID_RESCALE,
   KID_ROWS_FUSED,
   KID_COMPOSE_RESCALE,
+  KID_COEFFWISE,  // coefficient-wise ops, signed permutations, constant products
   KID_COUNT
 };
 
@@ -147,6 +195,18 @@ struct EventRecorder {
 
 void set_recorder(EventRecorder* r);  // host thread-local
 long long kernel_launch_count();      // kernels launched by this host thread so far
+void bracket_begin(int kid, hipStream_t s);
+void bracket_end(int kid, hipStream_t s, double work);
+
+// Brackets one kernel launch with the recorder's events; `work` is the kernel's
+// algorithmic HBM bytes (what it must read and write at least once).
+struct Bracket {
+  int kid;
+  hipStream_t s;
+  double work;
+  Bracket(int k, hipStream_t st, double w) : kid(k), s(st), work(w) { bracket_begin(kid, s); }
+  ~Bracket() { bracket_end(kid, s, work); }
+};
 
 // Launch parameters chosen by the autotuner (defaults: 16 primes per lift thread,
 // NTT column pass of ceil(logN / 2) stages).
@@ -180,5 +240,8 @@ hipError_t launch_add_small(const uint32_t* x, const uint32_t* y, const int32_t*
 hipError_t launch_bgv_decode(const uint32_t* ph, uint32_t* m, int N, int L, int logq, uint32_t t, uint32_t qmodt,
                              uint32_t ginv, hipStream_t s);
 hipError_t launch_bitrev(uint32_t* data, int logN, long long rows, hipStream_t s);
+hipError_t launch_limb_sum(const LimbSumArgs& a, int cnum, hipStream_t s);
+hipError_t launch_signed_perm(const PermArgs& a, int cnum, hipStream_t s);
+hipError_t launch_const_mul(const ConstMulArgs& a, int cnum, hipStream_t s);
 
 }  // namespace fhe

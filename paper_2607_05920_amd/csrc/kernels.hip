@@ -101,20 +101,13 @@ static thread_local long long g_launches = 0;
 void set_recorder(EventRecorder* r) { g_rec = r; }
 long long kernel_launch_count() { return g_launches; }
 
-// Brackets one kernel launch with the recorder's events; `work` is the kernel's
-// algorithmic HBM bytes (what it must read and write at least once).
-struct Bracket {
-  int kid;
-  hipStream_t s;
-  double work;
-  Bracket(int k, hipStream_t st, double w) : kid(k), s(st), work(w) {
-    ++g_launches;
-    if (g_rec) g_rec->begin(kid, s);
-  }
-  ~Bracket() {
-    if (g_rec) g_rec->end(kid, s, work);
-  }
-};
+void bracket_begin(int kid, hipStream_t s) {
+  ++g_launches;
+  if (g_rec) g_rec->begin(kid, s);
+}
+void bracket_end(int kid, hipStream_t s, double work) {
+  if (g_rec) g_rec->end(kid, s, work);
+}
 
 // ============================================================================ NTT
 //
@@ -557,7 +550,8 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 
   } else {  // ring: a times b, in place of a
     const uint32_t bytes = (uint32_t)(NSUB * n * 4);
     const __amdgpu_buffer_rsrc_t ra = row_buffer(wave_uniform(a.data + (long long)c * a.group_stride + base), bytes);
-    const __amdgpu_buffer_rsrc_t rb = row_buffer(wave_uniform(a.data2 + (long long)c * a.group_stride + base), bytes);
+    const __amdgpu_buffer_rsrc_t rb =
+        row_buffer(wave_uniform(a.data2 + (long long)(c % a.data2_groups) * a.data2_stride + base), bytes);
     uint32_t x[2][16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
@@ -588,10 +582,12 @@ static hipError_t rows_fused(const RowsArgs& a, hipStream_t st) {
   // below the out-of-range lane offset 0x7FFFFF00 (bytes)
   if ((3LL * a.K * (1LL << a.logN) + (long long)NSUB * n) * 4 >= 0x70000000LL) return hipErrorInvalidValue;
   dim3 grid(8 * kx * a.cnum * nwg);
-  // algorithmic HBM bytes per (ciphertext, prime): tensor 4 rows in, 3 out; relin
-  // 1 + 2 key rows in, 2 out; ring 2 in, 1 out
-  const double rows = MODE == 0 ? 7.0 : (MODE == 1 ? 5.0 : 3.0);
-  Bracket br(KID_ROWS_FUSED, st, 4.0 * rows * a.cnum * a.K * (double)(1 << a.logN));
+  // algorithmic HBM bytes per prime: tensor 4 rows in and 3 out per ciphertext; relin
+  // 1 row in and 2 out per ciphertext plus the key's 2 rows once; ring 2 in (b once per
+  // distinct operand) and 1 out per group
+  const int b_rows = a.data2_stride ? std::min(a.data2_groups, a.cnum) : 1;
+  const double rows = MODE == 0 ? 7.0 * a.cnum : (MODE == 1 ? 3.0 * a.cnum + 2.0 : 2.0 * a.cnum + b_rows);
+  Bracket br(KID_ROWS_FUSED, st, 4.0 * rows * a.K * (double)(1 << a.logN));
   hipLaunchKernelGGL((rows_fused_kernel<S, MODE>), grid, dim3(128), 0, st, a);
   return hipGetLastError();
 }
@@ -1197,7 +1193,7 @@ hipError_t launch_crt(CrtArgs a, int npoly, hipStream_t st) {
   if (npoly == 0) return hipSuccess;
   const int nkb = (a.K + 31) / 32;
   // algorithmic HBM bytes: K residues read and Lout limbs written per coefficient
-  Bracket br(KID_GARNER, st, 4.0 * npoly * a.N * (double)(a.K + a.Lout));
+  Bracket br(KID_CRT, st, 4.0 * npoly * a.N * (double)(a.K + a.Lout));
   switch (nkb) {
     case 1: crt_launch<1>(a, st); break;
     case 2: crt_launch<2>(a, st); break;
@@ -1246,6 +1242,7 @@ __global__ __launch_bounds__(256) void compose_kernel(ComposeArgs a) {
   const int c = z >> 1, i = z & 1;
   const uint32_t* k = a.k + (long long)z * a.kstride + jc;
   const uint32_t* d = a.d + (long long)(3 * c + i) * a.dstride + jc;
+  const bool dread = !(a.d1_zero && i);  // block-uniform
   uint32_t* o = (a.out0s ? (i ? a.out1s[c] : a.out0s[c]) : (i ? a.out1 : a.out0) + (long long)c * a.ostride) + jc;
   const int64_t corr = round_correction(k, a.N, a.LK, a.logP, a.scheme, a.t, a.invP, a.pw);
   const int sl = a.logP >> 5, rs = a.logP & 31;
@@ -1258,7 +1255,7 @@ __global__ __launch_bounds__(256) void compose_kernel(ComposeArgs a) {
     const uint32_t ks = rs ? ((klo >> rs) | (khi << (32 - rs))) : klo;
     klo = khi;
     const uint32_t cl = l == 0 ? (uint32_t)corr : ext;
-    const uint64_t sum = (uint64_t)d[(long long)l * a.N] + ks + cl + carry;
+    const uint64_t sum = (uint64_t)(dread ? d[(long long)l * a.N] : 0u) + ks + cl + carry;
     uint32_t wv = (uint32_t)sum;
     carry = sum >> 32;
     if (l == a.L - 1 && topbits < 32) wv &= (1u << topbits) - 1u;
@@ -1278,6 +1275,7 @@ __global__ __launch_bounds__(256) void compose_rescale_kernel(ComposeArgs a) {
   const int c = z >> 1, i = z & 1;
   const uint32_t* k = a.k + (long long)z * a.kstride + jc;
   const uint32_t* d = a.d + (long long)(3 * c + i) * a.dstride + jc;
+  const bool dread = !(a.d1_zero && i);  // block-uniform
   uint32_t* o = (a.out0s ? (i ? a.out1s[c] : a.out0s[c]) : (i ? a.out1 : a.out0) + (long long)c * a.ostride) + jc;
   // compose state
   const int64_t corrP = round_correction(k, a.N, a.LK, a.logP, a.scheme, a.t, a.invP, a.pw);
@@ -1307,7 +1305,7 @@ __global__ __launch_bounds__(256) void compose_rescale_kernel(ComposeArgs a) {
     const uint32_t ks = rs ? ((klo >> rs) | (khi << (32 - rs))) : klo;
     klo = khi;
     const uint32_t cp = l == 0 ? (uint32_t)corrP : extP;
-    const uint64_t sum = (uint64_t)d[(long long)l * a.N] + ks + cp + carryP;
+    const uint64_t sum = (uint64_t)(dread ? d[(long long)l * a.N] : 0u) + ks + cp + carryP;
     uint32_t cv = (uint32_t)sum;
     carryP = sum >> 32;
     if (l == a.L - 1 && topbits < 32) cv &= (1u << topbits) - 1u;

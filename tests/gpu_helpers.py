@@ -63,3 +63,14 @@ def check(got, want, what: str = "values"):
     bad = [i for i, (a, b) in enumerate(zip(got, want)) if a != b]
     first = ", ".join(f"[{i}] {str(got[i])[:24]} != {str(want[i])[:24]}" for i in bad[:4])
     raise AssertionError(f"{what}: {len(bad)} of {len(want)} differ; first: {first}")
+
+
+def oracle_pool(workers: int = 12):
+    """A process pool for the oracle's independent ring products (its ``map`` is the
+    ``mapper`` argument of oracle.scheme).  Workers are fresh interpreters (spawn):
+    they run only the pure-Python oracle and never touch the GPU."""
+    import multiprocessing
+    import os
+    from concurrent.futures import ProcessPoolExecutor
+    n = max(1, min(workers, os.cpu_count() or 1))
+    return ProcessPoolExecutor(max_workers=n, mp_context=multiprocessing.get_context("spawn"))
