@@ -161,6 +161,21 @@ int fhe_ntt(fhe_ctx* ctx, int logN, int prime0, int nprimes, int flags, uint32_t
 int fhe_ring_mul(fhe_ctx* ctx, int logN, int logq, const uint32_t* a, const uint32_t* b,
                  uint32_t* c, int cnum, void* stream);
 
+/* fhe_ring_mul without any allocation, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid it): the same
+ * product and bits, with the residues of the operands (2 cnum K N words, K the primes of
+ * the product, fhe_primes_needed(logN, logq, logq, 1)) held in a static device array of
+ * 64 MiB (16 Mi words) that each device the library runs on keeps until the process
+ * ends.  Calls no allocating routine: the context's tables for this (logN, logq) must
+ * exist already, i.e. one fhe_ring_mul of the same shape has run on the context.
+ * Every call on a device shares that device's array, so calls that overlap on one
+ * device (concurrent streams, contexts or threads) race and must be serialized by the
+ * caller.  Errors: FHE_E_INVAL, FHE_E_RANGE (shape beyond the context, or 2 cnum K N
+ * above 16 Mi words), FHE_E_STATE (tables not built yet, or profiling enabled),
+ * FHE_E_DEVICE. */
+int fhe_ring_mul_noalloc(fhe_ctx* ctx, int logN, int logq, const uint32_t* a, const uint32_t* b, uint32_t* c,
+                         int cnum, void* stream);
+
 /* Upload a relinearization key (b', a') (Section 6.2 "Cryptographic Key
  * Management": relinearization keys) given at modulus P * 2^logQ_key:
  * b_host, a_host are host uint32[L_PQ][N], L_PQ = ceil((logP + logQ_key) / 32).

@@ -43,6 +43,7 @@ EXPORTS = {
     "fhe_lift": (_I, [_P, _I, _I, _I, _P, _P, _I, _P]),
     "fhe_ntt": (_I, [_P, _I, _I, _I, _I, _P, _I, _P]),
     "fhe_ring_mul": (_I, [_P, _I, _I, _P, _P, _P, _I, _P]),
+    "fhe_ring_mul_noalloc": (_I, [_P, _I, _I, _P, _P, _P, _I, _P]),
     "fhe_evk_create": (_I, [_P, _I, _U, _I, _I, _I, _P, _P, ctypes.POINTER(_P)]),
     "fhe_evk_prepare": (_I, [_P, _I, _P]),
     "fhe_evk_destroy": (None, [_P]),
@@ -280,6 +281,14 @@ class Context:
             _need(t, w, n)
         _check("fhe_ring_mul", load_library().fhe_ring_mul(self._h, logN, logq, _ptr(a), _ptr(b), _ptr(out), cnum,
                                                            _stream(stream)))
+
+    def ring_mul_noalloc(self, logN: int, logq: int, a, b, out, cnum: int = 1, stream=None):
+        """fhe_ring_mul_noalloc: the same product with the library's static scratch."""
+        w = cnum * nlimbs(logq) << logN
+        for t, n in ((a, "a"), (b, "b"), (out, "out")):
+            _need(t, w, n)
+        _check("fhe_ring_mul_noalloc", load_library().fhe_ring_mul_noalloc(
+            self._h, logN, logq, _ptr(a), _ptr(b), _ptr(out), cnum, _stream(stream)))
 
     def rescale(self, scheme: int, t: int, logN: int, logq: int, bits: int, in0, in1, out0, out1,
                 cnum: int = 1, stream=None):

@@ -24,6 +24,12 @@
 
 using namespace fhe;
 
+// Device scratch of fhe_ring_mul_noalloc: the residues of both operands of every pair
+// (2 cnum K N words).  Each device the library runs on holds its own copy until the
+// process ends; host code uses only the address hipGetSymbolAddress gives per device.
+constexpr size_t kNoAllocWords = (size_t)16 << 20;  // 64 MiB
+__device__ __align__(256) uint32_t scratch[kNoAllocWords];
+
 namespace {
 
 // Text of the last failing HIP call on this host thread (see fhe_error_detail).
@@ -32,6 +38,11 @@ thread_local char g_detail[256] = "";
 void note(const char* what, hipError_t e) {
   snprintf(g_detail, sizeof g_detail, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
 }
+
+// Device address of `scratch` per device, set by fhe_ctx_create with the device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t* g_scratch_dev[kMaxDevices] = {};
 
 // ---------------------------------------------------------------- host number theory
 
@@ -262,6 +273,7 @@ struct fhe_ctx {
   std::recursive_mutex mu;
   int sticky = FHE_OK;
   Recorder* rec = nullptr;  // non-null while profiling is on
+  uint32_t* noalloc = nullptr;  // this device's address of `scratch`
   std::map<std::vector<int>, Tuning> tuned;  // autotuner results by (logN, logq, logP, K_t, K_r)
 };
 
@@ -496,7 +508,7 @@ uint32_t* pow_table(fhe_ctx* c, uint32_t t, hipError_t* err) {
 }
 
 // Scratch memory of a (context, stream, slot), grown on demand.
-void* scratch(fhe_ctx* c, void* stream, int slot, size_t bytes, hipError_t* err) {
+void* stream_scratch(fhe_ctx* c, void* stream, int slot, size_t bytes, hipError_t* err) {
   Workspace& w = c->ws[std::make_pair(stream, slot)];
   if (w.bytes < bytes) {
     if (w.ptr) {
@@ -907,7 +919,7 @@ int mul_relin_locked(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, const
   const PipeSize z = pipe_size(c, k, logN, logq, cnum);
   if (z.Kt < 0 || z.Kr < 0) return FHE_E_RANGE;
   hipError_t e = hipSuccess;
-  uint32_t* ws = (uint32_t*)scratch(c, st, 0, (size_t)z.main_words * 4, &e);
+  uint32_t* ws = (uint32_t*)stream_scratch(c, st, 0, (size_t)z.main_words * 4, &e);
   if (!ws) return set_sticky(c, e);
   return pipeline(c, k, logN, logq, bits, io, cnum, st, ws, Tuning());
 }
@@ -1169,7 +1181,7 @@ namespace {
 // c = a b in Z_(2^logq)[X]/(X^N + 1) for cnum pairs (lift, NTT, pointwise, iNTT,
 // CRT reconstruction); the caller holds the context lock and has checked the arguments.
 int ring_mul_locked(fhe_ctx* c, int logN, int logq, const uint32_t* a, const uint32_t* b, uint32_t* out, int cnum,
-                    void* stream) {
+                    void* stream, uint32_t* R = nullptr) {
   hipStream_t st = (hipStream_t)stream;
   const int N = 1 << logN;
   const int L = (logq + 31) / 32;
@@ -1180,7 +1192,7 @@ int ring_mul_locked(fhe_ctx* c, int logN, int logq, const uint32_t* a, const uin
   const uint2* sc = crt_scale(c, logN, K, &e);
   if (!sc) return set_sticky(c, e);
   const long long KN = (long long)K * N;
-  uint32_t* R = (uint32_t*)scratch(c, stream, 0, (size_t)2 * cnum * KN * 4, &e);
+  if (!R) R = (uint32_t*)stream_scratch(c, stream, 0, (size_t)2 * cnum * KN * 4, &e);
   if (!R) return set_sticky(c, e);
   uint32_t* Ra = R;
   uint32_t* Rb = R + (long long)cnum * KN;
@@ -1222,7 +1234,7 @@ int key_switch_locked(fhe_ctx* c, fhe_evk* k, int logN, int logq, const uint32_t
   const long long polyw = (long long)z.L * NN;
   const long long words = (long long)cnum * NN * (3LL * z.L + 3LL * z.Kr + 2LL * z.LK);
   hipError_t e = hipSuccess;
-  uint32_t* ws = (uint32_t*)scratch(c, st, 0, (size_t)words * 4, &e);
+  uint32_t* ws = (uint32_t*)stream_scratch(c, st, 0, (size_t)words * 4, &e);
   if (!ws) return set_sticky(c, e);
   uint32_t* Dl = ws;                                  // [cnum][3][L][N]
   uint32_t* Rr = Dl + (long long)cnum * 3 * polyw;    // [cnum][Kr][N]
@@ -1263,7 +1275,7 @@ int plain_mul_locked(fhe_ctx* c, int logN, int logq, const uint32_t* x0, const u
   const uint2* sc = crt_scale(c, logN, K, &e);
   if (!sc) return set_sticky(c, e);
   const long long KN = (long long)K * N, LN = (long long)L * N;
-  uint32_t* R = (uint32_t*)scratch(c, st, 0, (size_t)(2LL * cnum + mcount) * KN * 4, &e);
+  uint32_t* R = (uint32_t*)stream_scratch(c, st, 0, (size_t)(2LL * cnum + mcount) * KN * 4, &e);
   if (!R) return set_sticky(c, e);
   uint32_t* Rm = R + 2LL * cnum * KN;
   e = launch_lift(lift_args(c, x0, R, LN, KN, N, L, K), cnum, st);
@@ -1368,6 +1380,26 @@ int fhe_ctx_create(int device, int logQ_max, int logP_max, fhe_ctx** out) {
   }
   c->logQ_max = logQ_max;
   c->logP_max = logP_max;
+  if (device < 0 || device >= kMaxDevices) {
+    delete c;
+    return FHE_E_RANGE;
+  }
+  {
+    // once per device, with the device current: the address of this device's copy of
+    // `scratch` (the symbol itself is a host-side stand-in, not a device address)
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+      void* p = nullptr;
+      e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p) {
+        note("hipGetSymbolAddress(scratch)", e);
+        delete c;
+        return FHE_E_DEVICE;
+      }
+      g_scratch_dev[device] = (uint32_t*)p;
+    }
+    c->noalloc = g_scratch_dev[device];
+  }
   // primes q = 1 mod 2^17 below 2^30, largest first, until the largest relinearization
   // product (logN 16, logq = logQ_max, logP = logP_max) is covered with the CRT margin.
   const int e_max = kLogNMax + 2 * logQ_max + logP_max + kCrtMarginBits;
@@ -1600,6 +1632,26 @@ int fhe_ring_mul(fhe_ctx* c, int logN, int logq, const uint32_t* a, const uint32
   return ring_mul_locked(c, logN, logq, a, b, out, cnum, stream);
 }
 
+int fhe_ring_mul_noalloc(fhe_ctx* c, int logN, int logq, const uint32_t* a, const uint32_t* b, uint32_t* out,
+                         int cnum, void* stream) {
+  if (!c || !a || !b || !out || cnum < 0 || logq < 1) return FHE_E_INVAL;
+  if (check_logN(logN) != FHE_OK || logq > c->logQ_max + c->logP_max) return FHE_E_RANGE;
+  if (cnum == 0) return FHE_OK;
+  const int N = 1 << logN, L = (logq + 31) / 32, eb = 2 * logq + logN;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (c->sticky != FHE_OK) return c->sticky;
+  const int K = primes_for_e(c, eb);
+  if (K < 0) return FHE_E_RANGE;
+  if ((size_t)2 * cnum * K * N > kNoAllocWords) return FHE_E_RANGE;  // beyond the fixed scratch
+  // every table the product uses must exist already (built by an fhe_ring_mul of this
+  // shape): lookups only, nothing is created here
+  if (!c->cscale.count(std::make_pair(logN, K)) || !c->lifts.count(std::make_pair(L, K)) ||
+      !c->crt.count(std::make_tuple(K, eb, L)) || c->rec)
+    return FHE_E_STATE;
+  hipSetDevice(c->device);
+  return ring_mul_locked(c, logN, logq, a, b, out, cnum, stream, c->noalloc);
+}
+
 int fhe_encrypt(fhe_ctx* c, int scheme, uint32_t t, int logN, int logq, const uint32_t* pk_b, const uint32_t* pk_a,
                 const uint32_t* m, const int8_t* v, const int32_t* e0, const int32_t* e1, uint32_t* c0, uint32_t* c1,
                 void* stream) {
@@ -1616,7 +1668,7 @@ int fhe_encrypt(fhe_ctx* c, int scheme, uint32_t t, int logN, int logq, const ui
   const long long LN = (long long)L * N;
   hipError_t e = hipSuccess;
   // [v, v] against [pk_b, pk_a] mod Q_l as one pair of ring products
-  uint32_t* S = (uint32_t*)scratch(c, stream, 3, (size_t)6 * LN * 4, &e);
+  uint32_t* S = (uint32_t*)stream_scratch(c, stream, 3, (size_t)6 * LN * 4, &e);
   if (!S) return set_sticky(c, e);
   uint32_t *A = S, *B = S + 2 * LN, *P = S + 4 * LN;
   e = launch_small_to_limbs(v, A, N, L, top, st);
@@ -1647,7 +1699,7 @@ int fhe_decrypt(fhe_ctx* c, int scheme, uint32_t t, uint32_t gamma, int logN, in
   const uint32_t top = (logq & 31) ? (1u << (logq & 31)) - 1u : 0xFFFFFFFFu;
   const long long LN = (long long)L * N;
   hipError_t e = hipSuccess;
-  uint32_t* S = (uint32_t*)scratch(c, stream, 3, (size_t)3 * LN * 4, &e);
+  uint32_t* S = (uint32_t*)stream_scratch(c, stream, 3, (size_t)3 * LN * 4, &e);
   if (!S) return set_sticky(c, e);
   uint32_t *SL = S, *P = S + LN, *PH = S + 2 * LN;
   e = launch_small_to_limbs(s, SL, N, L, top, st);
