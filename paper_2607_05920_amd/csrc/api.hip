@@ -1478,6 +1478,7 @@ int fhe_ctx_create(int device, int logQ_max, int logP_max, fhe_ctx** out) {
       for (int i = 0; i < kNMax; ++i) {
         const uint32_t br = bitrev((uint32_t)i, kLogNMax);
         tw[(size_t)p * kNMax + i] = shoup_pair(pw[br], q);
+        tw[(size_t)p * kNMax + i].x = 0u - tw[(size_t)p * kNMax + i].x;  // forward butterflies take -w
         itw[(size_t)p * kNMax + i] = shoup_pair(ipw[br], q);
       }
     }

@@ -137,10 +137,12 @@ __device__ __forceinline__ void ct_bfly(uint32_t& X, uint32_t& Y, uint2 w, uint3
                                         uint32_t two_q) {
   // Lazy Cooley-Tukey butterfly: X, Y in [0, 4q) -> [0, 4q).  With the Shoup product
   // t = Y w - qh q in [0, 2q), nt = qh q - Y w = -t (mod 2^32); then X + t = X - nt
-  // and X - t + 2q = X + nt + 2q (one three-input add).
+  // and X - t + 2q = X + nt + 2q (one three-input add).  The forward table holds
+  // (-w mod 2^32, floor(w 2^32 / q)), so nt = qh q + Y (-w) is one multiply and one
+  // multiply-add: 7 operations per butterfly.
   const uint32_t x = csub(X, two_q);
   const uint32_t qh = __umulhi(Y, w.y);
-  const uint32_t nt = qh * q - Y * w.x;
+  const uint32_t nt = mad_lo(qh, q, Y * w.x);
   X = x - nt;
   Y = x + nt + two_q;
 }
@@ -330,7 +332,7 @@ __global__ __launch_bounds__((ntt_pass_threads<S, ROWS>())) void ntt_pass_kernel
 
 // Forward n-point row transforms of NP rows at once (the values x[r][u] at
 // e = u T + j, loaded by the caller): each twiddle is loaded once for all rows and
-// the NP exchanges share one barrier.  Leaves canonical values at e = 16 j + u.
+// the NP exchanges share one barrier.  Leaves values in [0, 2q) at e = 16 j + u.
 template <int S, int NP, int NB>
 __device__ __forceinline__ void fwd_rows(uint32_t (&x)[NP][16], uint32_t* const (&l)[NB], int j, const uint2* tw,
                                          int tw_mul, uint32_t q, uint32_t two_q) {
@@ -379,10 +381,11 @@ __device__ __forceinline__ void fwd_rows(uint32_t (&x)[NP][16], uint32_t* const 
         for (int u = b0; u < b0 + t; ++u) ct_bfly(x[r][u], x[r][u + t], w, q, two_q);
     }
   }
+  // [0, 4q) -> [0, 2q): the products below take lazy inputs
 #pragma unroll
   for (int r = 0; r < NP; ++r)
 #pragma unroll
-    for (int u = 0; u < 16; ++u) x[r][u] = csub(csub(x[r][u], two_q), q);
+    for (int u = 0; u < 16; ++u) x[r][u] = csub(x[r][u], two_q);
 }
 
 // First inverse n-point row stages of NP rows at once, values at e = 16 j + u in
@@ -505,13 +508,15 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 
     // transform's final factor.  d1 is formed directly (the Karatsuba identity of
     // Section 5.4 gives the same value; with full-rate multiplies the direct form issues
     // fewer instructions).
+    // Inputs in [0, 2q), outputs in [0, 2q) (what the inverse butterflies take): a
+    // product below 4 q^2 < q 2^32 reduces to [0, 2q); d1's sum below 8 q^2 (< 2^63, and
+    // T + m q < 2^64) reduces to [0, 3q), then one conditional subtraction of 2q.
     uint32_t d[3][16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      d[0][u] = mont_mul(x[0][u], x[2][u], q, qneg);
-      // canonical inputs: x0 y1 + x1 y0 < 2 q^2 < q 2^32, one Montgomery reduction
-      d[1][u] = csub(redc_lazy(mad64(x[0][u], x[3][u], mad64(x[1][u], x[2][u], 0)), q, qneg), q);
-      d[2][u] = mont_mul(x[1][u], x[3][u], q, qneg);
+      d[0][u] = redc_lazy(mad64(x[0][u], x[2][u], 0), q, qneg);
+      d[1][u] = csub(redc_lazy(mad64(x[0][u], x[3][u], mad64(x[1][u], x[2][u], 0)), q, qneg), two_q);
+      d[2][u] = redc_lazy(mad64(x[1][u], x[3][u], 0), q, qneg);
     }
     __syncthreads();  // every thread has read the forward exchange before it is overwritten
     inv_rows<S, 3, NB>(d, lb, j, itw, tw_mul, q, two_q);
@@ -536,8 +541,9 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 
     for (int u = 0; u < 16; ++u) {
       const uint32_t b = __builtin_amdgcn_raw_buffer_load_b32(rk, (int)(lane + 4u * u * T), 0, 0);
       const uint32_t ak = __builtin_amdgcn_raw_buffer_load_b32(rk, (int)(lane + 4u * u * T), (int)(4 * KN), 0);
-      k[0][u] = mont_mul(x[0][u], b, q, qneg);
-      k[1][u] = mont_mul(x[0][u], ak, q, qneg);
+      // x in [0, 2q), key canonical: products below 2 q^2, results in [0, 2q)
+      k[0][u] = redc_lazy(mad64(x[0][u], b, 0), q, qneg);
+      k[1][u] = redc_lazy(mad64(x[0][u], ak, 0), q, qneg);
     }
     // the buffer the forward exchange did not use
     uint32_t* const li[1] = {lb[1]};
@@ -562,7 +568,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 
     fwd_rows<S, 2, 2>(x, lf, j, tw, tw_mul, q, two_q);
     uint32_t y[1][16];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) y[0][u] = mont_mul(x[0][u], x[1][u], q, qneg);
+    for (int u = 0; u < 16; ++u) y[0][u] = redc_lazy(mad64(x[0][u], x[1][u], 0), q, qneg);  // [0, 2q)
     __syncthreads();  // the forward exchange's buffers are reused
     uint32_t* const li[1] = {lb[0]};
     inv_rows<S, 1, 1>(y, li, j, itw, tw_mul, q, two_q);
