@@ -352,6 +352,54 @@ int fhe_ct_key_switch(fhe_ctx* ctx, fhe_evk* key, const fhe_ct* x, fhe_ct* out, 
 int fhe_ct_leftrotate(fhe_ctx* ctx, fhe_evk* key, int r, const fhe_ct* x, fhe_ct* out, void* stream);
 int fhe_ct_conjugate(fhe_ctx* ctx, fhe_evk* key, const fhe_ct* x, fhe_ct* out, void* stream);
 
+/* ---------------------------------------------------------------- bootstrapping
+ * CKKS bootstrapping (Section 6.2 `bootstrap`, HEAAN's EvalBootstrap; Section 7.2: logT
+ * sets the precision of the circuit).  The paper gives no algorithm; the reading is the
+ * published bootstrapping for approximate HE, composed from this library's fhe_ct
+ * operations (n = 2^logslots slots, gap = N / 2n, q0 = 2^logq_in, V_jk = zeta^(r_j k)
+ * with zeta = exp(2 pi i / 4n), r_j = 5^j mod 4n):
+ *   1. modulus raise: the input's limbs read at 2^logQ, scale 2^(logq_in + log2 gap);
+ *   2. SubSum: x += leftrotate(x, 2^i) for logslots <= i < logN - 1;
+ *   3. CoeffToSlot: sum_d leftrotate(x, d) * c2s[d], rescale by logc;
+ *   4. a = (x + conj x) / 2, b = i (conj x - x) / 2 (the halving as logp + 1);
+ *   5. on a and b: y = x * k_y / 2^(logc + logT) (rescale by logc + logT, scale kept);
+ *      powers y^k (k <= degree) by y^k = y^h y^(k-h), h the largest power of two below
+ *      k (y^(k/2) squared when k is a power of two), each product rescaled by the
+ *      working scale; re = sum over even k, im = sum over odd k of y^k * taylor[k] /
+ *      2^logc; E = (re + 1) + i im; logT squarings; sin = i (conj E - E) / 2;
+ *   6. w = sin(a) + i sin(b);
+ *   7. SlotToCoeff: sum_d leftrotate(w, d) * s2c[d], rescale by logc; the output's
+ *      scale is lowered by logq_in - logp bits (a change of scale only).
+ * Operands of an addition or a product are first brought to the lower one's logq
+ * (moddownBy); products are HE-mults with the relinearization key.  c2s and s2c are
+ * the encodings at 2^logc of the diagonals d of V^-1 and V / (2 pi) (diag_d[j] =
+ * A[j][(j + d) mod n]), k_y = round(2 pi 2^logc), taylor[k] = round(c_k 2^logc) with c_k
+ * the coefficients of exp(i y)'s real part (even k) or imaginary part (odd k). */
+typedef struct {
+  int logN, logslots, logq_in, logQ, logc, logT, degree;
+} fhe_boot_params;
+
+typedef struct {
+  fhe_evk* relin;         /* relinearization key at logQ_key >= logQ */
+  fhe_evk* const* rot;    /* host array: rot[r] = switching key of 5^r (NULL where unused) */
+  int nrot;               /* entries of rot: above every rotation the circuit uses */
+  fhe_evk* conj;          /* switching key of 2N - 1 */
+  const uint32_t* c2s;    /* device uint32[n][L_Q][N]: [c2s_d]_(2^logQ), L_Q = ceil(logQ / 32) */
+  const uint32_t* s2c;    /* device uint32[n][L_Q][N] */
+  int64_t k_y;
+  const int64_t* taylor;  /* host, degree + 1 entries (entry 0 unused) */
+} fhe_boot_keys;
+
+/* Bootstrap one CKKS ciphertext (cnum = 1) at logq = logq_in (its logp <= logq_in):
+ * out receives the refreshed ciphertext; out->c0, out->c1 must each hold L_Q N words
+ * (the output's level is below logQ; the call writes out's metadata).  Allocates its
+ * temporaries and synchronizes `stream` before returning.  Errors: FHE_E_INVAL (null,
+ * parameters, a missing key), FHE_E_SHAPE (the input is not a one-ciphertext CKKS tensor
+ * at logq_in of ring degree 2^logN), FHE_E_RANGE (levels exhausted: logQ too small for
+ * the circuit), plus the errors of the operations. */
+int fhe_ct_bootstrap(fhe_ctx* ctx, const fhe_boot_params* params, const fhe_boot_keys* keys, const fhe_ct* in,
+                     fhe_ct* out, void* stream);
+
 /* ---------------------------------------------------------------- batches
  * A batch of HE-mults of uneven ring degree and level (the CipherTensor of Section
  * 6.1 generalised: ciphertexts of one cell share parameters, cells differ).

@@ -82,6 +82,7 @@ EXPORTS = {
     "fhe_ct_key_switch": (_I, [_P, _P, _P, _P, _P]),
     "fhe_ct_leftrotate": (_I, [_P, _P, _I, _P, _P, _P]),
     "fhe_ct_conjugate": (_I, [_P, _P, _P, _P, _P]),
+    "fhe_ct_bootstrap": (_I, [_P, _P, _P, _P, _P, _P]),
 }
 
 PLAN_GRAPH = 1
@@ -101,6 +102,19 @@ class CT(ctypes.Structure):
     _fields_ = [("c0", _P), ("c1", _P), ("cnum", ctypes.c_int32), ("logN", ctypes.c_int32),
                 ("logq", ctypes.c_int32), ("logp", ctypes.c_int32), ("scheme", ctypes.c_int32),
                 ("t", ctypes.c_uint32), ("gamma", ctypes.c_uint32)]
+
+
+class BootParams(ctypes.Structure):
+    """fhe_boot_params."""
+    _fields_ = [("logN", _I), ("logslots", _I), ("logq_in", _I), ("logQ", _I), ("logc", _I), ("logT", _I),
+                ("degree", _I)]
+
+
+class BootKeys(ctypes.Structure):
+    """fhe_boot_keys (pointers: keys, a host array of rotation keys, device diagonals,
+    a host array of Taylor constants)."""
+    _fields_ = [("relin", _P), ("rot", _P), ("nrot", _I), ("conj", _P), ("c2s", _P), ("s2c", _P),
+                ("k_y", ctypes.c_int64), ("taylor", _P)]
 
 
 class LibraryMissing(RuntimeError):
@@ -419,8 +433,32 @@ def _ctx_ct_methods():
                                                                _ptr(in1), _ptr(out0), _ptr(out1), cnum,
                                                                _stream(stream)))
 
+    def ct_bootstrap(self, params: dict, relin, rot: dict, conj, c2s, s2c, k_y: int, taylor, x, out, stream=None):
+        """fhe_ct_bootstrap.  params: the fhe_boot_params fields; rot: rotation amount ->
+        EvalKey (Galois); c2s, s2c: device uint32[n][L_Q][N]; taylor: ints (degree + 1).
+        out = (c0, c1), each L_Q N words; returns the output Ciphertext."""
+        P = BootParams(**params)
+        n, LQ, N = 1 << P.logslots, nlimbs(P.logQ), 1 << P.logN
+        _need(c2s, n * LQ * N, "c2s")
+        _need(s2c, n * LQ * N, "s2c")
+        for t, nm in ((out[0], "out c0"), (out[1], "out c1")):
+            _need(t, LQ * N, nm)
+        nrot = max(rot) + 1
+        arr = (_P * nrot)()
+        for r, k in rot.items():
+            arr[r] = k.handle.value
+        tay = (ctypes.c_int64 * len(taylor))(*[int(v) for v in taylor])
+        K = BootKeys(relin.handle.value, ctypes.cast(arr, _P), nrot, conj.handle.value, _ptr(c2s), _ptr(s2c),
+                     int(k_y), ctypes.cast(tay, _P))
+        o = CT(_ptr(out[0]), _ptr(out[1]), 0, 0, 0, 0, 0, 0, 0)
+        _check("fhe_ct_bootstrap", load_library().fhe_ct_bootstrap(self._h, ctypes.byref(P), ctypes.byref(K),
+                                                                   ctypes.byref(_ct_in(x)), ctypes.byref(o),
+                                                                   _stream(stream)))
+        return Ciphertext(out[0], out[1], o.logN, o.logq, o.logp, o.scheme, o.t, o.gamma, o.cnum)
+
     for f in (ct_mul_relin, ct_rescale, ct_moddown, ct_add, ct_sub, ct_negate, ct_imult, ct_multconst,
-              ct_multconstvec, ct_addconst, ct_key_switch, ct_leftrotate, ct_conjugate, automorphism, key_switch):
+              ct_multconstvec, ct_addconst, ct_key_switch, ct_leftrotate, ct_conjugate, automorphism, key_switch,
+              ct_bootstrap):
         setattr(Context, f.__name__, f)
 
 

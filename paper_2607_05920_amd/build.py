@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfhe_mi355x.so")
-SOURCES = ["api.hip", "kernels.hip", "ops.hip", "encode.cpp"]
+SOURCES = ["api.hip", "kernels.hip", "ops.hip", "encode.cpp", "boot.cpp"]
 
 
 def hipcc() -> str:
