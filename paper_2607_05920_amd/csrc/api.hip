@@ -963,8 +963,7 @@ int plan_run_cells(fhe_plan* pl, hipStream_t st) {
 }
 
 // Autotuner: times each candidate launch configuration of one cell (one warm-up, then
-// the median of three runs) and keeps the fastest.  Candidates: lift primes per
-// thread 8 / 16 / 32; for odd logN, which NTT pass takes the extra stage.
+// the median of three runs) and keeps the fastest.
 int plan_autotune(fhe_plan* pl, PlanCell& cell, hipStream_t st) {
   fhe_ctx* c = pl->ctx;
   const PipeSize z = pipe_size(c, cell.evk, cell.logN, cell.logq, cell.cnum);
@@ -974,6 +973,9 @@ int plan_autotune(fhe_plan* pl, PlanCell& cell, hipStream_t st) {
     cell.tune = it->second;
     return FHE_OK;
   }
+  // Candidates: the lift on the matrix cores or the VALU (16 primes per thread); for odd
+  // logN, which pass takes the extra stage; the column passes' workgroup width (64, 32
+  // or 16 columns of 2^8 points, 64 or 32 of 2^7).
   std::vector<Tuning> cands;
   for (int lp : {0, 16})
     for (int cf : {1, 0}) {
@@ -981,7 +983,14 @@ int plan_autotune(fhe_plan* pl, PlanCell& cell, hipStream_t st) {
       Tuning t;
       t.lift_primes = lp;
       t.ntt_cols_first = cf;
-      cands.push_back(t);
+      const int s_cols = ntt_split_cols(cell.logN, t);
+      std::vector<int> widths = {0};  // the default: 64 columns per workgroup
+      if (s_cols == 8) widths = {0, 512, 256};
+      if (s_cols == 7) widths = {0, 256};
+      for (int ct : widths) {
+        t.cols_threads = ct;
+        cands.push_back(t);
+      }
     }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return FHE_E_DEVICE;
@@ -2127,28 +2136,19 @@ int fhe_automorphism(fhe_ctx* c, int logN, int logq, uint32_t g, const uint32_t*
   if (c->sticky != FHE_OK) return c->sticky;
   hipSetDevice(c->device);
   RecGuard rg(c);
-  // count polynomials as (count + 1) / 2 "ciphertexts" of two components; an odd
-  // count's last one runs alone
+  // `count` one-component polynomials
   const long long LN = (long long)L << logN;
   PermArgs pa{};
   pa.in0 = in;
-  pa.in1 = in + LN;
   pa.out0 = out;
-  pa.out1 = out + LN;
-  pa.istride = 2 * LN;
-  pa.ostride = 2 * LN;
+  pa.istride = LN;
+  pa.ostride = LN;
   pa.logN = logN;
   pa.L = L;
   pa.topmask = top_mask(logq);
   pa.mul = (uint32_t)invmod(g, 2ull << logN);
-  hipError_t e = launch_signed_perm(pa, count / 2, (hipStream_t)stream);
-  if (e == hipSuccess && (count & 1)) {
-    PermArgs p1 = pa;
-    p1.in0 = p1.in1 = in + (long long)(count - 1) * LN;
-    p1.out0 = p1.out1 = out + (long long)(count - 1) * LN;
-    e = launch_signed_perm(p1, 1, (hipStream_t)stream);  // writes the same values twice
-  }
-  return set_sticky(c, e);
+  pa.comps = 1;
+  return set_sticky(c, launch_signed_perm(pa, count, (hipStream_t)stream));
 }
 
 int fhe_key_switch(fhe_ctx* c, fhe_evk* k, int logN, int logq, const uint32_t* in0, const uint32_t* in1,

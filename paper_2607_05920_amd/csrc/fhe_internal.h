@@ -153,6 +153,7 @@ struct PermArgs {
   int logN = 0, L = 0;
   uint32_t topmask = 0xFFFFFFFFu;
   uint32_t mul = 1, add = 0;
+  int comps = 2;  // components per ciphertext (1: in0 -> out0 only)
 };
 
 // out = [(-1)^neg in k]_(2^logq) for an integer constant k of klimbs limbs.
@@ -213,6 +214,7 @@ struct Bracket {
 struct Tuning {
   int lift_primes = 0;  // 0: matrix-core lift; 8, 16 or 32: VALU lift with that many primes per thread
   int ntt_cols_first = 1;  // 1: column pass takes ceil(logN/2) stages; 0: floor
+  int cols_threads = 0;    // column-pass workgroup: 0 default (64 columns), or 256 / 512 threads
 };
 
 hipError_t launch_ntt(const NttArgs& a, int ntransforms, bool inverse, hipStream_t s,

@@ -164,11 +164,13 @@ __device__ __forceinline__ void gs_bfly(uint32_t& X, uint32_t& Y, uint2 w, uint3
 template <int S, bool ROWS>
 constexpr int ntt_pass_threads() { return ROWS ? 256 : (S >= 8 ? 1024 : (S == 7 ? 512 : 256)); }
 
-template <int S, bool INV, bool ROWS>
-__global__ __launch_bounds__((ntt_pass_threads<S, ROWS>())) void ntt_pass_kernel(NttArgs a) {
+// BLK: threads per workgroup (the autotuner may take fewer columns per workgroup than
+// ntt_pass_threads gives).
+template <int S, bool INV, bool ROWS, int BLK = ntt_pass_threads<S, ROWS>()>
+__global__ __launch_bounds__(BLK) void ntt_pass_kernel(NttArgs a) {
   constexpr int n = 1 << S;
   constexpr int T = n / 16;
-  constexpr int NSUB = ntt_pass_threads<S, ROWS>() / T;
+  constexpr int NSUB = BLK / T;
   // Row stride in LDS, chosen so that both access patterns are free of bank
   // conflicts (element e sits at s * SS + e + e / 16).
   constexpr int SS = ((n + n / 16 + 1 + 31) / 32) * 32 + (ROWS ? T : (NSUB >= 32 ? 1 : 2));
@@ -609,10 +611,9 @@ static hipError_t rows_fused_s(int S, const RowsArgs& a, hipStream_t st) {
   }
 }
 
-template <int S, bool INV, bool ROWS>
+template <int S, bool INV, bool ROWS, int BLK = ntt_pass_threads<S, ROWS>()>
 static hipError_t ntt_pass(const NttArgs& a, int ntr, hipStream_t st) {
   constexpr int n = 1 << S;
-  constexpr int BLK = ntt_pass_threads<S, ROWS>();
   constexpr int NSUB = BLK / (n / 16);
   const int nsub_total = (1 << a.logN) / n;
   const int nwg = (nsub_total + NSUB - 1) / NSUB;
@@ -622,12 +623,17 @@ static hipError_t ntt_pass(const NttArgs& a, int ntr, hipStream_t st) {
   // algorithmic HBM bytes: every element of every transform read and written once
   Bracket br(INV ? (ROWS ? KID_NTT_INV_ROWS : KID_NTT_INV_COLS) : (ROWS ? KID_NTT_FWD_ROWS : KID_NTT_FWD_COLS), st,
              8.0 * ntr * (double)(1 << a.logN));
-  hipLaunchKernelGGL((ntt_pass_kernel<S, INV, ROWS>), grid, dim3(BLK), 0, st, a);
+  hipLaunchKernelGGL((ntt_pass_kernel<S, INV, ROWS, BLK>), grid, dim3(BLK), 0, st, a);
   return hipGetLastError();
 }
 
+// cols_threads: 0 for the default workgroup of a column pass, else 256 or 512 threads
+// (16 or 32 columns of 2^8 points, 32 of 2^7) where it is smaller than the default.
 template <bool INV, bool ROWS>
-static hipError_t ntt_pass_s(int S, const NttArgs& a, int ntr, hipStream_t st) {
+static hipError_t ntt_pass_s(int S, const NttArgs& a, int ntr, hipStream_t st, int cols_threads = 0) {
+  if (!ROWS && S == 8 && cols_threads == 256) return ntt_pass<8, INV, false, 256>(a, ntr, st);
+  if (!ROWS && S == 8 && cols_threads == 512) return ntt_pass<8, INV, false, 512>(a, ntr, st);
+  if (!ROWS && S == 7 && cols_threads == 256) return ntt_pass<7, INV, false, 256>(a, ntr, st);
   switch (S) {
     case 5: return ntt_pass<5, INV, ROWS>(a, ntr, st);
     case 6: return ntt_pass<6, INV, ROWS>(a, ntr, st);
@@ -681,7 +687,8 @@ hipError_t launch_ntt_cols(const NttArgs& a0, int ntr, bool inverse, hipStream_t
   NttArgs a = a0;
   a.ntr = ntr;
   const int s_cols = ntt_split_cols(a.logN, tu);
-  return inverse ? ntt_pass_s<true, false>(s_cols, a, ntr, st) : ntt_pass_s<false, false>(s_cols, a, ntr, st);
+  return inverse ? ntt_pass_s<true, false>(s_cols, a, ntr, st, tu.cols_threads)
+                 : ntt_pass_s<false, false>(s_cols, a, ntr, st, tu.cols_threads);
 }
 
 hipError_t launch_rows_fused(const RowsArgs& a, int mode, hipStream_t st, const Tuning& tu) {

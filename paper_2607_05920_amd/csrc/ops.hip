@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void signed_perm_kernel(PermArgs a) {
   const int k = blockIdx.x * 256 + threadIdx.x;
   const int N = 1 << a.logN;
   if (k >= N) return;
-  const int z = blockIdx.y, c = z >> 1, i = z & 1;
+  const int z = blockIdx.y, c = z / a.comps, i = z % a.comps;
   const uint32_t twoN_mask = (2u << a.logN) - 1u;
   const uint32_t src = ((uint32_t)k * a.mul + a.add) & twoN_mask;
   const bool neg = src >= (uint32_t)N;
@@ -114,8 +114,9 @@ hipError_t launch_signed_perm(const PermArgs& a, int cnum, hipStream_t st) {
   if (cnum <= 0) return hipSuccess;
   if (a.logN < 1 || a.logN > kLogNMax || a.L <= 0) return hipErrorInvalidValue;
   const int N = 1 << a.logN;
-  Bracket br(KID_COEFFWISE, st, 16.0 * cnum * N * (double)a.L);
-  hipLaunchKernelGGL(signed_perm_kernel, dim3((N + 255) / 256, 2 * cnum), dim3(256), 0, st, a);
+  Bracket br(KID_COEFFWISE, st, 8.0 * a.comps * cnum * N * (double)a.L);
+  if (a.comps != 1 && a.comps != 2) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(signed_perm_kernel, dim3((N + 255) / 256, a.comps * cnum), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
