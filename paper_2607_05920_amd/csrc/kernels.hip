@@ -32,8 +32,12 @@ __device__ __forceinline__ T* wave_uniform(T* p) {
 // Raw buffer over `bytes` bytes from the wave-uniform `base`.  Loads at lane offsets at
 // or beyond `bytes` return zero (the buffer range check), which stands in for clamping
 // and masking rows past the end of a polynomial.
+// `bytes` is uniform too: it is moved to a scalar register, so that a value the compiler
+// happened to compute in vector registers does not make the descriptor divergent (which
+// would wrap every access in a loop over lanes).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_buffer(const uint32_t* base, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)bytes, 0x00020000);
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes),
+                                           0x00020000);
 }
 
 __device__ __forceinline__ uint32_t buffer_word(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
@@ -452,17 +456,25 @@ struct RowsShape {
   static constexpr int SS = ((n + n / 16 + 1 + 31) / 32) * 32 + T;
 };
 
-// 3 waves per SIMD where the LDS allows it (rows of 64 points and more)
-template <int S, int MODE>
+// 3 waves per SIMD where the LDS allows it (rows of 64 points and more).
+// CG ciphertexts per sub-row: with CG = 4 (rows of 256 points, 16 threads each), the
+// four 16-lane slots of a wave take one sub-row of four ciphertexts, so that its
+// twiddles are wave-uniform (scalar loads) and, in the relinearization form, one wave
+// instruction reads a key row once for four ciphertexts.
+template <int S, int MODE, int CG>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 : 2))) void rows_fused_kernel(
     RowsArgs a) {
   constexpr int n = RowsShape<S>::n, T = RowsShape<S>::T, NSUB = RowsShape<S>::NSUB, SS = RowsShape<S>::SS;
   constexpr int NB = kRowsBuffers;
   static_assert(NB == 2, "the relin and ring forms below pair their exchanges with 2 buffers");
+  static_assert(CG == 1 || (CG == 4 && T * CG == 64 && MODE != 2), "four ciphertexts fill one wave");
+  constexpr int RPW = NSUB / CG;  // sub-rows per workgroup
   __shared__ uint32_t lds[NB][NSUB * SS];
 
   const int tid = threadIdx.x;
   const int s = tid / T, j = tid % T;
+  const int cs = CG > 1 ? s % CG : 0;  // ciphertext within the group
+  const int sl = CG > 1 ? s / CG : s;  // sub-row within the workgroup
   const int N = 1 << a.logN;
   const int nsub_total = N / n;
   // XCD-aware: workgroup w runs on XCD w % 8, which takes primes p = w % 8 (mod 8).
@@ -470,35 +482,40 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 
   // this pass starts on the rows the forward column pass wrote last and the inverse
   // column pass on the rows this pass wrote last: those still sit in the device's
   // last-level cache.
-  const int nwg = (nsub_total + NSUB - 1) / NSUB;
-  const int per_prime = a.cnum * nwg;
+  const int nwg = (nsub_total + RPW - 1) / RPW;
+  const int ncg = (a.cnum + CG - 1) / CG;
+  const int per_prime = ncg * nwg;
   const int w = blockIdx.x, xcd = w & 7, l = w >> 3;
   const int p = (((a.K + 7) >> 3) - 1 - l / per_prime) * 8 + xcd;
   if (p >= a.K) return;  // whole workgroup exits
   const int rem = l % per_prime;
-  const int c = rem / nwg;
-  const int sg = (rem % nwg) * NSUB + s;
-  const bool valid = sg < nsub_total;
+  const int c = (rem / nwg) * CG;  // the group's first ciphertext
+  const int sg = (rem % nwg) * RPW + sl;
+  const bool valid = sg < nsub_total && c + cs < a.cnum;
   const PrimeC pc = a.pc[p];
   const uint32_t q = pc.q, two_q = pc.two_q, qneg = pc.qneg;
   const uint2* tw = a.tw + (long long)p * kNMax;
   const uint2* itw = a.itw + (long long)p * kNMax;
-  const int tw_mul = nsub_total + sg;
+  // one sub-row per wave when CG = 4: the strided stages' twiddle index is then uniform
+  const int tw_mul = CG > 1 ? __builtin_amdgcn_readfirstlane(nsub_total + sg) : nsub_total + sg;
   const long long KN = (long long)a.K * N;
   // Rows are addressed through buffer resources from the workgroup's first row of
-  // prime p: a lane's 32-bit offset selects its sub-row, a slot or key row goes into
-  // the scalar offset, and the lanes of a sub-row past the last take an offset beyond
-  // the buffer, so that their loads return zero and their stores are dropped (the
-  // range check), with no branches and no 64-bit addresses held in registers.
-  const long long base = (long long)p * N + (long long)(rem % nwg) * NSUB * n;
-  const uint32_t lane = valid ? 4u * (uint32_t)(s * n + j) : 0x7FFFFF00u;
+  // prime p (and its first ciphertext): a lane's 32-bit offset selects its sub-row and
+  // ciphertext, a slot or key row goes into the scalar offset, and the lanes of a
+  // sub-row past the last take an offset beyond the buffer, so that their loads return
+  // zero and their stores are dropped (the range check), with no branches and no 64-bit
+  // addresses held in registers.
+  const long long base = (long long)p * N + (long long)(rem % nwg) * RPW * n;
+  const uint32_t lrow = 4u * (uint32_t)(sl * n + j);
+  const uint32_t lane = valid ? lrow + 4u * (uint32_t)(cs * a.group_stride) : 0x7FFFFF00u;
+  const uint32_t span = (uint32_t)((CG - 1) * a.group_stride);  // words before the last ciphertext's rows
   uint32_t* lb[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) lb[b] = lds[b] + s * SS;
 
   if (MODE == 0) {  // tensor, in place: slots 0..3 in, 0..2 out
     const __amdgpu_buffer_rsrc_t rs =
-        row_buffer(wave_uniform(a.data + (long long)c * a.group_stride + base), (uint32_t)((3 * KN + NSUB * n) * 4));
+        row_buffer(wave_uniform(a.data + (long long)c * a.group_stride + base), (uint32_t)((3 * KN + NSUB * n) * 4) + 4u * span);
     uint32_t x[4][16];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -529,9 +546,14 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 
         __builtin_amdgcn_raw_buffer_store_b32(d[r][u], rs, (int)(lane + 4u * u * T), (int)(4 * r * KN), 0);
   } else if (MODE == 1) {  // relin: d2 row times the key's two rows, to out
     const uint32_t bytes = (uint32_t)((KN + NSUB * n) * 4);
-    const __amdgpu_buffer_rsrc_t ri = row_buffer(wave_uniform(a.data + (long long)c * a.group_stride + base), bytes);
+    const __amdgpu_buffer_rsrc_t ri =
+        row_buffer(wave_uniform(a.data + (long long)c * a.group_stride + base), bytes + 4u * span);
     const __amdgpu_buffer_rsrc_t rk = row_buffer(wave_uniform(a.key + base), bytes);
-    const __amdgpu_buffer_rsrc_t ro = row_buffer(wave_uniform(a.out + (long long)c * a.out_stride + base), bytes);
+    const __amdgpu_buffer_rsrc_t ro = row_buffer(wave_uniform(a.out + (long long)c * a.out_stride + base),
+                                                 bytes + 4u * (uint32_t)((CG - 1) * a.out_stride));
+    // the key rows are the same for every ciphertext: lane offset without the ciphertext's
+    const uint32_t lk = valid ? lrow : 0x7FFFFF00u;
+    const uint32_t lo = valid ? lrow + 4u * (uint32_t)(cs * a.out_stride) : 0x7FFFFF00u;
     uint32_t x[1][16], k[2][16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) x[0][u] = __builtin_amdgcn_raw_buffer_load_b32(ri, (int)(lane + 4u * u * T), 0, 0);
@@ -541,8 +563,8 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 
     // 16 j + u sits at u T + j, so that these loads are coalesced
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const uint32_t b = __builtin_amdgcn_raw_buffer_load_b32(rk, (int)(lane + 4u * u * T), 0, 0);
-      const uint32_t ak = __builtin_amdgcn_raw_buffer_load_b32(rk, (int)(lane + 4u * u * T), (int)(4 * KN), 0);
+      const uint32_t b = __builtin_amdgcn_raw_buffer_load_b32(rk, (int)(lk + 4u * u * T), 0, 0);
+      const uint32_t ak = __builtin_amdgcn_raw_buffer_load_b32(rk, (int)(lk + 4u * u * T), (int)(4 * KN), 0);
       // x in [0, 2q), key canonical: products below 2 q^2, results in [0, 2q)
       k[0][u] = redc_lazy(mad64(x[0][u], b, 0), q, qneg);
       k[1][u] = redc_lazy(mad64(x[0][u], ak, 0), q, qneg);
@@ -554,7 +576,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 
     for (int r = 0; r < 2; ++r)
 #pragma unroll
       for (int u = 0; u < 16; ++u)
-        __builtin_amdgcn_raw_buffer_store_b32(k[r][u], ro, (int)(lane + 4u * u * T), (int)(4 * r * KN), 0);
+        __builtin_amdgcn_raw_buffer_store_b32(k[r][u], ro, (int)(lo + 4u * u * T), (int)(4 * r * KN), 0);
   } else {  // ring: a times b, in place of a
     const uint32_t bytes = (uint32_t)(NSUB * n * 4);
     const __amdgpu_buffer_rsrc_t ra = row_buffer(wave_uniform(a.data + (long long)c * a.group_stride + base), bytes);
@@ -579,34 +601,47 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 
   }
 }
 
-template <int S, int MODE>
+template <int S, int MODE, int CG>
 static hipError_t rows_fused(const RowsArgs& a, hipStream_t st) {
   constexpr int n = 1 << S;
-  constexpr int NSUB = RowsShape<S>::NSUB;
+  constexpr int RPW = RowsShape<S>::NSUB / CG;
   const int nsub_total = (1 << a.logN) / n;
-  const int nwg = (nsub_total + NSUB - 1) / NSUB;
+  const int nwg = (nsub_total + RPW - 1) / RPW;
   const int kx = (a.K + 7) / 8;
-  // the largest buffer (the tensor form's) spans 3 K N + NSUB n words and must stay
-  // below the out-of-range lane offset 0x7FFFFF00 (bytes)
-  if ((3LL * a.K * (1LL << a.logN) + (long long)NSUB * n) * 4 >= 0x70000000LL) return hipErrorInvalidValue;
-  dim3 grid(8 * kx * a.cnum * nwg);
+  const int ncg = (a.cnum + CG - 1) / CG;
+  dim3 grid(8 * kx * ncg * nwg);
   // algorithmic HBM bytes per prime: tensor 4 rows in and 3 out per ciphertext; relin
   // 1 row in and 2 out per ciphertext plus the key's 2 rows once; ring 2 in (b once per
   // distinct operand) and 1 out per group
   const int b_rows = a.data2_stride ? std::min(a.data2_groups, a.cnum) : 1;
   const double rows = MODE == 0 ? 7.0 * a.cnum : (MODE == 1 ? 3.0 * a.cnum + 2.0 : 2.0 * a.cnum + b_rows);
   Bracket br(KID_ROWS_FUSED, st, 4.0 * rows * a.K * (double)(1 << a.logN));
-  hipLaunchKernelGGL((rows_fused_kernel<S, MODE>), grid, dim3(128), 0, st, a);
+  hipLaunchKernelGGL((rows_fused_kernel<S, MODE, CG>), grid, dim3(128), 0, st, a);
   return hipGetLastError();
+}
+
+// Bytes a workgroup's buffers span from their base: they must stay below the
+// out-of-range lane offset 0x7FFFFF00 (the tensor form's, the largest, spans 3 K N words
+// past its group's last ciphertext; the relinearization output 1 K N past it), plus the
+// workgroup's NSUB n = 2048 words.
+static long long rows_span_bytes(const RowsArgs& a, int cg) {
+  const long long KN = (long long)a.K << a.logN;
+  const long long last = (long long)(cg - 1) * std::max(a.group_stride, a.out_stride);
+  return (last + 3 * KN + 2048) * 4;
 }
 
 template <int MODE>
 static hipError_t rows_fused_s(int S, const RowsArgs& a, hipStream_t st) {
+  if (rows_span_bytes(a, 1) >= 0x70000000LL) return hipErrorInvalidValue;
+  // four ciphertexts per sub-row where rows are 256 points and at most 1 slot in 8 idles
+  if (MODE != 2 && S == 8 && 8 * (4 * ((a.cnum + 3) / 4) - a.cnum) <= 4 * ((a.cnum + 3) / 4) &&
+      rows_span_bytes(a, 4) < 0x70000000LL)
+    return rows_fused<8, MODE == 2 ? 0 : MODE, 4>(a, st);
   switch (S) {
-    case 5: return rows_fused<5, MODE>(a, st);
-    case 6: return rows_fused<6, MODE>(a, st);
-    case 7: return rows_fused<7, MODE>(a, st);
-    case 8: return rows_fused<8, MODE>(a, st);
+    case 5: return rows_fused<5, MODE, 1>(a, st);
+    case 6: return rows_fused<6, MODE, 1>(a, st);
+    case 7: return rows_fused<7, MODE, 1>(a, st);
+    case 8: return rows_fused<8, MODE, 1>(a, st);
     default: return hipErrorInvalidValue;
   }
 }

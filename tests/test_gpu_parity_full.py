@@ -8,6 +8,9 @@ the smaller cases do not reach:
 - BGV and CKKS with the ciphertext below the key's level (the key reduced mod P Q_l);
 - N = 2^15 (the 2^8 x 2^7 transform split), per-op and through an autotuned batch plan
   (which may pick the other split and the key's second layout);
+- N = 2^16 CipherTensors of 7 and 8 pairs (the fused row pass then takes four
+  ciphertexts per sub-row, the last group of 7 with one slot idle) against the same pairs
+  one at a time, and one ciphertext of the idle-slot group against the oracle;
 - a relinearization product whose reconstruction table exceeds the LDS (the
   reconstruction's global-memory form).
 
@@ -195,6 +198,40 @@ def test_he_mult_logn15_per_op_and_autotuned_plan():
             k.close()
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("cnum", [7, 8])
+def test_he_mult_logn16_ciphertext_groups(cnum):
+    """N = 2^16, logq = logP = 218: a CipherTensor of cnum pairs equals the same pairs
+    run one at a time (one ciphertext per sub-row), and ciphertext 6 equals the oracle on
+    every coefficient."""
+    logN, logq, logP, bits = 16, 218, 218, 40
+    N = 1 << logN
+    rk, rm, _, _ = synth.streams(16 + cnum)
+    eb = synth.uniform_limbs(rk, logq + logP, N)
+    ea = synth.uniform_limbs(rk, logq + logP, N)
+    x = (synth.uniform_limbs(rm, logq, N, count=cnum), synth.uniform_limbs(rm, logq, N, count=cnum))
+    y = (synth.uniform_limbs(rm, logq, N, count=cnum), synth.uniform_limbs(rm, logq, N, count=cnum))
+    ctx = fhe.Context(logq, logP)
+    try:
+        k = fhe.EvalKey(ctx, fhe.CKKS, 0, logN, logq, logP, eb, ea)
+        say(f"logN=16 CipherTensor of {cnum}")
+        g0, g1 = _run(ctx, k, logN, logq, bits, x, y, cnum)
+        for c in range(cnum):
+            say(f"logN=16 single ciphertext {c}")
+            s0, s1 = _run(ctx, k, logN, logq, bits, tuple(v[c:c + 1] for v in x), tuple(v[c:c + 1] for v in y), 1)
+            assert np.array_equal(g0[c], s0[0]) and np.array_equal(g1[c], s1[0]), f"ciphertext {c}"
+        k.close()
+    finally:
+        ctx.close()
+    say("logN=16 oracle, ciphertext 6")
+    evk = scheme.EvalKey(ints(eb), ints(ea), logN, logq, logP, scheme.CKKS, 0)
+    with oracle_pool(6) as pool:
+        want = scheme.mult_rescale(oracle_ct(x[0][6], x[1][6], logN, logq, scheme.CKKS, 0),
+                                   oracle_ct(y[0][6], y[1][6], logN, logq, scheme.CKKS, 0), evk, bits,
+                                   mapper=pool.map)
+    check(ints(g0[6]), want.c0, "c0[6]")
+    check(ints(g1[6]), want.c1, "c1[6]")
 
 
 def test_relin_reconstruction_table_in_global_memory():
