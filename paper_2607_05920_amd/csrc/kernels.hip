@@ -324,6 +324,16 @@ __global__ __launch_bounds__(BLK) void ntt_pass_kernel(NttArgs a) {
 }
 
 // ---------------------------------------------------------------------------- fused row pass
+// Every LDS exchange of the row passes stays inside one T-thread slot, and a slot
+// (T <= 16 threads) never straddles two waves: a wave-level ordering point is enough
+// between the writes and the reads (a wave's LDS accesses are performed in order), so
+// the two waves of a workgroup never wait for each other.
+__device__ __forceinline__ void slot_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // The last forward pass, the pointwise products and the first inverse pass touch
 // the same n-point rows: one kernel loads each input row once, finishes its forward
 // transform in registers, multiplies (Eq. ntt_mul), runs the first inverse stages
@@ -358,7 +368,7 @@ __device__ __forceinline__ void fwd_rows(uint32_t (&x)[NP][16], uint32_t* const 
   // the transpose through LDS, NB rows at a time (fewer buffers, more workgroups per CU)
 #pragma unroll
   for (int r0 = 0; r0 < NP; r0 += NB) {
-    if (r0 > 0) __syncthreads();  // every thread has read the previous round
+    if (r0 > 0) slot_sync();  // every lane of the slot has read the previous round
 #pragma unroll
     for (int r = r0; r < NP && r < r0 + NB; ++r)
 #pragma unroll
@@ -366,7 +376,7 @@ __device__ __forceinline__ void fwd_rows(uint32_t (&x)[NP][16], uint32_t* const 
         const int e = u * T + j;
         l[r - r0][e + (e >> 4)] = x[r][u];
       }
-    __syncthreads();
+    slot_sync();
 #pragma unroll
     for (int r = r0; r < NP && r < r0 + NB; ++r)
 #pragma unroll
@@ -414,7 +424,7 @@ __device__ __forceinline__ void inv_rows(uint32_t (&x)[NP][16], uint32_t* const 
   }
 #pragma unroll
   for (int r0 = 0; r0 < NP; r0 += NB) {
-    if (r0 > 0) __syncthreads();  // every thread has read the previous round
+    if (r0 > 0) slot_sync();  // every lane of the slot has read the previous round
 #pragma unroll
     for (int r = r0; r < NP && r < r0 + NB; ++r)
 #pragma unroll
@@ -422,7 +432,7 @@ __device__ __forceinline__ void inv_rows(uint32_t (&x)[NP][16], uint32_t* const 
         const int e = 16 * j + u;
         l[r - r0][e + (e >> 4)] = x[r][u];
       }
-    __syncthreads();
+    slot_sync();
 #pragma unroll
     for (int r = r0; r < NP && r < r0 + NB; ++r)
 #pragma unroll
@@ -446,8 +456,10 @@ __device__ __forceinline__ void inv_rows(uint32_t (&x)[NP][16], uint32_t* const 
 }
 
 // Rows per workgroup of the fused pass: 8 rows of 256 points (128 threads).  The LDS
-// transposes go through kRowsBuffers buffers of 8 rows, as many rows at a time: with
-// the registers of 3 waves per SIMD (168), 6 workgroups of 2 buffers fit in the LDS.
+// transposes of the tensor and ring forms go through kRowsBuffers buffers of 8 rows, as
+// many rows at a time: with the registers of 3 waves per SIMD (168), 6 workgroups of 2
+// buffers fit in the LDS.  The relinearization form (under 96 registers) takes one
+// buffer, so that 10 of its workgroups (5 waves per SIMD) fit.
 constexpr int kRowsBuffers = 2;
 template <int S>
 struct RowsShape {
@@ -456,7 +468,8 @@ struct RowsShape {
   static constexpr int SS = ((n + n / 16 + 1 + 31) / 32) * 32 + T;
 };
 
-// 3 waves per SIMD where the LDS allows it (rows of 64 points and more).
+// At least 3 waves per SIMD where the LDS allows it (rows of 64 points and more); the
+// relinearization form's registers give it 5.
 // CG ciphertexts per sub-row: with CG = 4 (rows of 256 points, 16 threads each), the
 // four 16-lane slots of a wave take one sub-row of four ciphertexts, so that its
 // twiddles are wave-uniform (scalar loads) and, in the relinearization form, one wave
@@ -465,8 +478,10 @@ template <int S, int MODE, int CG>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 : 2))) void rows_fused_kernel(
     RowsArgs a) {
   constexpr int n = RowsShape<S>::n, T = RowsShape<S>::T, NSUB = RowsShape<S>::NSUB, SS = RowsShape<S>::SS;
-  constexpr int NB = kRowsBuffers;
-  static_assert(NB == 2, "the relin and ring forms below pair their exchanges with 2 buffers");
+  // the relinearization form exchanges one row at a time through one buffer: half the
+  // LDS, so that its registers (below 100) and not the LDS bound its waves per SIMD
+  constexpr int NB = MODE == 1 ? 1 : kRowsBuffers;
+  static_assert(kRowsBuffers == 2, "the tensor and ring forms below pair their exchanges with 2 buffers");
   static_assert(CG == 1 || (CG == 4 && T * CG == 64 && MODE != 2), "four ciphertexts fill one wave");
   constexpr int RPW = NSUB / CG;  // sub-rows per workgroup
   __shared__ uint32_t lds[NB][NSUB * SS];
@@ -537,7 +552,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 
       d[1][u] = csub(redc_lazy(mad64(x[0][u], x[3][u], mad64(x[1][u], x[2][u], 0)), q, qneg), two_q);
       d[2][u] = redc_lazy(mad64(x[1][u], x[3][u], 0), q, qneg);
     }
-    __syncthreads();  // every thread has read the forward exchange before it is overwritten
+    slot_sync();  // every lane has read the forward exchange before it is overwritten
     inv_rows<S, 3, NB>(d, lb, j, itw, tw_mul, q, two_q);
 #pragma unroll
     for (int r = 0; r < 3; ++r)
@@ -569,8 +584,8 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 
       k[0][u] = redc_lazy(mad64(x[0][u], b, 0), q, qneg);
       k[1][u] = redc_lazy(mad64(x[0][u], ak, 0), q, qneg);
     }
-    // the buffer the forward exchange did not use
-    uint32_t* const li[1] = {lb[1]};
+    slot_sync();  // every lane has read the forward exchange before it is overwritten
+    uint32_t* const li[1] = {lb[0]};
     inv_rows<S, 2, 1>(k, li, j, itw, tw_mul, q, two_q);
 #pragma unroll
     for (int r = 0; r < 2; ++r)
@@ -593,7 +608,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 
     uint32_t y[1][16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) y[0][u] = redc_lazy(mad64(x[0][u], x[1][u], 0), q, qneg);  // [0, 2q)
-    __syncthreads();  // the forward exchange's buffers are reused
+    slot_sync();  // the forward exchange's buffers are reused
     uint32_t* const li[1] = {lb[0]};
     inv_rows<S, 1, 1>(y, li, j, itw, tw_mul, q, two_q);
 #pragma unroll
