@@ -346,23 +346,75 @@ __device__ __forceinline__ void slot_sync() {
 //   relin:  row d2 and the key's rows b', a' -> k0 = d2 b', k1 = d2 a' (to out)
 //   ring:   rows a, b -> a b (in place of a)
 
+// A row's twiddles for one direction, loaded ahead of the stages that use them: the
+// exchange's ordering points keep the compiler from moving loads across them, so the
+// loads are issued before (the strided stages' 15, wave-uniform when a wave holds one
+// sub-row, land in scalar registers; the contiguous stages' up to 15 per thread).
+template <int S>
+struct RowTw {
+  uint2 s[15];  // strided stages: stage st, group g at (1 << st) - 1 + g
+  uint2 c[15];  // contiguous stages, in the order the stages run
+};
+
+template <int S, bool INV>
+__device__ __forceinline__ void load_strided_tw(RowTw<S>& w, const uint2* tw, int tw_mul) {
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int m = INV ? (8 >> st) : (1 << st);
+#pragma unroll
+    for (int g = 0; g < m; ++g) w.s[m - 1 + g] = tw[tw_mul * m + g];
+  }
+}
+
+// Index in RowTw::c of the contiguous stage with half-distance t, block b0: the forward
+// stages run t = T/2 .. 1 (8/t twiddles each), the inverse ones t = 1 .. T/2.
+template <int S>
+__device__ constexpr int fwd_ci(int t, int b0) { return 8 / t - 256 / (1 << S) + b0 / (2 * t); }
+__device__ constexpr int inv_ci(int t, int b0) { return 16 - 16 / t + b0 / (2 * t); }
+
+template <int S, bool INV>
+__device__ __forceinline__ void load_contig_tw(RowTw<S>& w, const uint2* tw, int tw_mul, int j) {
+  constexpr int n = 1 << S, T = n / 16;
+#pragma unroll
+  for (int t = 1; t < T; t <<= 1)
+#pragma unroll
+    for (int b0 = 0; b0 < 16; b0 += 2 * t)
+      w.c[INV ? inv_ci(t, b0) : fwd_ci<S>(t, b0)] = tw[tw_mul * (n / (2 * t)) + j * (8 / t) + b0 / (2 * t)];
+}
+
+// The inverse direction's twiddles, issued at once (before the products that precede
+// their first use).
+template <int S>
+__device__ __forceinline__ void load_inv_tw(RowTw<S>& w, const uint2* itw, int tw_mul, int j) {
+  load_contig_tw<S, true>(w, itw, tw_mul, j);
+  load_strided_tw<S, true>(w, itw, tw_mul);
+  __builtin_amdgcn_sched_barrier(0);
+}
+
 // Forward n-point row transforms of NP rows at once (the values x[r][u] at
 // e = u T + j, loaded by the caller): each twiddle is loaded once for all rows and
-// the NP exchanges share one barrier.  Leaves values in [0, 2q) at e = 16 j + u.
-template <int S, int NP, int NB>
+// the NP exchanges share one ordering point.  Leaves values in [0, 2q) at e = 16 j + u.
+// HOIST: twiddles loaded ahead of their stages (RowTw).
+template <int S, int NP, int NB, bool HOIST = false>
 __device__ __forceinline__ void fwd_rows(uint32_t (&x)[NP][16], uint32_t* const (&l)[NB], int j, const uint2* tw,
                                          int tw_mul, uint32_t q, uint32_t two_q) {
   constexpr int n = 1 << S, T = n / 16;
+  RowTw<S> w;
+  if (HOIST) {  // all of this direction's twiddles issued before the first stage
+    load_strided_tw<S, false>(w, tw, tw_mul);
+    load_contig_tw<S, false>(w, tw, tw_mul, j);
+    __builtin_amdgcn_sched_barrier(0);
+  }
 #pragma unroll
   for (int st = 0; st < 4; ++st) {
     const int m = 1 << st, h = 8 >> st;
 #pragma unroll
     for (int g = 0; g < m; ++g) {
-      const uint2 w = tw[tw_mul * m + g];
+      const uint2 wg = HOIST ? w.s[m - 1 + g] : tw[tw_mul * m + g];
 #pragma unroll
       for (int r = 0; r < NP; ++r)
 #pragma unroll
-        for (int u = 2 * h * g; u < 2 * h * g + h; ++u) ct_bfly(x[r][u], x[r][u + h], w, q, two_q);
+        for (int u = 2 * h * g; u < 2 * h * g + h; ++u) ct_bfly(x[r][u], x[r][u + h], wg, q, two_q);
     }
   }
   // the transpose through LDS, NB rows at a time (fewer buffers, more workgroups per CU)
@@ -390,11 +442,11 @@ __device__ __forceinline__ void fwd_rows(uint32_t (&x)[NP][16], uint32_t* const 
     const int m = n / (2 * t);
 #pragma unroll
     for (int b0 = 0; b0 < 16; b0 += 2 * t) {
-      const uint2 w = tw[tw_mul * m + j * (8 / t) + b0 / (2 * t)];
+      const uint2 wg = HOIST ? w.c[fwd_ci<S>(t, b0)] : tw[tw_mul * m + j * (8 / t) + b0 / (2 * t)];
 #pragma unroll
       for (int r = 0; r < NP; ++r)
 #pragma unroll
-        for (int u = b0; u < b0 + t; ++u) ct_bfly(x[r][u], x[r][u + t], w, q, two_q);
+        for (int u = b0; u < b0 + t; ++u) ct_bfly(x[r][u], x[r][u + t], wg, q, two_q);
     }
   }
   // [0, 4q) -> [0, 2q): the products below take lazy inputs
@@ -405,21 +457,22 @@ __device__ __forceinline__ void fwd_rows(uint32_t (&x)[NP][16], uint32_t* const 
 }
 
 // First inverse n-point row stages of NP rows at once, values at e = 16 j + u in
-// [0, 2q); leaves values in [0, 2q) at e = u T + j for the caller to store.
-template <int S, int NP, int NB>
+// [0, 2q); leaves values in [0, 2q) at e = u T + j for the caller to store.  HOIST: the
+// caller has loaded the twiddles into pre (load_inv_tw, before the products).
+template <int S, int NP, int NB, bool HOIST = false>
 __device__ __forceinline__ void inv_rows(uint32_t (&x)[NP][16], uint32_t* const (&l)[NB], int j, const uint2* tw,
-                                         int tw_mul, uint32_t q, uint32_t two_q) {
+                                         int tw_mul, uint32_t q, uint32_t two_q, RowTw<S>& pre) {
   constexpr int n = 1 << S, T = n / 16;
 #pragma unroll
   for (int t = 1; t < T; t <<= 1) {
     const int h = n / (2 * t);
 #pragma unroll
     for (int b0 = 0; b0 < 16; b0 += 2 * t) {
-      const uint2 w = tw[tw_mul * h + j * (8 / t) + b0 / (2 * t)];
+      const uint2 wg = HOIST ? pre.c[inv_ci(t, b0)] : tw[tw_mul * h + j * (8 / t) + b0 / (2 * t)];
 #pragma unroll
       for (int r = 0; r < NP; ++r)
 #pragma unroll
-        for (int u = b0; u < b0 + t; ++u) gs_bfly(x[r][u], x[r][u + t], w, q, two_q);
+        for (int u = b0; u < b0 + t; ++u) gs_bfly(x[r][u], x[r][u + t], wg, q, two_q);
     }
   }
 #pragma unroll
@@ -446,11 +499,11 @@ __device__ __forceinline__ void inv_rows(uint32_t (&x)[NP][16], uint32_t* const 
     const int hd = 1 << st, h = 8 >> st;
 #pragma unroll
     for (int g = 0; g < h; ++g) {
-      const uint2 w = tw[tw_mul * h + g];
+      const uint2 wg = HOIST ? pre.s[h - 1 + g] : tw[tw_mul * h + g];
 #pragma unroll
       for (int r = 0; r < NP; ++r)
 #pragma unroll
-        for (int u = 2 * hd * g; u < 2 * hd * g + hd; ++u) gs_bfly(x[r][u], x[r][u + hd], w, q, two_q);
+        for (int u = 2 * hd * g; u < 2 * hd * g + hd; ++u) gs_bfly(x[r][u], x[r][u + hd], wg, q, two_q);
     }
   }
 }
@@ -484,6 +537,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 
   static_assert(kRowsBuffers == 2, "the tensor and ring forms below pair their exchanges with 2 buffers");
   static_assert(CG == 1 || (CG == 4 && T * CG == 64 && MODE != 2), "four ciphertexts fill one wave");
   constexpr int RPW = NSUB / CG;  // sub-rows per workgroup
+  constexpr bool HOIST = CG > 1;   // twiddles loaded ahead (scalar registers for the strided stages)
   __shared__ uint32_t lds[NB][NSUB * SS];
 
   const int tid = threadIdx.x;
@@ -537,7 +591,9 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 
 #pragma unroll
       for (int u = 0; u < 16; ++u)
         x[r][u] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(lane + 4u * u * T), (int)(4 * r * KN), 0);
-    fwd_rows<S, 4, NB>(x, lb, j, tw, tw_mul, q, two_q);
+    fwd_rows<S, 4, NB, HOIST>(x, lb, j, tw, tw_mul, q, two_q);
+    RowTw<S> wi;
+    if (HOIST) load_inv_tw<S>(wi, itw, tw_mul, j);  // in flight during the products
     // Montgomery products (Eq. ntt_mul) carry a factor 2^-32, compensated in the inverse
     // transform's final factor.  d1 is formed directly (the Karatsuba identity of
     // Section 5.4 gives the same value; with full-rate multiplies the direct form issues
@@ -553,7 +609,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 
       d[2][u] = redc_lazy(mad64(x[1][u], x[3][u], 0), q, qneg);
     }
     slot_sync();  // every lane has read the forward exchange before it is overwritten
-    inv_rows<S, 3, NB>(d, lb, j, itw, tw_mul, q, two_q);
+    inv_rows<S, 3, NB, HOIST>(d, lb, j, itw, tw_mul, q, two_q, wi);
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -573,7 +629,9 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 
 #pragma unroll
     for (int u = 0; u < 16; ++u) x[0][u] = __builtin_amdgcn_raw_buffer_load_b32(ri, (int)(lane + 4u * u * T), 0, 0);
     uint32_t* const lf[1] = {lb[0]};
-    fwd_rows<S, 1, 1>(x, lf, j, tw, tw_mul, q, two_q);
+    fwd_rows<S, 1, 1, HOIST>(x, lf, j, tw, tw_mul, q, two_q);
+    RowTw<S> wi;
+    if (HOIST) load_inv_tw<S>(wi, itw, tw_mul, j);
     // the key rows are stored transposed (launch_row_transpose): thread j's element
     // 16 j + u sits at u T + j, so that these loads are coalesced
 #pragma unroll
@@ -586,7 +644,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 
     }
     slot_sync();  // every lane has read the forward exchange before it is overwritten
     uint32_t* const li[1] = {lb[0]};
-    inv_rows<S, 2, 1>(k, li, j, itw, tw_mul, q, two_q);
+    inv_rows<S, 2, 1, HOIST>(k, li, j, itw, tw_mul, q, two_q, wi);
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
@@ -610,7 +668,8 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 
     for (int u = 0; u < 16; ++u) y[0][u] = redc_lazy(mad64(x[0][u], x[1][u], 0), q, qneg);  // [0, 2q)
     slot_sync();  // the forward exchange's buffers are reused
     uint32_t* const li[1] = {lb[0]};
-    inv_rows<S, 1, 1>(y, li, j, itw, tw_mul, q, two_q);
+    RowTw<S> wi;  // unused: this form loads its twiddles in place
+    inv_rows<S, 1, 1>(y, li, j, itw, tw_mul, q, two_q, wi);
 #pragma unroll
     for (int u = 0; u < 16; ++u) __builtin_amdgcn_raw_buffer_store_b32(y[0][u], ra, (int)(lane + 4u * u * T), 0, 0);
   }
