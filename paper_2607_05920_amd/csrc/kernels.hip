@@ -212,21 +212,29 @@ __global__ __launch_bounds__(BLK) void ntt_pass_kernel(NttArgs a) {
   const uint2* tw = a.tw + (long long)p * kNMax;
 
   // ROWS: element e of block sg at sg * n + e.  COLS: element e of column sg at
-  // sg + (N / n) e.
-  const long long gstride = ROWS ? 1 : (long long)nsub_total;
-  uint32_t* gp = base + (ROWS ? (long long)sg * n : (long long)sg);
+  // sg + (N / n) e.  Elements are addressed through a buffer resource over the transform
+  // (N words from its first): a lane's 32-bit offset holds its block or column and its
+  // thread index, the element index's part that is the same on every lane goes into the
+  // scalar offset, and lanes past the last block or column take an offset beyond the
+  // buffer (their loads return zero and their stores are dropped).
+  const uint32_t es = ROWS ? 4u : 4u * (uint32_t)nsub_total;  // bytes from element e to e + 1
+  const __amdgpu_buffer_rsrc_t rb = row_buffer(wave_uniform(base), 4u * (uint32_t)N);
+  const uint32_t sub = 4u * (uint32_t)(ROWS ? sg * n : sg);
+  const uint32_t o_str = valid ? sub + (uint32_t)j * es : 0x7FFFFF00u;        // e = u T + j
+  const uint32_t o_con = valid ? sub + 16u * (uint32_t)j * es : 0x7FFFFF00u;  // e = 16 j + u
   // Twiddle index of local stage m (groups) and local group i:
   // COLS -> m + i; ROWS -> (N / n + sg) m + i.
   const int tw_mul = ROWS ? (nsub_total + sg) : 1;
+  // a column pass of 64 columns or more per workgroup has one j per wave: its contiguous
+  // stages' twiddles are then wave-uniform (scalar loads)
+  const int jt = (!ROWS && NSUB % 64 == 0) ? __builtin_amdgcn_readfirstlane(j) : j;
 
   uint32_t x[16];
   uint32_t* lrow = lds + s * SS;
 
   if (!INV) {
-    if (valid) {
 #pragma unroll
-      for (int u = 0; u < 16; ++u) x[u] = gp[(long long)(u * T + j) * gstride];
-    }
+    for (int u = 0; u < 16; ++u) x[u] = __builtin_amdgcn_raw_buffer_load_b32(rb, (int)o_str, (int)(u * T * es), 0);
     // strided stages: m = 1, 2, 4, 8 groups, register distance 8 / m
 #pragma unroll
     for (int st = 0; st < 4; ++st) {
@@ -255,7 +263,7 @@ __global__ __launch_bounds__(BLK) void ntt_pass_kernel(NttArgs a) {
       const int m = n / (2 * t);
 #pragma unroll
       for (int b0 = 0; b0 < 16; b0 += 2 * t) {
-        const uint2 w = tw[tw_mul * m + j * (8 / t) + b0 / (2 * t)];
+        const uint2 w = tw[tw_mul * m + jt * (8 / t) + b0 / (2 * t)];
 #pragma unroll
         for (int u = b0; u < b0 + t; ++u) ct_bfly(x[u], x[u + t], w, q, two_q);
       }
@@ -264,22 +272,18 @@ __global__ __launch_bounds__(BLK) void ntt_pass_kernel(NttArgs a) {
 #pragma unroll
       for (int u = 0; u < 16; ++u) x[u] = csub(csub(x[u], two_q), q);
     }
-    if (valid) {
 #pragma unroll
-      for (int u = 0; u < 16; ++u) gp[(long long)(16 * j + u) * gstride] = x[u];
-    }
+    for (int u = 0; u < 16; ++u) __builtin_amdgcn_raw_buffer_store_b32(x[u], rb, (int)o_con, (int)(u * es), 0);
   } else {
-    if (valid) {
 #pragma unroll
-      for (int u = 0; u < 16; ++u) x[u] = gp[(long long)(16 * j + u) * gstride];
-    }
+    for (int u = 0; u < 16; ++u) x[u] = __builtin_amdgcn_raw_buffer_load_b32(rb, (int)o_con, (int)(u * es), 0);
     // contiguous stages: t = 1 .. T/2, h = n / (2t) groups
 #pragma unroll
     for (int t = 1; t < T; t <<= 1) {
       const int h = n / (2 * t);
 #pragma unroll
       for (int b0 = 0; b0 < 16; b0 += 2 * t) {
-        const uint2 w = tw[tw_mul * h + j * (8 / t) + b0 / (2 * t)];
+        const uint2 w = tw[tw_mul * h + jt * (8 / t) + b0 / (2 * t)];
 #pragma unroll
         for (int u = b0; u < b0 + t; ++u) gs_bfly(x[u], x[u + t], w, q, two_q);
       }
@@ -316,10 +320,8 @@ __global__ __launch_bounds__(BLK) void ntt_pass_kernel(NttArgs a) {
         for (int u = 0; u < 16; ++u) x[u] = csub(x[u], q);
       }
     }
-    if (valid) {
 #pragma unroll
-      for (int u = 0; u < 16; ++u) gp[(long long)(u * T + j) * gstride] = x[u];
-    }
+    for (int u = 0; u < 16; ++u) __builtin_amdgcn_raw_buffer_store_b32(x[u], rb, (int)o_str, (int)(u * T * es), 0);
   }
 }
 
