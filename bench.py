@@ -219,12 +219,53 @@ def batched_uneven(fhe, torch, synth, dev, stream, njobs):
     torch.cuda.synchronize()
     perop = reps * njobs / (ev0.elapsed_time(ev1) / 1e3)
     exact = all(torch.equal(j[7], r[0]) and torch.equal(j[8], r[1]) for j, r in zip(jobs, ref))
+    plan.close()
+    # the same jobs stage by stage: one launch per pipeline step and kernel variant over
+    # every cell (a device table of cell segments), captured in one graph
+    for j in jobs:
+        j[7].zero_()
+        j[8].zero_()
+    t0 = time.perf_counter()
+    qplan = fhe.BatchPlan(ctx, jobs, flags=fhe.PLAN_QUEUE | fhe.PLAN_GRAPH | fhe.PLAN_AUTOTUNE)
+    qplan_s = time.perf_counter() - t0
+    qinfo = qplan.info()
+    qplan.run()
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(reps):
+        qplan.run()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    queued = reps * njobs / (ev0.elapsed_time(ev1) / 1e3)
+    qexact = all(torch.equal(j[7], r[0]) and torch.equal(j[8], r[1]) for j, r in zip(jobs, ref))
+    qplan.close()
+    # one stream, no graph: every stage one launch per kernel variant over all cells
+    for j in jobs:
+        j[7].zero_()
+        j[8].zero_()
+    eplan = fhe.BatchPlan(ctx, jobs, flags=fhe.PLAN_QUEUE | fhe.PLAN_AUTOTUNE)
+    einfo = eplan.info()
+    ev0.record(stream)
+    for _ in range(reps):
+        eplan.run()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    eager_q = reps * njobs / (ev0.elapsed_time(ev1) / 1e3)
+    eexact = all(torch.equal(j[7], r[0]) and torch.equal(j[8], r[1]) for j, r in zip(jobs, ref))
+    eplan.close()
     out = {"jobs": njobs, "cells": info["cells"], "kernels_per_run": info["kernels"], "graphed": info["graphed"],
            "plan_seconds": plan_s, "he_mults_per_s": batched, "per_op_he_mults_per_s": perop,
            "speedup_vs_per_op": batched / perop, "bit_exact_vs_per_op": bool(exact),
+           "stage_batched_graph": {"he_mults_per_s": queued, "kernels_per_run": qinfo["kernels"],
+                                   "plan_seconds": qplan_s, "speedup_vs_per_op": queued / perop,
+                                   "bit_exact_vs_per_op": bool(qexact),
+                                   "layout": "cells on up to 4 graph branches, each branch stage-batched"},
+           "stage_batched_one_stream": {"he_mults_per_s": eager_q, "kernels_per_run": einfo["kernels"],
+                                        "speedup_vs_per_op": eager_q / perop, "bit_exact_vs_per_op": bool(eexact),
+                                        "layout": "every stage one launch per kernel variant over all cells, "
+                                                  "no graph"},
            "workload": "CKKS, logN ~ U{13..16}, logq ~ U{218,438,874,1555}, rescale 40, one key per N at "
                        "logQ = logP = 1555 (seed 4000)"}
-    plan.close()
     for k in keys.values():
         k.close()
     ctx.close()

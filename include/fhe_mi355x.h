@@ -417,6 +417,7 @@ typedef struct {
 
 #define FHE_PLAN_GRAPH 1    /* capture the whole batch in one hipGraph */
 #define FHE_PLAN_AUTOTUNE 2 /* time launch-parameter candidates per cell at plan time */
+#define FHE_PLAN_QUEUE 4    /* stage-batched: each pipeline stage as one launch over all cells */
 
 /* Build a plan for `njobs` jobs (host array, read during the call).  Jobs are grouped
  * into cells of equal (key, logq, bits); each cell runs as one CipherTensor pipeline
@@ -424,7 +425,14 @@ typedef struct {
  * owns its scratch memory, the prepared key levels it needs, and (FHE_PLAN_GRAPH)
  * an instantiated hipGraph in which the cells run on up to 4 concurrent branches,
  * each with its own scratch (so a graphed plan holds up to 4 cells' scratch at once,
- * against 1 for an eager plan).  Planning prepares keys and, with FHE_PLAN_AUTOTUNE, runs
+ * against 1 for an eager plan).  With FHE_PLAN_QUEUE the cells instead run stage by
+ * stage: each stage of the pipeline (lift, transforms, products, reconstruction,
+ * composition) is one launch per kernel variant whose workgroups are drawn from a
+ * device table of (cell, workgroup) units over every cell using that variant, so a
+ * batch takes about as many launches as one cell; every cell then holds scratch of its
+ * own.  With FHE_PLAN_GRAPH as well, the cells are spread over the same branches as
+ * above and each branch's cells run stage-batched on it.  Planning prepares keys
+ * and, with FHE_PLAN_AUTOTUNE, runs
  * every cell a few times on `stream` (writing the outputs); it synchronizes.  The
  * job buffers must stay valid for the plan's lifetime.  Errors: FHE_E_INVAL,
  * FHE_E_SHAPE, FHE_E_RANGE, FHE_E_NOMEM, FHE_E_DEVICE. */

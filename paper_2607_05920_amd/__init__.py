@@ -87,6 +87,7 @@ EXPORTS = {
 
 PLAN_GRAPH = 1
 PLAN_AUTOTUNE = 2
+PLAN_QUEUE = 4
 NTT_INVERSE = 1
 NTT_BITREV = 2
 

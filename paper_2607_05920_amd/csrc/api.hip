@@ -290,9 +290,27 @@ struct PlanCell {
 // fill the device) overlap.
 constexpr int kPlanBranches = 4;
 
+// One launch of a stage-batched plan: a kernel variant's stage-batched entry point over
+// the cells whose pipeline step uses that variant at this stage.
+struct QueueLaunch {
+  const void* multi = nullptr;
+  unsigned blocks = 0;  // workgroups: the cells' grids, each rounded up to 8
+  dim3 block;
+  size_t lds = 0;       // dynamic LDS: the largest of the cells'
+  void* args = nullptr;      // device: the cells' argument structs
+  CellSeg* seg = nullptr;    // device: their segments
+  int ncells = 0;
+  int branch = 0;            // graph branch of its cells
+};
+
 struct fhe_plan {
   fhe_ctx* ctx = nullptr;
   std::vector<PlanCell> cells;
+  // stage-batched (FHE_PLAN_QUEUE): the launches in order, each cell's own scratch, and
+  // the one device buffer holding every launch's argument structs and segments
+  std::vector<QueueLaunch> queue;
+  std::vector<uint32_t*> cws;
+  void* qmem = nullptr;
   std::vector<int> branch;         // per cell: its graph branch
   uint32_t* ws = nullptr;          // scratch of eager runs and of branch 0
   uint32_t* bws[kPlanBranches] = {nullptr, nullptr, nullptr, nullptr};  // scratch of branches 1..
@@ -964,6 +982,134 @@ int plan_run_cells(fhe_plan* pl, hipStream_t st) {
 
 // Autotuner: times each candidate launch configuration of one cell (one warm-up, then
 // the median of three runs) and keeps the fastest.
+// Stage-batched plan: each cell's pipeline is recorded (a LaunchSink: nothing runs),
+// every cell with scratch of its own; then step s of every cell's pipeline, which is
+// the same stage of the same pipeline for all cells, becomes one launch per kernel
+// variant (template instance and workgroup) over the cells that use it, in order of
+// first appearance.  A launch's workgroups are the cells' grids laid end to end, each
+// rounded up to a multiple of 8 workgroups so that every workgroup keeps the XCD its
+// own launch would give it (the kernels' prime-to-XCD assignment).
+int plan_build_queue(fhe_plan* pl, hipStream_t st) {
+  fhe_ctx* c = pl->ctx;
+  const size_t nc = pl->cells.size();
+  pl->cws.assign(nc, nullptr);
+  std::vector<std::vector<LaunchRec>> recs(nc);
+  for (size_t ci = 0; ci < nc; ++ci) {
+    PlanCell& cell = pl->cells[ci];
+    const PipeSize z = pipe_size(c, cell.evk, cell.logN, cell.logq, cell.cnum);
+    hipError_t e = hipMalloc((void**)&pl->cws[ci], (size_t)std::max(z.main_words, 1LL) * 4);
+    if (e != hipSuccess) return set_sticky(c, e);
+    PipeIO io;
+    io.ins = cell.ptrs;
+    io.outs = cell.ptrs + 4LL * cell.cnum;
+    LaunchSink sink;
+    set_launch_sink(&sink);
+    const int rc = pipeline(c, cell.evk, cell.logN, cell.logq, cell.bits, io, cell.cnum, st, pl->cws[ci], cell.tune);
+    set_launch_sink(nullptr);
+    if (rc != FHE_OK) return rc;
+    recs[ci] = std::move(sink.recs);
+    if (recs[ci].size() != recs[0].size()) return FHE_E_STATE;  // every pipeline has the same steps
+  }
+  // host image of the device buffer: argument structs and segments, 256-byte aligned
+  std::vector<char> img;
+  auto put = [&](const void* p, size_t n) {
+    const size_t at = (img.size() + 255) & ~(size_t)255;
+    img.resize(at + n);
+    memcpy(img.data() + at, p, n);
+    return at;
+  };
+  struct Pending {
+    QueueLaunch q;
+    size_t args_at = 0, seg_at = 0;
+  };
+  std::vector<Pending> pend;
+  std::map<const void*, size_t> lds_need;
+  const size_t nsteps = nc ? recs[0].size() : 0;
+  for (size_t s = 0; s < nsteps; ++s) {
+    std::vector<int> done(nc, 0);
+    for (size_t c0 = 0; c0 < nc; ++c0) {
+      if (done[c0]) continue;
+      const LaunchRec& r0 = recs[c0][s];
+      std::vector<char> args;
+      std::vector<CellSeg> segs;
+      Pending pd;
+      uint32_t off = 0;
+      for (size_t ci = c0; ci < nc; ++ci) {
+        const LaunchRec& r = recs[ci][s];
+        if (done[ci] || pl->branch[ci] != pl->branch[c0] || r.multi != r0.multi || r.block.x != r0.block.x ||
+            r.block.y != r0.block.y)
+          continue;
+        if (r.args.size() != r0.args.size() || r.grid.z != 1 || r.block.z != r0.block.z) return FHE_E_STATE;
+        done[ci] = 1;
+        CellSeg sg;
+        sg.off = off;
+        sg.gx = r.grid.x;
+        sg.gy = r.grid.y;
+        const unsigned long long span = ((unsigned long long)r.grid.x * r.grid.y + 7) & ~7ull;
+        if (off + span > 0x7FFFFFFFull) return FHE_E_RANGE;
+        off += (uint32_t)span;
+        segs.push_back(sg);
+        args.insert(args.end(), r.args.begin(), r.args.end());
+        pd.q.lds = std::max(pd.q.lds, r.lds);
+      }
+      pd.q.multi = r0.multi;
+      pd.q.branch = pl->branch[c0];
+      pd.q.block = r0.block;
+      pd.q.blocks = off;
+      pd.q.ncells = (int)segs.size();
+      pd.args_at = put(args.data(), args.size());
+      pd.seg_at = put(segs.data(), segs.size() * sizeof(CellSeg));
+      if (pd.q.lds) lds_need[pd.q.multi] = std::max(lds_need[pd.q.multi], pd.q.lds);
+      pend.push_back(pd);
+    }
+  }
+  hipError_t e = hipSuccess;
+  for (const auto& kv : lds_need)  // dynamic LDS beyond the default for these entry points
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(kv.first, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kv.second);
+  if (e == hipSuccess && !img.empty()) e = hipMalloc(&pl->qmem, img.size());
+  if (e == hipSuccess && !img.empty()) e = hipMemcpy(pl->qmem, img.data(), img.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return set_sticky(c, e);
+  for (Pending& pd : pend) {
+    pd.q.args = (char*)pl->qmem + pd.args_at;
+    pd.q.seg = (CellSeg*)((char*)pl->qmem + pd.seg_at);
+    pl->queue.push_back(pd.q);
+  }
+  return FHE_OK;
+}
+
+// The launches of `branch` (all of them for branch -1), in order, on st.
+int plan_run_queue(fhe_plan* pl, hipStream_t st, int branch = -1) {
+  for (QueueLaunch& q : pl->queue) {
+    if (branch >= 0 && q.branch != branch) continue;
+    void* kargs[] = {(void*)&q.args, (void*)&q.seg, (void*)&q.ncells};
+    hipError_t e = hipLaunchKernel(q.multi, dim3(q.blocks), q.block, kargs, q.lds, st);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return set_sticky(pl->ctx, e);
+  }
+  return FHE_OK;
+}
+
+// Under capture on pl->cap: each graph branch's launches on its own stream, forked from
+// and joined back into the capture stream, as for a plan of cell pipelines.
+int plan_capture_queue(fhe_plan* pl) {
+  hipError_t e = hipEventRecord(pl->fork, pl->cap);
+  for (int b = 1; b < kPlanBranches && e == hipSuccess; ++b)
+    if (pl->bst[b]) e = hipStreamWaitEvent(pl->bst[b], pl->fork, 0);
+  if (e != hipSuccess) return set_sticky(pl->ctx, e);
+  for (int b = 0; b < kPlanBranches; ++b) {
+    if (b > 0 && !pl->bst[b]) continue;
+    const int rc = plan_run_queue(pl, b ? pl->bst[b] : pl->cap, b);
+    if (rc != FHE_OK) return rc;
+  }
+  for (int b = 1; b < kPlanBranches && e == hipSuccess; ++b)
+    if (pl->bst[b]) {
+      e = hipEventRecord(pl->join[b], pl->bst[b]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(pl->cap, pl->join[b], 0);
+    }
+  return e == hipSuccess ? FHE_OK : set_sticky(pl->ctx, e);
+}
+
 int plan_autotune(fhe_plan* pl, PlanCell& cell, hipStream_t st) {
   fhe_ctx* c = pl->ctx;
   const PipeSize z = pipe_size(c, cell.evk, cell.logN, cell.logq, cell.cnum);
@@ -1042,7 +1188,9 @@ void plan_free(fhe_plan* pl) {
   if (pl->fork) hipEventDestroy(pl->fork);
   for (PlanCell& cell : pl->cells)
     if (cell.ptrs) hipFree(cell.ptrs);
-  for (void* p : {(void*)pl->ws})
+  for (uint32_t* w : pl->cws)
+    if (w) hipFree(w);
+  for (void* p : {(void*)pl->ws, pl->qmem})
     if (p) hipFree(p);
   delete pl;
 }
@@ -1829,7 +1977,7 @@ int fhe_mul_relin_rescale(fhe_ctx* c, fhe_evk* k, int logN, int logq, int bits, 
 }
 
 int fhe_batch_plan(fhe_ctx* c, const fhe_job* jobs, int njobs, int flags, void* stream, fhe_plan** out) {
-  if (!c || !out || njobs < 0 || (njobs > 0 && !jobs) || (flags & ~(FHE_PLAN_GRAPH | FHE_PLAN_AUTOTUNE)))
+  if (!c || !out || njobs < 0 || (njobs > 0 && !jobs) || (flags & ~(FHE_PLAN_GRAPH | FHE_PLAN_AUTOTUNE | FHE_PLAN_QUEUE)))
     return FHE_E_INVAL;
   *out = nullptr;
   for (int i = 0; i < njobs; ++i) {
@@ -1908,6 +2056,7 @@ int fhe_batch_plan(fhe_ctx* c, const fhe_job* jobs, int njobs, int flags, void* 
   // graph branches: cells by decreasing scratch size (a proxy for their work), each to
   // the branch with the least so far; branches 1.. get scratch for their largest cell
   pl->branch.assign(pl->cells.size(), 0);
+  const bool queue = (flags & FHE_PLAN_QUEUE) != 0;
   if (rc == FHE_OK && (flags & FHE_PLAN_GRAPH)) {
     std::vector<long long> words(pl->cells.size());
     std::vector<int> order(pl->cells.size());
@@ -1929,7 +2078,8 @@ int fhe_batch_plan(fhe_ctx* c, const fhe_job* jobs, int njobs, int flags, void* 
     hipError_t e = hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming);
     for (int b = 1; b < kPlanBranches && e == hipSuccess; ++b) {
       if (need[b] == 0) continue;  // an empty branch
-      e = hipMalloc((void**)&pl->bws[b], (size_t)need[b] * 4);
+      // a stage-batched plan gives every cell scratch of its own instead
+      if (!queue) e = hipMalloc((void**)&pl->bws[b], (size_t)need[b] * 4);
       if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->bst[b], hipStreamNonBlocking);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->join[b], hipEventDisableTiming);
     }
@@ -1940,7 +2090,26 @@ int fhe_batch_plan(fhe_ctx* c, const fhe_job* jobs, int njobs, int flags, void* 
     for (PlanCell& cell : pl->cells)
       if ((rc = plan_autotune(pl, cell, st)) != FHE_OK) break;
   }
-  if (rc == FHE_OK) {
+  if (rc == FHE_OK && queue) {
+    set_recorder(nullptr);
+    rc = plan_build_queue(pl, st);
+    if (rc == FHE_OK && (flags & FHE_PLAN_GRAPH)) {
+      hipError_t e = hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        rc = plan_capture_queue(pl);
+        hipGraph_t gr = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(pl->cap, &gr);
+        pl->graph = gr;
+        if (rc == FHE_OK && e2 != hipSuccess) e = e2;
+      }
+      if (rc == FHE_OK && e == hipSuccess) e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
+      if (rc == FHE_OK && e != hipSuccess) rc = set_sticky(c, e);
+    } else if (rc == FHE_OK) {
+      rc = plan_run_queue(pl, st);  // the first execution, as for an eager plan
+    }
+    pl->kernels = (int)pl->queue.size();
+  } else if (rc == FHE_OK) {
     const long long k0 = kernel_launch_count();
     set_recorder(nullptr);
     if (flags & FHE_PLAN_GRAPH) {
@@ -1982,6 +2151,7 @@ int fhe_batch_run(fhe_plan* pl, void* stream) {
   if (c->sticky != FHE_OK) return c->sticky;
   hipSetDevice(c->device);
   if (pl->exec) return set_sticky(c, hipGraphLaunch(pl->exec, (hipStream_t)stream));
+  if (!pl->queue.empty()) return plan_run_queue(pl, (hipStream_t)stream);
   RecGuard rg(c);
   return plan_run_cells(pl, (hipStream_t)stream);
 }

@@ -201,6 +201,28 @@ void bracket_end(int kid, hipStream_t s, double work);
 
 // Brackets one kernel launch with the recorder's events; `work` is the kernel's
 // algorithmic HBM bytes (what it must read and write at least once).
+// One cell's segment of a stage-batched launch (see LaunchSink): its first workgroup
+// (a multiple of 8) and the grid gx x gy of the cell's own launch.
+struct CellSeg {
+  uint32_t off = 0, gx = 0, gy = 0, pad = 0;
+};
+
+// A launch as recorded instead of issued while a sink is installed: the entry point
+// that runs it as one cell of a stage-batched launch, its grid, workgroup, dynamic LDS
+// and argument struct (raw bytes; every entry point takes one struct).
+struct LaunchRec {
+  const void* multi = nullptr;
+  dim3 grid, block;
+  size_t lds = 0;
+  std::vector<char> args;
+};
+struct LaunchSink {
+  std::vector<LaunchRec> recs;
+};
+// While a sink is installed on this thread, the pipeline launchers append to it and
+// launch nothing.
+void set_launch_sink(LaunchSink* s);
+
 struct Bracket {
   int kid;
   hipStream_t s;

@@ -105,6 +105,28 @@ static thread_local long long g_launches = 0;
 void set_recorder(EventRecorder* r) { g_rec = r; }
 long long kernel_launch_count() { return g_launches; }
 
+static thread_local LaunchSink* g_sink = nullptr;
+void set_launch_sink(LaunchSink* s) { g_sink = s; }
+
+// Issues a launch of `single` (one struct argument), or records it with its
+// stage-batched entry point `multi` while a sink is installed.
+template <typename A>
+static hipError_t emit(const void* single, const void* multi, dim3 grid, dim3 block, size_t lds, hipStream_t st,
+                       const A& a) {
+  if (g_sink) {
+    LaunchRec r;
+    r.multi = multi;
+    r.grid = grid;
+    r.block = block;
+    r.lds = lds;
+    r.args.assign((const char*)&a, (const char*)&a + sizeof(A));
+    g_sink->recs.push_back(std::move(r));
+    return hipSuccess;
+  }
+  void* args[] = {(void*)&a};
+  return hipLaunchKernel(single, grid, block, args, lds, st);
+}
+
 void bracket_begin(int kid, hipStream_t s) {
   ++g_launches;
   if (g_rec) g_rec->begin(kid, s);
@@ -128,6 +150,34 @@ void bracket_end(int kid, hipStream_t s, double work) {
 // register phase works on elements {u T + j} ("strided"), the other on
 // {16 j + u} ("contiguous"); one LDS exchange connects them.  Forward passes run
 // strided then contiguous; inverse passes the reverse.
+
+// Workgroup coordinates within one launch's grid.  A kernel body takes them as an
+// argument, so that it runs either as its own launch (own_blk) or as one cell's
+// segment of a stage-batched launch over many cells (cell_of).
+struct Blk {
+  uint32_t x, y, nx;  // block index (x, y) and the grid's width in x
+};
+
+__device__ __forceinline__ Blk own_blk() { return Blk{blockIdx.x, blockIdx.y, gridDim.x}; }
+
+// The cell that workgroup blockIdx.x of a stage-batched launch belongs to: seg[c].off
+// (ascending, multiples of 8, so that a workgroup's XCD, blockIdx.x mod 8, is the one
+// its own launch would give it) is the first workgroup of cell c, whose own grid is
+// gx x gy.  Workgroups past a cell's grid (the rounding to 8) take -1 and exit.
+__device__ __forceinline__ int cell_of(const CellSeg* seg, int ncells, Blk& bk) {
+  const uint32_t w = blockIdx.x;
+  int lo = 0, hi = ncells;  // the last cell with off <= w
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (seg[mid].off <= w) lo = mid;
+    else hi = mid;
+  }
+  const CellSeg sg = seg[lo];
+  const uint32_t l = w - sg.off;
+  if (l >= sg.gx * sg.gy) return -1;
+  bk = Blk{l % sg.gx, l / sg.gx, sg.gx};
+  return lo;
+}
 
 // Low 32 bits of a b + c in one v_mad_u64_u32 (the compiler would otherwise narrow
 // the expression to a 32-bit multiply and an add).
@@ -170,8 +220,8 @@ constexpr int ntt_pass_threads() { return ROWS ? 256 : (S >= 8 ? 1024 : (S == 7 
 
 // BLK: threads per workgroup (the autotuner may take fewer columns per workgroup than
 // ntt_pass_threads gives).
-template <int S, bool INV, bool ROWS, int BLK = ntt_pass_threads<S, ROWS>()>
-__global__ __launch_bounds__(BLK) void ntt_pass_kernel(NttArgs a) {
+template <int S, bool INV, bool ROWS, int BLK>
+__device__ __forceinline__ void ntt_pass_kernel_body(const NttArgs& a, const Blk bk) {
   constexpr int n = 1 << S;
   constexpr int T = n / 16;
   constexpr int NSUB = BLK / T;
@@ -195,7 +245,7 @@ __global__ __launch_bounds__(BLK) void ntt_pass_kernel(NttArgs a) {
   const int nwg = (nsub_total + NSUB - 1) / NSUB;  // workgroups per transform
   const int npp = a.ntr / a.K;                     // transforms per prime
   const int kx = (a.K + 7) >> 3;                   // primes per XCD (the largest share)
-  const int w = blockIdx.x, xcd = w & 7, l = w >> 3;
+  const int w = bk.x, xcd = w & 7, l = w >> 3;
   constexpr bool BY_TRANSFORM = !INV && !ROWS;
   const int p = (BY_TRANSFORM ? (l / nwg) % kx : l / (npp * nwg)) * 8 + xcd;
   if (p >= a.K) return;  // whole workgroup exits (primes not a multiple of 8)
@@ -323,6 +373,19 @@ __global__ __launch_bounds__(BLK) void ntt_pass_kernel(NttArgs a) {
 #pragma unroll
     for (int u = 0; u < 16; ++u) __builtin_amdgcn_raw_buffer_store_b32(x[u], rb, (int)o_str, (int)(u * T * es), 0);
   }
+}
+
+template <int S, bool INV, bool ROWS, int BLK = ntt_pass_threads<S, ROWS>()>
+__global__ __launch_bounds__(BLK) void ntt_pass_kernel(NttArgs a) { ntt_pass_kernel_body<S, INV, ROWS, BLK>(a, own_blk()); }
+
+// The same over the cells of a stage-batched plan: one launch, each workgroup in its
+// cell's segment (cell_of) with that cell's arguments.
+template <int S, bool INV, bool ROWS, int BLK>
+__global__ __launch_bounds__(BLK) void ntt_pass_kernel_multi(const NttArgs* __restrict__ cells, const CellSeg* __restrict__ seg, int ncells) {
+  Blk bk;
+  const int c = cell_of(seg, ncells, bk);
+  if (c < 0) return;
+  ntt_pass_kernel_body<S, INV, ROWS, BLK>(cells[c], bk);
 }
 
 // ---------------------------------------------------------------------------- fused row pass
@@ -530,8 +593,7 @@ struct RowsShape {
 // twiddles are wave-uniform (scalar loads) and, in the relinearization form, one wave
 // instruction reads a key row once for four ciphertexts.
 template <int S, int MODE, int CG>
-__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 : 2))) void rows_fused_kernel(
-    RowsArgs a) {
+__device__ __forceinline__ void rows_fused_kernel_body(const RowsArgs& a, const Blk bk) {
   constexpr int n = RowsShape<S>::n, T = RowsShape<S>::T, NSUB = RowsShape<S>::NSUB, SS = RowsShape<S>::SS;
   // the relinearization form exchanges one row at a time through one buffer: half the
   // LDS, so that its registers (below 100) and not the LDS bound its waves per SIMD
@@ -556,7 +618,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 
   const int nwg = (nsub_total + RPW - 1) / RPW;
   const int ncg = (a.cnum + CG - 1) / CG;
   const int per_prime = ncg * nwg;
-  const int w = blockIdx.x, xcd = w & 7, l = w >> 3;
+  const int w = bk.x, xcd = w & 7, l = w >> 3;
   const int p = (((a.K + 7) >> 3) - 1 - l / per_prime) * 8 + xcd;
   if (p >= a.K) return;  // whole workgroup exits
   const int rem = l % per_prime;
@@ -636,13 +698,19 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 
     if (HOIST) load_inv_tw<S>(wi, itw, tw_mul, j);
     // the key rows are stored transposed (launch_row_transpose): thread j's element
     // 16 j + u sits at u T + j, so that these loads are coalesced
+    // all 32 key words issued together (left to the scheduler, they may be issued two
+    // at a time, each pair waited for before the next)
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const uint32_t b = __builtin_amdgcn_raw_buffer_load_b32(rk, (int)(lk + 4u * u * T), 0, 0);
-      const uint32_t ak = __builtin_amdgcn_raw_buffer_load_b32(rk, (int)(lk + 4u * u * T), (int)(4 * KN), 0);
+      k[0][u] = __builtin_amdgcn_raw_buffer_load_b32(rk, (int)(lk + 4u * u * T), 0, 0);
+      k[1][u] = __builtin_amdgcn_raw_buffer_load_b32(rk, (int)(lk + 4u * u * T), (int)(4 * KN), 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
       // x in [0, 2q), key canonical: products below 2 q^2, results in [0, 2q)
-      k[0][u] = redc_lazy(mad64(x[0][u], b, 0), q, qneg);
-      k[1][u] = redc_lazy(mad64(x[0][u], ak, 0), q, qneg);
+      k[0][u] = redc_lazy(mad64(x[0][u], k[0][u], 0), q, qneg);
+      k[1][u] = redc_lazy(mad64(x[0][u], k[1][u], 0), q, qneg);
     }
     slot_sync();  // every lane has read the forward exchange before it is overwritten
     uint32_t* const li[1] = {lb[0]};
@@ -678,6 +746,19 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 
 }
 
 template <int S, int MODE, int CG>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 : 2))) void rows_fused_kernel(RowsArgs a) { rows_fused_kernel_body<S, MODE, CG>(a, own_blk()); }
+
+// The same over the cells of a stage-batched plan: one launch, each workgroup in its
+// cell's segment (cell_of) with that cell's arguments.
+template <int S, int MODE, int CG>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 : 2))) void rows_fused_kernel_multi(const RowsArgs* __restrict__ cells, const CellSeg* __restrict__ seg, int ncells) {
+  Blk bk;
+  const int c = cell_of(seg, ncells, bk);
+  if (c < 0) return;
+  rows_fused_kernel_body<S, MODE, CG>(cells[c], bk);
+}
+
+template <int S, int MODE, int CG>
 static hipError_t rows_fused(const RowsArgs& a, hipStream_t st) {
   constexpr int n = 1 << S;
   constexpr int RPW = RowsShape<S>::NSUB / CG;
@@ -692,8 +773,9 @@ static hipError_t rows_fused(const RowsArgs& a, hipStream_t st) {
   const int b_rows = a.data2_stride ? std::min(a.data2_groups, a.cnum) : 1;
   const double rows = MODE == 0 ? 7.0 * a.cnum : (MODE == 1 ? 3.0 * a.cnum + 2.0 : 2.0 * a.cnum + b_rows);
   Bracket br(KID_ROWS_FUSED, st, 4.0 * rows * a.K * (double)(1 << a.logN));
-  hipLaunchKernelGGL((rows_fused_kernel<S, MODE, CG>), grid, dim3(128), 0, st, a);
-  return hipGetLastError();
+  const hipError_t e = emit((const void*)rows_fused_kernel<S, MODE, CG>, (const void*)rows_fused_kernel_multi<S, MODE, CG>,
+                             grid, dim3(128), 0, st, a);
+  return e != hipSuccess ? e : hipGetLastError();
 }
 
 // Bytes a workgroup's buffers span from their base: they must stay below the
@@ -734,7 +816,9 @@ static hipError_t ntt_pass(const NttArgs& a, int ntr, hipStream_t st) {
   // algorithmic HBM bytes: every element of every transform read and written once
   Bracket br(INV ? (ROWS ? KID_NTT_INV_ROWS : KID_NTT_INV_COLS) : (ROWS ? KID_NTT_FWD_ROWS : KID_NTT_FWD_COLS), st,
              8.0 * ntr * (double)(1 << a.logN));
-  hipLaunchKernelGGL((ntt_pass_kernel<S, INV, ROWS, BLK>), grid, dim3(BLK), 0, st, a);
+  const hipError_t e = emit((const void*)ntt_pass_kernel<S, INV, ROWS, BLK>,
+                             (const void*)ntt_pass_kernel_multi<S, INV, ROWS, BLK>, grid, dim3(BLK), 0, st, a);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
@@ -848,13 +932,13 @@ __device__ __forceinline__ const uint32_t* lift_source(const LiftArgs& a, uint32
 }
 
 template <int PB>
-__global__ __launch_bounds__(256) void lift_kernel(LiftArgs a) {
+__device__ __forceinline__ void lift_kernel_body(const LiftArgs& a, const Blk bk) {
   // Workgroup w runs on XCD w % 8.  The prime groups of one (polynomial,
   // coefficient block) unit are consecutive workgroups of one XCD, so the unit's
   // limbs are read from HBM once and then from that XCD's L2.
   const int G = (a.K + PB - 1) / PB;
   const int nb = (a.N + 255) / 256;
-  const int w = blockIdx.x, xcd = w & 7, l = w >> 3;
+  const int w = bk.x, xcd = w & 7, l = w >> 3;
   const int unit = (l / G) * 8 + xcd;
   if (unit >= nb * a.npoly) return;
   const int p0 = (l % G) * PB;
@@ -902,11 +986,24 @@ __global__ __launch_bounds__(256) void lift_kernel(LiftArgs a) {
 }
 
 template <int PB>
+__global__ __launch_bounds__(256) void lift_kernel(LiftArgs a) { lift_kernel_body<PB>(a, own_blk()); }
+
+// The same over the cells of a stage-batched plan: one launch, each workgroup in its
+// cell's segment (cell_of) with that cell's arguments.
+template <int PB>
+__global__ __launch_bounds__(256) void lift_kernel_multi(const LiftArgs* __restrict__ cells, const CellSeg* __restrict__ seg, int ncells) {
+  Blk bk;
+  const int c = cell_of(seg, ncells, bk);
+  if (c < 0) return;
+  lift_kernel_body<PB>(cells[c], bk);
+}
+
+template <int PB>
 static void lift_launch(const LiftArgs& b, int npoly, hipStream_t st) {
   const int G = (b.K + PB - 1) / PB;
   const int units = ((b.N + 255) / 256) * npoly;
   dim3 grid(8 * ((units + 7) / 8) * G);
-  hipLaunchKernelGGL((lift_kernel<PB>), grid, dim3(256), 0, st, b);
+  (void)emit((const void*)lift_kernel<PB>, (const void*)lift_kernel_multi<PB>, grid, dim3(256), 0, st, b);
 }
 
 // The same projection on the i8 matrix cores.  A limb's four bytes minus 128 are
@@ -922,7 +1019,7 @@ static void lift_launch(const LiftArgs& b, int npoly, hipStream_t st) {
 // Workgroups are persistent: each wave takes groups of 32 coefficients in turn.
 // With LDSA the A table is staged once per workgroup in LDS (else read from L2).
 template <int NKB, bool LDSA, int BLK>
-__global__ __launch_bounds__(BLK) void lift_mfma_kernel(LiftArgs a) {
+__device__ __forceinline__ void lift_mfma_kernel_body(const LiftArgs& a, const Blk bk) {
   extern __shared__ v4i sA[];
   __shared__ uint32_t s_q[kCrtMaxPrimes], s_qn[kCrtMaxPrimes], s_olo[kCrtMaxPrimes], s_ohi[kCrtMaxPrimes];
   const int nfrag = a.ntiles * NKB * 64;
@@ -948,7 +1045,7 @@ __global__ __launch_bounds__(BLK) void lift_mfma_kernel(LiftArgs a) {
   const uint32_t total = (uint32_t)a.npoly << lg;
   const uint32_t row = 4u * (uint32_t)a.N;          // bytes between limb (or residue) rows
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  for (uint32_t unit = blockIdx.x * (BLK / 64) + wave; unit < total; unit += gridDim.x * (BLK / 64)) {
+  for (uint32_t unit = bk.x * (BLK / 64) + wave; unit < total; unit += bk.nx * (BLK / 64)) {
     // row 4 h, column c of a 32-coefficient group; recomputed per unit (opaque), or the
     // row offsets derived from it are hoisted out of the loop, each holding a register
     uint32_t lane_off = 4u * h * row + 4u * c;
@@ -997,6 +1094,19 @@ __global__ __launch_bounds__(BLK) void lift_mfma_kernel(LiftArgs a) {
   }
 }
 
+template <int NKB, bool LDSA, int BLK>
+__global__ __launch_bounds__(BLK) void lift_mfma_kernel(LiftArgs a) { lift_mfma_kernel_body<NKB, LDSA, BLK>(a, own_blk()); }
+
+// The same over the cells of a stage-batched plan: one launch, each workgroup in its
+// cell's segment (cell_of) with that cell's arguments.
+template <int NKB, bool LDSA, int BLK>
+__global__ __launch_bounds__(BLK) void lift_mfma_kernel_multi(const LiftArgs* __restrict__ cells, const CellSeg* __restrict__ seg, int ncells) {
+  Blk bk;
+  const int c = cell_of(seg, ncells, bk);
+  if (c < 0) return;
+  lift_mfma_kernel_body<NKB, LDSA, BLK>(cells[c], bk);
+}
+
 // Persistent grid: enough workgroups to fill the chip, no more than the work needs.
 static unsigned persistent_grid(long long units, int waves_per_block, int blocks_per_cu, int cus) {
   const long long need = (units + waves_per_block - 1) / waves_per_block;
@@ -1014,11 +1124,11 @@ static void lift_mfma_launch(const LiftArgs& b, hipStream_t st) {
       attr = hipFuncSetAttribute((const void*)lift_mfma_kernel<NKB, true, 768>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                  b.lds_max - (int)lds_static) == hipSuccess;
-    hipLaunchKernelGGL((lift_mfma_kernel<NKB, true, 768>), dim3(persistent_grid(units, 12, 1, b.cus)), dim3(768),
-                       lds, st, b);
+    (void)emit((const void*)lift_mfma_kernel<NKB, true, 768>, (const void*)lift_mfma_kernel_multi<NKB, true, 768>,
+               dim3(persistent_grid(units, 12, 1, b.cus)), dim3(768), lds, st, b);
   } else {
-    hipLaunchKernelGGL((lift_mfma_kernel<NKB, false, 256>), dim3(persistent_grid(units, 4, 8, b.cus)), dim3(256), 0,
-                       st, b);
+    (void)emit((const void*)lift_mfma_kernel<NKB, false, 256>, (const void*)lift_mfma_kernel_multi<NKB, false, 256>,
+               dim3(persistent_grid(units, 4, 8, b.cus)), dim3(256), 0, st, b);
   }
 }
 
@@ -1109,7 +1219,7 @@ template <int NKB>
 constexpr int crt_waves() { return NKB <= 4 ? 12 : 8; }
 
 template <int NKB, bool LDSA>
-__global__ __launch_bounds__(64 * crt_waves<NKB>()) void crt_kernel(CrtArgs a) {
+__device__ __forceinline__ void crt_kernel_body(const CrtArgs& a, const Blk bk) {
   constexpr int kCrtWaves = crt_waves<NKB>();
   extern __shared__ v4i sA[];
   __shared__ uint32_t s_q[32 * NKB], s_d[32 * NKB], s_r[32 * NKB];
@@ -1135,7 +1245,7 @@ __global__ __launch_bounds__(64 * crt_waves<NKB>()) void crt_kernel(CrtArgs a) {
   // the waves sharing a SIMD start apart, so that one's loads overlap another's products
   if (wave >= 4) __builtin_amdgcn_s_sleep(63);
   if (wave >= 8) __builtin_amdgcn_s_sleep(63);
-  for (uint32_t unit = blockIdx.x * kCrtWaves + wave; unit < total; unit += gridDim.x * kCrtWaves) {
+  for (uint32_t unit = bk.x * kCrtWaves + wave; unit < total; unit += bk.nx * kCrtWaves) {
   const uint32_t z = unit >> lg, j0 = (unit & ((1u << lg) - 1u)) << 5;
   const uint32_t row = 4u * (uint32_t)a.N;  // bytes between residue (or limb) rows
   const uint32_t* xb = wave_uniform(a.res + (long long)(z / a.per_group) * a.gstride +
@@ -1294,6 +1404,19 @@ __global__ __launch_bounds__(64 * crt_waves<NKB>()) void crt_kernel(CrtArgs a) {
   }
 }
 
+template <int NKB, bool LDSA>
+__global__ __launch_bounds__(64 * crt_waves<NKB>()) void crt_kernel(CrtArgs a) { crt_kernel_body<NKB, LDSA>(a, own_blk()); }
+
+// The same over the cells of a stage-batched plan: one launch, each workgroup in its
+// cell's segment (cell_of) with that cell's arguments.
+template <int NKB, bool LDSA>
+__global__ __launch_bounds__(64 * crt_waves<NKB>()) void crt_kernel_multi(const CrtArgs* __restrict__ cells, const CellSeg* __restrict__ seg, int ncells) {
+  Blk bk;
+  const int c = cell_of(seg, ncells, bk);
+  if (c < 0) return;
+  crt_kernel_body<NKB, LDSA>(cells[c], bk);
+}
+
 template <int NKB>
 static void crt_launch(const CrtArgs& a, hipStream_t st) {
   constexpr int kCrtWaves = crt_waves<NKB>();
@@ -1306,9 +1429,11 @@ static void crt_launch(const CrtArgs& a, hipStream_t st) {
     if (!attr)
       attr = hipFuncSetAttribute((const void*)crt_kernel<NKB, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  a.lds_max - (int)lds_static) == hipSuccess;
-    hipLaunchKernelGGL((crt_kernel<NKB, true>), dim3(grid), dim3(64 * kCrtWaves), lds, st, a);
+    (void)emit((const void*)crt_kernel<NKB, true>, (const void*)crt_kernel_multi<NKB, true>, dim3(grid),
+               dim3(64 * kCrtWaves), lds, st, a);
   } else {
-    hipLaunchKernelGGL((crt_kernel<NKB, false>), dim3(grid), dim3(64 * kCrtWaves), 0, st, a);
+    (void)emit((const void*)crt_kernel<NKB, false>, (const void*)crt_kernel_multi<NKB, false>, dim3(grid),
+               dim3(64 * kCrtWaves), 0, st, a);
   }
 }
 
@@ -1359,9 +1484,9 @@ __device__ __forceinline__ int64_t round_correction(const uint32_t* x, long long
   return (2 * rr > t) ? (int64_t)rr - (int64_t)t : (int64_t)rr;
 }
 
-__global__ __launch_bounds__(256) void compose_kernel(ComposeArgs a) {
-  const int jc = blockIdx.x * 256 + threadIdx.x;
-  const int z = blockIdx.y;  // 2 c + i
+__device__ __forceinline__ void compose_kernel_body(const ComposeArgs& a, const Blk bk) {
+  const int jc = bk.x * 256 + threadIdx.x;
+  const int z = bk.y;  // 2 c + i
   if (jc >= a.N) return;
   const int c = z >> 1, i = z & 1;
   const uint32_t* k = a.k + (long long)z * a.kstride + jc;
@@ -1387,14 +1512,25 @@ __global__ __launch_bounds__(256) void compose_kernel(ComposeArgs a) {
   }
 }
 
+__global__ __launch_bounds__(256) void compose_kernel(ComposeArgs a) { compose_kernel_body(a, own_blk()); }
+
+// The same over the cells of a stage-batched plan: one launch, each workgroup in its
+// cell's segment (cell_of) with that cell's arguments.
+__global__ __launch_bounds__(256) void compose_kernel_multi(const ComposeArgs* __restrict__ cells, const CellSeg* __restrict__ seg, int ncells) {
+  Blk bk;
+  const int c = cell_of(seg, ncells, bk);
+  if (c < 0) return;
+  compose_kernel_body(cells[c], bk);
+}
+
 // compose and rescale in one pass (a HE-mult with rescale): c = [d + R_P(k)]_(2^logq)
 // is produced limb by limb and never stored; the rescale's correction is collected
 // from its low limbs as they appear (the round bit, or (c mod 2^bits) mod t), and
 // output limb m of [R_B(c)]_(2^(logq - bits)) is emitted once c limbs sb + m and
 // sb + m + 1 exist (sb = bits / 32).
-__global__ __launch_bounds__(256) void compose_rescale_kernel(ComposeArgs a) {
-  const int jc = blockIdx.x * 256 + threadIdx.x;
-  const int z = blockIdx.y;  // 2 c + i
+__device__ __forceinline__ void compose_rescale_kernel_body(const ComposeArgs& a, const Blk bk) {
+  const int jc = bk.x * 256 + threadIdx.x;
+  const int z = bk.y;  // 2 c + i
   if (jc >= a.N) return;
   const int c = z >> 1, i = z & 1;
   const uint32_t* k = a.k + (long long)z * a.kstride + jc;
@@ -1460,6 +1596,17 @@ __global__ __launch_bounds__(256) void compose_rescale_kernel(ComposeArgs a) {
   if (m >= 0 && m < Lout) emit(m, rb ? (cprev >> rb) : cprev);
 }
 
+__global__ __launch_bounds__(256) void compose_rescale_kernel(ComposeArgs a) { compose_rescale_kernel_body(a, own_blk()); }
+
+// The same over the cells of a stage-batched plan: one launch, each workgroup in its
+// cell's segment (cell_of) with that cell's arguments.
+__global__ __launch_bounds__(256) void compose_rescale_kernel_multi(const ComposeArgs* __restrict__ cells, const CellSeg* __restrict__ seg, int ncells) {
+  Blk bk;
+  const int c = cell_of(seg, ncells, bk);
+  if (c < 0) return;
+  compose_rescale_kernel_body(cells[c], bk);
+}
+
 __global__ __launch_bounds__(256) void rescale_kernel(RescaleArgs a) {
   const int jc = blockIdx.x * 256 + threadIdx.x;
   const int z = blockIdx.y;
@@ -1493,8 +1640,8 @@ __global__ __launch_bounds__(256) void rescale_kernel(RescaleArgs a) {
 hipError_t launch_compose(const ComposeArgs& a, int cnum, hipStream_t st) {
   dim3 grid((a.N + 255) / 256, 2 * cnum);
   Bracket br(KID_COMPOSE, st, 8.0 * cnum * a.N * (double)(a.LK + 2 * a.L));  // bytes: k_i, d_i in, c_i out
-  hipLaunchKernelGGL(compose_kernel, grid, dim3(256), 0, st, a);
-  return hipGetLastError();
+  const hipError_t e = emit((const void*)compose_kernel, (const void*)compose_kernel_multi, grid, dim3(256), 0, st, a);
+  return e != hipSuccess ? e : hipGetLastError();
 }
 
 hipError_t launch_compose_rescale(const ComposeArgs& a, int cnum, hipStream_t st) {
@@ -1502,8 +1649,9 @@ hipError_t launch_compose_rescale(const ComposeArgs& a, int cnum, hipStream_t st
   // bytes: k_i and d_i in, the rescaled c_i out
   Bracket br(KID_COMPOSE_RESCALE, st,
              8.0 * cnum * a.N * (double)(a.LK + a.L + ((a.logq - a.bits + 31) >> 5)));
-  hipLaunchKernelGGL(compose_rescale_kernel, grid, dim3(256), 0, st, a);
-  return hipGetLastError();
+  const hipError_t e =
+      emit((const void*)compose_rescale_kernel, (const void*)compose_rescale_kernel_multi, grid, dim3(256), 0, st, a);
+  return e != hipSuccess ? e : hipGetLastError();
 }
 
 hipError_t launch_rescale(const RescaleArgs& a, int cnum, hipStream_t st) {

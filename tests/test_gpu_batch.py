@@ -1,5 +1,6 @@
 """GPU: batched uneven HE-mults (fhe_batch_plan / fhe_batch_run) against per-op calls
-and the oracle, eager and graph-captured, with the autotuner on and off."""
+and the oracle: cell pipelines and stage-batched launches (FHE_PLAN_QUEUE), eager and
+graph-captured, with the autotuner on and off."""
 import numpy as np
 import pytest
 
@@ -57,7 +58,9 @@ def per_op(ctx, jobs):
     return res
 
 
-@pytest.mark.parametrize("flags", [0, fhe.PLAN_GRAPH, fhe.PLAN_GRAPH | fhe.PLAN_AUTOTUNE])
+@pytest.mark.parametrize("flags", [0, fhe.PLAN_GRAPH, fhe.PLAN_GRAPH | fhe.PLAN_AUTOTUNE, fhe.PLAN_QUEUE,
+                                   fhe.PLAN_QUEUE | fhe.PLAN_GRAPH,
+                                   fhe.PLAN_QUEUE | fhe.PLAN_GRAPH | fhe.PLAN_AUTOTUNE])
 def test_batch_equals_per_op(setup, flags):
     import torch
     ctx, keys, khost, jobs, data = setup
@@ -69,6 +72,10 @@ def test_batch_equals_per_op(setup, flags):
     plan = fhe.BatchPlan(ctx, jobs, flags=flags)
     info = plan.info()
     assert info["cells"] == 8 and info["graphed"] == bool(flags & fhe.PLAN_GRAPH)
+    if flags & fhe.PLAN_QUEUE:
+        # 11 pipeline steps, each one launch per kernel variant in use: far fewer than
+        # the 8 cells' 88 launches
+        assert 11 <= info["kernels"] < 8 * 11, info
     for rep in range(3):
         for j in jobs:           # eager work between replays
             j[7].fill_(rep + 1)
@@ -80,11 +87,15 @@ def test_batch_equals_per_op(setup, flags):
     plan.close()
 
 
-def test_batch_sampled_jobs_match_oracle(setup):
+@pytest.mark.parametrize("flags", [fhe.PLAN_GRAPH, fhe.PLAN_QUEUE | fhe.PLAN_GRAPH])
+def test_batch_sampled_jobs_match_oracle(setup, flags):
     import torch
     ctx, keys, khost, jobs, data = setup
-    say("batch vs oracle")
-    plan = fhe.BatchPlan(ctx, jobs, flags=fhe.PLAN_GRAPH)
+    say(f"batch vs oracle flags={flags}")
+    for j in jobs:
+        j[7].zero_()
+        j[8].zero_()
+    plan = fhe.BatchPlan(ctx, jobs, flags=flags)
     plan.run()
     torch.cuda.synchronize()
     for i in (0, 5):   # (13, 218) and (14, 218): full oracle products are cheap
