@@ -1026,15 +1026,22 @@ int plan_build_queue(fhe_plan* pl, hipStream_t st) {
   std::map<const void*, size_t> lds_need;
   const size_t nsteps = nc ? recs[0].size() : 0;
   for (size_t s = 0; s < nsteps; ++s) {
+    // cells in reverse order every other step: a step then starts on the cells whose
+    // data the step before wrote last (still in the last-level cache), as the kernels
+    // themselves do within a cell
+    std::vector<size_t> ord(nc);
+    for (size_t i = 0; i < nc; ++i) ord[i] = (s & 1) ? nc - 1 - i : i;
     std::vector<int> done(nc, 0);
-    for (size_t c0 = 0; c0 < nc; ++c0) {
+    for (size_t i0 = 0; i0 < nc; ++i0) {
+      const size_t c0 = ord[i0];
       if (done[c0]) continue;
       const LaunchRec& r0 = recs[c0][s];
       std::vector<char> args;
       std::vector<CellSeg> segs;
       Pending pd;
       uint32_t off = 0;
-      for (size_t ci = c0; ci < nc; ++ci) {
+      for (size_t i = i0; i < nc; ++i) {
+        const size_t ci = ord[i];
         const LaunchRec& r = recs[ci][s];
         if (done[ci] || pl->branch[ci] != pl->branch[c0] || r.multi != r0.multi || r.block.x != r0.block.x ||
             r.block.y != r0.block.y)
