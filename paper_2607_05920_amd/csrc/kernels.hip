@@ -322,11 +322,29 @@ __device__ __forceinline__ void ntt_pass_kernel_body(const NttArgs& a, const Blk
 #pragma unroll
       for (int u = 0; u < 16; ++u) x[u] = csub(csub(x[u], two_q), q);
     }
+    if (ROWS) {  // a lane's 16 consecutive words: four 16-byte stores
 #pragma unroll
-    for (int u = 0; u < 16; ++u) __builtin_amdgcn_raw_buffer_store_b32(x[u], rb, (int)o_con, (int)(u * es), 0);
+      for (int v = 0; v < 4; ++v)
+        __builtin_amdgcn_raw_buffer_store_b128(v4i_t{(int)x[4 * v], (int)x[4 * v + 1], (int)x[4 * v + 2], (int)x[4 * v + 3]},
+                                               rb, (int)o_con, 16 * v, 0);
+    } else {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) __builtin_amdgcn_raw_buffer_store_b32(x[u], rb, (int)o_con, (int)(u * es), 0);
+    }
   } else {
+    if (ROWS) {  // a lane's 16 consecutive words: four 16-byte loads
 #pragma unroll
-    for (int u = 0; u < 16; ++u) x[u] = __builtin_amdgcn_raw_buffer_load_b32(rb, (int)o_con, (int)(u * es), 0);
+      for (int v = 0; v < 4; ++v) {
+        const v4i_t w = __builtin_amdgcn_raw_buffer_load_b128(rb, (int)o_con, 16 * v, 0);
+        x[4 * v] = (uint32_t)w[0];
+        x[4 * v + 1] = (uint32_t)w[1];
+        x[4 * v + 2] = (uint32_t)w[2];
+        x[4 * v + 3] = (uint32_t)w[3];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) x[u] = __builtin_amdgcn_raw_buffer_load_b32(rb, (int)o_con, (int)(u * es), 0);
+    }
     // contiguous stages: t = 1 .. T/2, h = n / (2t) groups
 #pragma unroll
     for (int t = 1; t < T; t <<= 1) {
