@@ -109,3 +109,70 @@ def test_batch_sampled_jobs_match_oracle(setup, flags):
         check(ints(host(jobs[i][7], (Lo, N))), want.c0, f"job {i} c0")
         check(ints(host(jobs[i][8], (Lo, N))), want.c1, f"job {i} c1")
     plan.close()
+
+
+def test_stage_batched_both_schemes_and_levels():
+    """Stage-batched plans (eager and graph) over CKKS and BGV cells at logN 13 and 14,
+    levels 218 and 438 under a key at 438, rescale 0, 7 and 40 bits: bit-identical to
+    per-op calls; one BGV job against the oracle on every coefficient."""
+    import torch
+    logQ = logP = 438
+    rk, rm, _, _ = synth.streams(21)
+    ctx = fhe.Context(logQ, logP)
+    try:
+        keys, khost = {}, {}
+        for sch, t in ((fhe.CKKS, 0), (fhe.BGV, 65537)):
+            for logN in (13, 14):
+                N = 1 << logN
+                eb = synth.uniform_limbs(rk, logQ + logP, N)
+                ea = synth.uniform_limbs(rk, logQ + logP, N)
+                keys[(sch, logN)] = fhe.EvalKey(ctx, sch, t, logN, logQ, logP, eb, ea)
+                khost[(sch, logN)] = (eb, ea)
+        shapes = [(fhe.CKKS, 13, 218, 40), (fhe.BGV, 14, 438, 7), (fhe.BGV, 13, 218, 0), (fhe.CKKS, 14, 438, 40),
+                  (fhe.BGV, 14, 438, 7), (fhe.CKKS, 13, 438, 0), (fhe.BGV, 13, 218, 0)]
+        jobs, data = [], []
+        for sch, logN, logq, bits in shapes:
+            N = 1 << logN
+            x = [synth.uniform_limbs(rm, logq, N) for _ in range(2)]
+            y = [synth.uniform_limbs(rm, logq, N) for _ in range(2)]
+            Lo = synth.nlimbs(logq - bits)
+            outs = [torch.zeros(Lo * N, dtype=torch.int32, device="cuda") for _ in range(2)]
+            jobs.append((keys[(sch, logN)], logq, bits, *[dev(v) for v in x + y], *outs))
+            data.append((sch, logN, logq, bits, x, y))
+        say("stage-batched both schemes: per-op reference")
+        ref = []
+        for (evk, logq, bits, x0, x1, y0, y1, o0, o1) in jobs:
+            a, b = torch.empty_like(o0), torch.empty_like(o1)
+            if bits:
+                ctx.mul_relin_rescale(evk, logq, bits, x0, x1, y0, y1, a, b)
+            else:
+                ctx.mul_relin(evk, logq, x0, x1, y0, y1, a, b)
+            ref.append((a, b))
+        torch.cuda.synchronize()
+        for flags in (fhe.PLAN_QUEUE, fhe.PLAN_QUEUE | fhe.PLAN_GRAPH):
+            say(f"stage-batched both schemes flags={flags}")
+            for j in jobs:
+                j[7].zero_()
+                j[8].zero_()
+            plan = fhe.BatchPlan(ctx, jobs, flags=flags)
+            assert plan.info()["cells"] == 5
+            for _ in range(2):
+                plan.run()
+                torch.cuda.synchronize()
+                for (j, (a, b)) in zip(jobs, ref):
+                    assert torch.equal(j[7], a) and torch.equal(j[8], b)
+            plan.close()
+        sch, logN, logq, bits, x, y = data[1]
+        N = 1 << logN
+        eb, ea = khost[(sch, logN)]
+        say("stage-batched both schemes: oracle, BGV job 1")
+        evk = scheme.EvalKey(ints(eb), ints(ea), logN, logQ, logP, scheme.BGV, 65537)
+        want = scheme.mult_rescale(oracle_ct(*x, logN, logq, scheme.BGV, 65537),
+                                   oracle_ct(*y, logN, logq, scheme.BGV, 65537), evk, bits)
+        Lo = synth.nlimbs(logq - bits)
+        check(ints(host(jobs[1][7], (Lo, N))), want.c0, "BGV job 1 c0")
+        check(ints(host(jobs[1][8], (Lo, N))), want.c1, "BGV job 1 c1")
+        for k in keys.values():
+            k.close()
+    finally:
+        ctx.close()
