@@ -619,7 +619,9 @@ __device__ __forceinline__ void rows_fused_kernel_body(const RowsArgs& a, const 
   static_assert(kRowsBuffers == 2, "the tensor and ring forms below pair their exchanges with 2 buffers");
   static_assert(CG == 1 || (CG == 4 && T * CG == 64 && MODE != 2), "four ciphertexts fill one wave");
   constexpr int RPW = NSUB / CG;  // sub-rows per workgroup
-  constexpr bool HOIST = CG > 1;   // twiddles loaded ahead (scalar registers for the strided stages)
+  // twiddles loaded ahead (scalar registers for the strided stages when CG > 1); the
+  // one-ciphertext relinearization form has the registers for them too
+  constexpr bool HOIST = CG > 1 || MODE == 1;
   __shared__ uint32_t lds[NB][NSUB * SS];
 
   const int tid = threadIdx.x;
