@@ -560,6 +560,22 @@ def main():
         torch.cuda.synchronize()
         extras["per_op_he_mults_per_s"] = cnum * steps1 / (ev0.elapsed_time(ev1) / 1e3)
         extras["batched_over_per_op"] = value / extras["per_op_he_mults_per_s"]
+        # the same step as a graph: a plan of the cnum pairs (one cell, the same kernels
+        # through pointer arrays) captured once and replayed
+        log("graph replay leg")
+        gjobs = [(evk, LOGQ, BITS, *singles[i], *so[i]) for i in range(cnum)]
+        gplan = fhe.BatchPlan(ctx, gjobs, flags=fhe.PLAN_GRAPH)
+        gplan.run()
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            gplan.run()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        gms = ev0.elapsed_time(ev1) / args.steps
+        extras["graph_replay"] = {"he_mults_per_s": cnum / (gms / 1e3), "ms_per_step": gms,
+                                  "kernels_per_step": gplan.info()["kernels"]}
+        gplan.close()
         # standalone NTT throughput: 64 polynomials of this size lifted to the tensor primes
         log("NTT leg")
         del xs, o0, o1, singles, so
