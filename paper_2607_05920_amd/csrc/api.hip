@@ -20,6 +20,7 @@
 
 #include "fhe_internal.h"
 #include "fhe_mi355x.h"
+#include "queue_layout.h"
 #include "srv_core.h"
 
 using namespace fhe;
@@ -984,11 +985,11 @@ int plan_run_cells(fhe_plan* pl, hipStream_t st) {
 // the median of three runs) and keeps the fastest.
 // Stage-batched plan: each cell's pipeline is recorded (a LaunchSink: nothing runs),
 // every cell with scratch of its own; then step s of every cell's pipeline, which is
-// the same stage of the same pipeline for all cells, becomes one launch per kernel
-// variant (template instance and workgroup) over the cells that use it, in order of
-// first appearance.  A launch's workgroups are the cells' grids laid end to end, each
-// rounded up to a multiple of 8 workgroups so that every workgroup keeps the XCD its
-// own launch would give it (the kernels' prime-to-XCD assignment).
+// the same stage of the same pipeline for all cells, becomes one launch per graph
+// branch and kernel variant (template instance and workgroup) over the cells that use
+// it (queue_layout.h: the grouping, the cells' order, and the segments, each cell's
+// grid rounded up to a multiple of 8 workgroups so that every workgroup keeps the XCD
+// its own launch would give it, the kernels' prime-to-XCD assignment).
 int plan_build_queue(fhe_plan* pl, hipStream_t st) {
   fhe_ctx* c = pl->ctx;
   const size_t nc = pl->cells.size();
@@ -1008,9 +1009,27 @@ int plan_build_queue(fhe_plan* pl, hipStream_t st) {
     set_launch_sink(nullptr);
     if (rc != FHE_OK) return rc;
     recs[ci] = std::move(sink.recs);
-    if (recs[ci].size() != recs[0].size()) return FHE_E_STATE;  // every pipeline has the same steps
   }
-  // host image of the device buffer: argument structs and segments, 256-byte aligned
+  // which cells go into which launch (queue_layout.h), then the host image of the
+  // device buffer: argument structs and segments, 256-byte aligned
+  std::vector<std::vector<QRec>> q(nc);
+  for (size_t ci = 0; ci < nc; ++ci)
+    for (const LaunchRec& r : recs[ci]) {
+      QRec x;
+      x.variant = r.multi;
+      x.bx = r.block.x;
+      x.by = r.block.y;
+      x.bz = r.block.z;
+      x.gx = r.grid.x;
+      x.gy = r.grid.y;
+      x.gz = r.grid.z;
+      x.arg_bytes = (uint32_t)r.args.size();
+      x.branch = pl->branch[ci];
+      q[ci].push_back(x);
+    }
+  std::vector<QLaunch> lay;
+  const int lr = queue_layout(q, &lay);
+  if (lr != QL_OK) return lr == QL_TOO_BIG ? FHE_E_RANGE : FHE_E_STATE;
   std::vector<char> img;
   auto put = [&](const void* p, size_t n) {
     const size_t at = (img.size() + 255) & ~(size_t)255;
@@ -1024,51 +1043,30 @@ int plan_build_queue(fhe_plan* pl, hipStream_t st) {
   };
   std::vector<Pending> pend;
   std::map<const void*, size_t> lds_need;
-  const size_t nsteps = nc ? recs[0].size() : 0;
-  for (size_t s = 0; s < nsteps; ++s) {
-    // cells in reverse order every other step: a step then starts on the cells whose
-    // data the step before wrote last (still in the last-level cache), as the kernels
-    // themselves do within a cell
-    std::vector<size_t> ord(nc);
-    for (size_t i = 0; i < nc; ++i) ord[i] = (s & 1) ? nc - 1 - i : i;
-    std::vector<int> done(nc, 0);
-    for (size_t i0 = 0; i0 < nc; ++i0) {
-      const size_t c0 = ord[i0];
-      if (done[c0]) continue;
-      const LaunchRec& r0 = recs[c0][s];
-      std::vector<char> args;
-      std::vector<CellSeg> segs;
-      Pending pd;
-      uint32_t off = 0;
-      for (size_t i = i0; i < nc; ++i) {
-        const size_t ci = ord[i];
-        const LaunchRec& r = recs[ci][s];
-        if (done[ci] || pl->branch[ci] != pl->branch[c0] || r.multi != r0.multi || r.block.x != r0.block.x ||
-            r.block.y != r0.block.y)
-          continue;
-        if (r.args.size() != r0.args.size() || r.grid.z != 1 || r.block.z != r0.block.z) return FHE_E_STATE;
-        done[ci] = 1;
-        CellSeg sg;
-        sg.off = off;
-        sg.gx = r.grid.x;
-        sg.gy = r.grid.y;
-        const unsigned long long span = ((unsigned long long)r.grid.x * r.grid.y + 7) & ~7ull;
-        if (off + span > 0x7FFFFFFFull) return FHE_E_RANGE;
-        off += (uint32_t)span;
-        segs.push_back(sg);
-        args.insert(args.end(), r.args.begin(), r.args.end());
-        pd.q.lds = std::max(pd.q.lds, r.lds);
-      }
-      pd.q.multi = r0.multi;
-      pd.q.branch = pl->branch[c0];
-      pd.q.block = r0.block;
-      pd.q.blocks = off;
-      pd.q.ncells = (int)segs.size();
-      pd.args_at = put(args.data(), args.size());
-      pd.seg_at = put(segs.data(), segs.size() * sizeof(CellSeg));
-      if (pd.q.lds) lds_need[pd.q.multi] = std::max(lds_need[pd.q.multi], pd.q.lds);
-      pend.push_back(pd);
+  for (const QLaunch& L : lay) {
+    std::vector<char> args;
+    std::vector<CellSeg> segs;
+    Pending pd;
+    for (const QSeg& g : L.segs) {
+      const LaunchRec& r = recs[g.cell][L.step];
+      CellSeg sg;
+      sg.off = g.off;
+      sg.gx = g.gx;
+      sg.gy = g.gy;
+      segs.push_back(sg);
+      args.insert(args.end(), r.args.begin(), r.args.end());
+      pd.q.lds = std::max(pd.q.lds, r.lds);
     }
+    const LaunchRec& r0 = recs[L.segs[0].cell][L.step];
+    pd.q.multi = L.variant;
+    pd.q.branch = L.branch;
+    pd.q.block = r0.block;
+    pd.q.blocks = L.blocks;
+    pd.q.ncells = (int)segs.size();
+    pd.args_at = put(args.data(), args.size());
+    pd.seg_at = put(segs.data(), segs.size() * sizeof(CellSeg));
+    if (pd.q.lds) lds_need[pd.q.multi] = std::max(lds_need[pd.q.multi], pd.q.lds);
+    pend.push_back(pd);
   }
   hipError_t e = hipSuccess;
   for (const auto& kv : lds_need)  // dynamic LDS beyond the default for these entry points
