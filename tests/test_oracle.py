@@ -363,3 +363,22 @@ def test_samplers():
     assert abs(np.mean(v == 0) - 0.5) < 0.01
     z = synth.unit_disk(rng, 1000)
     assert np.all(np.abs(z) <= 1.0)
+
+
+def test_relinearization_hand_example():
+    """R3 pinned: the hand-worked N = 2 relinearization of the golden fixture (d2 taken in
+    [0, Q_l)), both schemes; the centered representative of d2 gives another c0."""
+    g = GOLD["relin"]
+    N = 1 << g["logN"]
+    assert len(g["d2"]) == N
+    for sch, t, want in ((scheme.CKKS, 0, g["ckks"]), (scheme.BGV, 17, g["bgv_t17"])):
+        evk = scheme.EvalKey(g["evk_b"], g["evk_a"], g["logN"], g["logq"], g["logP"], sch, t)
+        c0, c1 = scheme.relinearize(g["d0"], g["d1"], g["d2"], evk, g["logq"], sch, t)
+        assert c0 == want["c0"] and c1 == want["c1"], (sch, c0, c1)
+    # the other representative choice changes the output bits
+    Q = 1 << g["logq"]
+    centered = [v - Q if v >= Q // 2 else v for v in g["d2"]]
+    PQ = 1 << (g["logP"] + g["logq"])
+    k0 = ring.ring_mul(centered, [b % PQ for b in g["evk_b"]], PQ)
+    c0 = [(g["d0"][i] + scheme.divide_round(k0[i], g["logP"], scheme.CKKS, 0)) % Q for i in range(N)]
+    assert c0 == g["ckks_if_d2_centered"]["c0"] != g["ckks"]["c0"]
