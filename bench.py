@@ -272,6 +272,77 @@ def batched_uneven(fhe, torch, synth, dev, stream, njobs):
     return out
 
 
+def op_latency_leg(fhe, torch, synth, dev, stream, reps=10):
+    """Latency of each homomorphic operation of the paper's operation table at its
+    parameters (a CipherTensor of cnum = 4 ciphertexts, logN = 16, logQ = 1024, scale
+    2^60; CKKS), through the fhe_ct entry points: the CipherTensor latency and the
+    amortized latency per ciphertext, with the paper's Tesla T4 figures beside them as
+    context (another machine, another implementation).  Inputs and keys are uniform
+    synthetic limbs; moddownBy and rescaleBy take 60 bits, leftrotate one slot,
+    multconstvec one plaintext per ciphertext, the broadcast forms one shared operand.
+    Bootstrapping is the separate leg (its own parameters)."""
+    logN, logQ, logP, logp, cnum = 16, 1024, 1024, 60, 4
+    N, L = 1 << logN, synth.nlimbs(logQ)
+    rk, rm, _, _ = synth.streams(8)
+    ctx = fhe.Context(logQ, logP)
+
+    def key(g=0):
+        return fhe.EvalKey(ctx, fhe.CKKS, 0, logN, logQ, logP, synth.uniform_limbs(rk, logQ + logP, N),
+                           synth.uniform_limbs(rk, logQ + logP, N), g=g)
+
+    relin, rot1, conj = key(), key(pow(5, 1, 2 * N)), key(2 * N - 1)
+
+    def ct():
+        c0 = fhe.to_device(synth.uniform_limbs(rm, logQ, N, count=cnum)).reshape(-1)
+        c1 = fhe.to_device(synth.uniform_limbs(rm, logQ, N, count=cnum)).reshape(-1)
+        return fhe.Ciphertext(c0, c1, logN, logQ, logp, fhe.CKKS, 0, 1, cnum)
+
+    x, y = ct(), ct()
+    pv = fhe.to_device(synth.uniform_limbs(rm, logQ, N, count=cnum)).reshape(-1)   # one plaintext per ciphertext
+    p1 = fhe.to_device(synth.uniform_limbs(rm, logQ, N, count=1)).reshape(-1)      # one shared plaintext
+    out = (torch.empty(cnum * L * N, dtype=torch.int32, device=dev), torch.empty(cnum * L * N, dtype=torch.int32,
+                                                                                  device=dev))
+    kconst = (1 << 59) + 12345
+    ops = {
+        "negate_pairwise_into": lambda: ctx.ct_negate(x, out),
+        "moddownBy_pairwise_into": lambda: ctx.ct_moddown(x, 60, out),
+        "rescaleBy_pairwise_into": lambda: ctx.ct_rescale(x, 60, out),
+        "conjugate_pairwise_into": lambda: ctx.ct_conjugate(conj, x, out),
+        "mult_pairwise_into": lambda: ctx.ct_mul_relin(relin, x, y, out),
+        "leftrotate_broadcast_into": lambda: ctx.ct_leftrotate(rot1, 1, x, out),
+        "add_pairwise_into": lambda: ctx.ct_add(x, y, out),
+        "sub_pairwise_into": lambda: ctx.ct_sub(x, y, out),
+        "addconst_broadcast_into": lambda: ctx.ct_addconst(x, p1, 1, out),
+        "addconst_pairwise_into": lambda: ctx.ct_addconst(x, pv, cnum, out),
+        "imult_pairwise_into": lambda: ctx.ct_imult(x, out),
+        "multconst_broadcast_into": lambda: ctx.ct_multconst(x, kconst, out, logp_k=logp),
+        "multconstvec_pairwise_into": lambda: ctx.ct_multconstvec(x, pv, cnum, out, logp_m=logp),
+    }
+    paper_t4 = {"negate_pairwise_into": 0.0191, "moddownBy_pairwise_into": 0.0131, "rescaleBy_pairwise_into": 0.0770,
+                "conjugate_pairwise_into": 5.5614, "mult_pairwise_into": 8.1862,
+                "leftrotate_broadcast_into": 5.6852, "add_pairwise_into": 0.0286, "sub_pairwise_into": 0.0260,
+                "addconst_broadcast_into": 0.0007, "addconst_pairwise_into": 0.0170,
+                "imult_pairwise_into": 0.0170, "multconst_broadcast_into": 0.6219,
+                "multconstvec_pairwise_into": 1.9930}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {}
+    for name, f in ops.items():
+        f()  # prepares key levels and tables
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(reps):
+            f()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        s_ = ev0.elapsed_time(ev1) / 1e3 / reps
+        res[name] = {"ciphertensor_s": s_, "per_ciphertext_s": s_ / cnum, "paper_t4_ciphertensor_s": paper_t4[name]}
+    for k in (relin, rot1, conj):
+        k.close()
+    ctx.close()
+    return {"ops": res, "workload": "CKKS CipherTensor of 4, logN = 16, logQ = logP = 1024, scale 2^60; "
+                                    "uniform synthetic ciphertexts and keys (seed 8000); mean of 10 calls after one"}
+
+
 def bootstrap_leg(fhe, torch, synth, dev, reps=3):
     """CKKS bootstrapping of one ciphertext at N = 2^16 with 4 slots (logs = 2), input at
     logq = 40 and scale 2^30 (the paper's bootstrapping setting), raised to logQ = 1024;
@@ -603,6 +674,8 @@ def main():
         extras["batched_uneven"] = batched_uneven(fhe, torch, synth, dev, stream, args.batch_jobs)
 
     if not args.no_extras and not args.no_boot:
+        log("operation latency leg")
+        extras["op_latency"] = op_latency_leg(fhe, torch, synth, dev, stream)
         log("bootstrapping leg")
         extras["bootstrap"] = bootstrap_leg(fhe, torch, synth, dev)
 
