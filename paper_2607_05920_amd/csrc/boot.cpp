@@ -47,11 +47,13 @@ class CtPool {
 class Boot {
  public:
   Boot(fhe_ctx* c, const fhe_boot_params& P, const fhe_boot_keys& K, void* st)
-      : c_(c), P_(P), K_(K), st_(st), half_((size_t)((P.logQ + 31) / 32) << P.logN), pool_(2 * half_) {}
+      : c_(c), P_(P), K_(K), st_(st), half_((size_t)((P.logQ + 31) / 32) << P.logN), pool_(4 * half_) {}
 
   int rc = FHE_OK;
 
-  // A ciphertext value owning one pool buffer (c0 at its start, c1 at half_).
+  // A ciphertext value owning one pool buffer, room for a CipherTensor of up to two at
+  // the top level: c0 at its start, c1 at 2 half_ (a CipherTensor's ciphertexts follow
+  // each other at its level's stride inside each).
   struct V {
     fhe_ct ct{};
     uint32_t* buf = nullptr;
@@ -62,8 +64,17 @@ class Boot {
     v.buf = pool_.get();
     if (!v.buf && rc == FHE_OK) rc = FHE_E_NOMEM;
     v.ct.c0 = v.buf;
-    v.ct.c1 = v.buf ? v.buf + half_ : nullptr;
+    v.ct.c1 = v.buf ? v.buf + 2 * half_ : nullptr;
     return v;
+  }
+  // ciphertext i of a CipherTensor value, as a one-ciphertext view (not owned)
+  fhe_ct part(const V& x, int i) const {
+    fhe_ct p = x.ct;
+    const size_t stride = (size_t)((x.ct.logq + 31) / 32) << P_.logN;
+    p.c0 = x.ct.c0 + i * stride;
+    p.c1 = x.ct.c1 + i * stride;
+    p.cnum = 1;
+    return p;
   }
   void drop(V& v) {
     pool_.put(v.buf);
@@ -278,26 +289,42 @@ class Boot {
     // B3
     V y = linear(x, K_.c2s);
     drop(x);
-    // B4
+    // B4: a and b written as the two ciphertexts of one CipherTensor, so that B5 runs
+    // once on both (every operation of EvalMod is pairwise or broadcast)
     V yc = conj(y);
-    V a = add(y, yc);
-    a.ct.logp += 1;
-    V d = add(yc, y, true);
-    V b = imult(d);
-    b.ct.logp += 1;
-    drop(d);
+    V ab = fresh();
+    if (ok()) {
+      fhe_ct a = part(ab, 0);
+      a.logq = y.ct.logq;  // the output level sets the stride of ciphertext 1 below
+      check(fhe_ct_add(c_, &y.ct, &yc.ct, &a, st_));
+      V d = add(yc, y, true);
+      fhe_ct b = a;
+      const size_t stride = (size_t)((a.logq + 31) / 32) << P_.logN;
+      b.c0 = ab.ct.c0 + stride;
+      b.c1 = ab.ct.c1 + stride;
+      if (ok()) check(fhe_ct_imult(c_, &d.ct, &b, st_));
+      drop(d);
+      ab.ct = a;
+      ab.ct.c0 = ab.buf;
+      ab.ct.c1 = ab.buf + 2 * half_;
+      ab.ct.cnum = 2;
+      ab.ct.logp += 1;  // the halving of both
+    }
     drop(y);
     drop(yc);
     // B5, B6
-    V sa = eval_mod(a);
-    drop(a);
-    V sb = eval_mod(b);
-    drop(b);
-    V isb = imult(sb);
-    drop(sb);
-    V w = add(sa, isb);
-    drop(sa);
-    drop(isb);
+    V sab = eval_mod(ab);
+    drop(ab);
+    V w;
+    if (ok()) {
+      const fhe_ct sa = part(sab, 0), sb = part(sab, 1);
+      V isb = fresh();
+      if (ok()) check(fhe_ct_imult(c_, &sb, &isb.ct, st_));
+      w = fresh();
+      if (ok()) check(fhe_ct_add(c_, &sa, &isb.ct, &w.ct, st_));
+      drop(isb);
+    }
+    drop(sab);
     // B7
     V z = linear(w, K_.s2c);
     drop(w);
