@@ -325,8 +325,8 @@ __device__ __forceinline__ void ntt_pass_kernel_body(const NttArgs& a, const Blk
     if (ROWS) {  // a lane's 16 consecutive words: four 16-byte stores
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        __builtin_amdgcn_raw_buffer_store_b128(v4i_t{(int)x[4 * v], (int)x[4 * v + 1], (int)x[4 * v + 2], (int)x[4 * v + 3]},
-                                               rb, (int)o_con, 16 * v, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(
+            v4i_t{(int)x[4 * v], (int)x[4 * v + 1], (int)x[4 * v + 2], (int)x[4 * v + 3]}, rb, (int)o_con, 16 * v, 0);
     } else {
 #pragma unroll
       for (int u = 0; u < 16; ++u) __builtin_amdgcn_raw_buffer_store_b32(x[u], rb, (int)o_con, (int)(u * es), 0);
@@ -394,12 +394,15 @@ __device__ __forceinline__ void ntt_pass_kernel_body(const NttArgs& a, const Blk
 }
 
 template <int S, bool INV, bool ROWS, int BLK = ntt_pass_threads<S, ROWS>()>
-__global__ __launch_bounds__(BLK) void ntt_pass_kernel(NttArgs a) { ntt_pass_kernel_body<S, INV, ROWS, BLK>(a, own_blk()); }
+__global__ __launch_bounds__(BLK) void ntt_pass_kernel(NttArgs a) {
+  ntt_pass_kernel_body<S, INV, ROWS, BLK>(a, own_blk());
+}
 
 // The same over the cells of a stage-batched plan: one launch, each workgroup in its
 // cell's segment (cell_of) with that cell's arguments.
 template <int S, bool INV, bool ROWS, int BLK>
-__global__ __launch_bounds__(BLK) void ntt_pass_kernel_multi(const NttArgs* __restrict__ cells, const CellSeg* __restrict__ seg, int ncells) {
+__global__ __launch_bounds__(BLK) void ntt_pass_kernel_multi(
+    const NttArgs* __restrict__ cells, const CellSeg* __restrict__ seg, int ncells) {
   Blk bk;
   const int c = cell_of(seg, ncells, bk);
   if (c < 0) return;
@@ -614,7 +617,7 @@ template <int S, int MODE, int CG>
 __device__ __forceinline__ void rows_fused_kernel_body(const RowsArgs& a, const Blk bk) {
   constexpr int n = RowsShape<S>::n, T = RowsShape<S>::T, NSUB = RowsShape<S>::NSUB, SS = RowsShape<S>::SS;
   // the relinearization form exchanges one row at a time through one buffer: half the
-  // LDS, so that its registers (below 100) and not the LDS bound its waves per SIMD
+  // LDS, so that its registers and not the LDS bound its waves per SIMD
   constexpr int NB = MODE == 1 ? 1 : kRowsBuffers;
   static_assert(kRowsBuffers == 2, "the tensor and ring forms below pair their exchanges with 2 buffers");
   static_assert(CG == 1 || (CG == 4 && T * CG == 64 && MODE != 2), "four ciphertexts fill one wave");
@@ -668,7 +671,8 @@ __device__ __forceinline__ void rows_fused_kernel_body(const RowsArgs& a, const 
 
   if (MODE == 0) {  // tensor, in place: slots 0..3 in, 0..2 out
     const __amdgpu_buffer_rsrc_t rs =
-        row_buffer(wave_uniform(a.data + (long long)c * a.group_stride + base), (uint32_t)((3 * KN + NSUB * n) * 4) + 4u * span);
+        row_buffer(wave_uniform(a.data + (long long)c * a.group_stride + base),
+                   (uint32_t)((3 * KN + NSUB * n) * 4) + 4u * span);
     uint32_t x[4][16];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -766,12 +770,16 @@ __device__ __forceinline__ void rows_fused_kernel_body(const RowsArgs& a, const 
 }
 
 template <int S, int MODE, int CG>
-__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 : 2))) void rows_fused_kernel(RowsArgs a) { rows_fused_kernel_body<S, MODE, CG>(a, own_blk()); }
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 : 2))) void rows_fused_kernel(
+    RowsArgs a) {
+  rows_fused_kernel_body<S, MODE, CG>(a, own_blk());
+}
 
 // The same over the cells of a stage-batched plan: one launch, each workgroup in its
 // cell's segment (cell_of) with that cell's arguments.
 template <int S, int MODE, int CG>
-__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 : 2))) void rows_fused_kernel_multi(const RowsArgs* __restrict__ cells, const CellSeg* __restrict__ seg, int ncells) {
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(S >= 6 ? 3 : 2))) void rows_fused_kernel_multi(
+    const RowsArgs* __restrict__ cells, const CellSeg* __restrict__ seg, int ncells) {
   Blk bk;
   const int c = cell_of(seg, ncells, bk);
   if (c < 0) return;
@@ -793,8 +801,8 @@ static hipError_t rows_fused(const RowsArgs& a, hipStream_t st) {
   const int b_rows = a.data2_stride ? std::min(a.data2_groups, a.cnum) : 1;
   const double rows = MODE == 0 ? 7.0 * a.cnum : (MODE == 1 ? 3.0 * a.cnum + 2.0 : 2.0 * a.cnum + b_rows);
   Bracket br(KID_ROWS_FUSED, st, 4.0 * rows * a.K * (double)(1 << a.logN));
-  const hipError_t e = emit((const void*)rows_fused_kernel<S, MODE, CG>, (const void*)rows_fused_kernel_multi<S, MODE, CG>,
-                             grid, dim3(128), 0, st, a);
+  const hipError_t e = emit((const void*)rows_fused_kernel<S, MODE, CG>,
+                            (const void*)rows_fused_kernel_multi<S, MODE, CG>, grid, dim3(128), 0, st, a);
   return e != hipSuccess ? e : hipGetLastError();
 }
 
@@ -860,7 +868,8 @@ static hipError_t ntt_pass_s(int S, const NttArgs& a, int ntr, hipStream_t st, i
 
 // dst[r n + u T + j] = src[r n + 16 j + u] within rows of n = 2^S words (T = n / 16):
 // a key in NTT form laid out in the order the fused relinearization pass holds it.
-__global__ __launch_bounds__(256) void row_transpose_kernel(const uint32_t* src, uint32_t* dst, long long total, int S) {
+__global__ __launch_bounds__(256) void row_transpose_kernel(
+    const uint32_t* src, uint32_t* dst, long long total, int S) {
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
   if (i >= total) return;
   const int n = 1 << S, T = n >> 4;
@@ -1011,7 +1020,8 @@ __global__ __launch_bounds__(256) void lift_kernel(LiftArgs a) { lift_kernel_bod
 // The same over the cells of a stage-batched plan: one launch, each workgroup in its
 // cell's segment (cell_of) with that cell's arguments.
 template <int PB>
-__global__ __launch_bounds__(256) void lift_kernel_multi(const LiftArgs* __restrict__ cells, const CellSeg* __restrict__ seg, int ncells) {
+__global__ __launch_bounds__(256) void lift_kernel_multi(
+    const LiftArgs* __restrict__ cells, const CellSeg* __restrict__ seg, int ncells) {
   Blk bk;
   const int c = cell_of(seg, ncells, bk);
   if (c < 0) return;
@@ -1115,12 +1125,15 @@ __device__ __forceinline__ void lift_mfma_kernel_body(const LiftArgs& a, const B
 }
 
 template <int NKB, bool LDSA, int BLK>
-__global__ __launch_bounds__(BLK) void lift_mfma_kernel(LiftArgs a) { lift_mfma_kernel_body<NKB, LDSA, BLK>(a, own_blk()); }
+__global__ __launch_bounds__(BLK) void lift_mfma_kernel(LiftArgs a) {
+  lift_mfma_kernel_body<NKB, LDSA, BLK>(a, own_blk());
+}
 
 // The same over the cells of a stage-batched plan: one launch, each workgroup in its
 // cell's segment (cell_of) with that cell's arguments.
 template <int NKB, bool LDSA, int BLK>
-__global__ __launch_bounds__(BLK) void lift_mfma_kernel_multi(const LiftArgs* __restrict__ cells, const CellSeg* __restrict__ seg, int ncells) {
+__global__ __launch_bounds__(BLK) void lift_mfma_kernel_multi(
+    const LiftArgs* __restrict__ cells, const CellSeg* __restrict__ seg, int ncells) {
   Blk bk;
   const int c = cell_of(seg, ncells, bk);
   if (c < 0) return;
@@ -1425,12 +1438,15 @@ __device__ __forceinline__ void crt_kernel_body(const CrtArgs& a, const Blk bk) 
 }
 
 template <int NKB, bool LDSA>
-__global__ __launch_bounds__(64 * crt_waves<NKB>()) void crt_kernel(CrtArgs a) { crt_kernel_body<NKB, LDSA>(a, own_blk()); }
+__global__ __launch_bounds__(64 * crt_waves<NKB>()) void crt_kernel(CrtArgs a) {
+  crt_kernel_body<NKB, LDSA>(a, own_blk());
+}
 
 // The same over the cells of a stage-batched plan: one launch, each workgroup in its
 // cell's segment (cell_of) with that cell's arguments.
 template <int NKB, bool LDSA>
-__global__ __launch_bounds__(64 * crt_waves<NKB>()) void crt_kernel_multi(const CrtArgs* __restrict__ cells, const CellSeg* __restrict__ seg, int ncells) {
+__global__ __launch_bounds__(64 * crt_waves<NKB>()) void crt_kernel_multi(
+    const CrtArgs* __restrict__ cells, const CellSeg* __restrict__ seg, int ncells) {
   Blk bk;
   const int c = cell_of(seg, ncells, bk);
   if (c < 0) return;
@@ -1536,7 +1552,8 @@ __global__ __launch_bounds__(256) void compose_kernel(ComposeArgs a) { compose_k
 
 // The same over the cells of a stage-batched plan: one launch, each workgroup in its
 // cell's segment (cell_of) with that cell's arguments.
-__global__ __launch_bounds__(256) void compose_kernel_multi(const ComposeArgs* __restrict__ cells, const CellSeg* __restrict__ seg, int ncells) {
+__global__ __launch_bounds__(256) void compose_kernel_multi(
+    const ComposeArgs* __restrict__ cells, const CellSeg* __restrict__ seg, int ncells) {
   Blk bk;
   const int c = cell_of(seg, ncells, bk);
   if (c < 0) return;
@@ -1616,11 +1633,14 @@ __device__ __forceinline__ void compose_rescale_kernel_body(const ComposeArgs& a
   if (m >= 0 && m < Lout) emit(m, rb ? (cprev >> rb) : cprev);
 }
 
-__global__ __launch_bounds__(256) void compose_rescale_kernel(ComposeArgs a) { compose_rescale_kernel_body(a, own_blk()); }
+__global__ __launch_bounds__(256) void compose_rescale_kernel(ComposeArgs a) {
+  compose_rescale_kernel_body(a, own_blk());
+}
 
 // The same over the cells of a stage-batched plan: one launch, each workgroup in its
 // cell's segment (cell_of) with that cell's arguments.
-__global__ __launch_bounds__(256) void compose_rescale_kernel_multi(const ComposeArgs* __restrict__ cells, const CellSeg* __restrict__ seg, int ncells) {
+__global__ __launch_bounds__(256) void compose_rescale_kernel_multi(
+    const ComposeArgs* __restrict__ cells, const CellSeg* __restrict__ seg, int ncells) {
   Blk bk;
   const int c = cell_of(seg, ncells, bk);
   if (c < 0) return;
