@@ -212,6 +212,31 @@ __device__ __forceinline__ void gs_bfly(uint32_t& X, uint32_t& Y, uint2 w, uint3
   Y = mad_lo(qh, 0u - q, d * w.x);
 }
 
+// Inverse twiddles from the forward table.  The bit-reversed index (over the table's
+// 16 bits) of 2H - 1 - i is 2^16 minus that of H + i (H a power of two, i < H), and
+// psi^(2^16) = -1, so psi^-bitrev(H + i) = -v for v = psi^bitrev(2H - 1 - i): for a
+// stage of H groups starting at table index mi H - H (mi the caller's mirrored
+// multiplier), group g's inverse twiddle is minus forward entry mi H - 1 - g.  That
+// entry holds (-v mod 2^32, floor(v 2^32 / q)); mirror_tw makes it the Shoup pair of v
+// (the negation opaque, else the compiler moves it into every butterfly), which
+// gs_bfly_neg takes.
+__device__ __forceinline__ uint2 mirror_tw(uint2 f) {
+  uint32_t v = 0u - f.x;
+  opaque(v);
+  return make_uint2(v, f.y);
+}
+
+// gs_bfly with the twiddle given as -v (the Shoup pair of v): (X - Y)(-v) = (Y - X) v,
+// the Shoup product of d = Y - X + 2q.
+__device__ __forceinline__ void gs_bfly_neg(uint32_t& X, uint32_t& Y, uint2 v, uint32_t q,
+                                            uint32_t two_q) {
+  const uint32_t x = X, y = Y;
+  X = csub(x + y, two_q);
+  const uint32_t d = y - x + two_q;
+  const uint32_t qh = __umulhi(d, v.y);
+  Y = mad_lo(qh, 0u - q, d * v.x);
+}
+
 // Threads per workgroup: column passes of 2^8 and 2^7 points take 64 columns of 1024
 // threads and 64 of 512 (256- and 128-byte runs per row); row passes, and column passes
 // of shorter transforms (fewer columns exist), take 256.
@@ -436,19 +461,22 @@ __device__ __forceinline__ void slot_sync() {
 // exchange's ordering points keep the compiler from moving loads across them, so the
 // loads are issued before (the strided stages' 15, wave-uniform when a wave holds one
 // sub-row, land in scalar registers; the contiguous stages' up to 15 per thread).
+// MIR: the inverse direction's come from the forward table (mirror_tw, applied where
+// they are used, so that the loads stay in flight until then).
 template <int S>
 struct RowTw {
   uint2 s[15];  // strided stages: stage st, group g at (1 << st) - 1 + g
   uint2 c[15];  // contiguous stages, in the order the stages run
 };
 
-template <int S, bool INV>
+// MIR (inverse only): tw is the forward table and tw_mul the mirrored multiplier.
+template <int S, bool INV, bool MIR = false>
 __device__ __forceinline__ void load_strided_tw(RowTw<S>& w, const uint2* tw, int tw_mul) {
 #pragma unroll
   for (int st = 0; st < 4; ++st) {
     const int m = INV ? (8 >> st) : (1 << st);
 #pragma unroll
-    for (int g = 0; g < m; ++g) w.s[m - 1 + g] = tw[tw_mul * m + g];
+    for (int g = 0; g < m; ++g) w.s[m - 1 + g] = tw[MIR ? tw_mul * m - 1 - g : tw_mul * m + g];
   }
 }
 
@@ -458,22 +486,39 @@ template <int S>
 __device__ constexpr int fwd_ci(int t, int b0) { return 8 / t - 256 / (1 << S) + b0 / (2 * t); }
 __device__ constexpr int inv_ci(int t, int b0) { return 16 - 16 / t + b0 / (2 * t); }
 
-template <int S, bool INV>
+template <int S, bool INV, bool MIR = false>
 __device__ __forceinline__ void load_contig_tw(RowTw<S>& w, const uint2* tw, int tw_mul, int j) {
   constexpr int n = 1 << S, T = n / 16;
 #pragma unroll
-  for (int t = 1; t < T; t <<= 1)
+  for (int t = 1; t < T; t <<= 1) {
+    const int cnt = 8 / t;  // this thread's twiddles of the stage: groups j cnt + k, k < cnt
+    if (!MIR) {
 #pragma unroll
-    for (int b0 = 0; b0 < 16; b0 += 2 * t)
-      w.c[INV ? inv_ci(t, b0) : fwd_ci<S>(t, b0)] = tw[tw_mul * (n / (2 * t)) + j * (8 / t) + b0 / (2 * t)];
+      for (int b0 = 0; b0 < 16; b0 += 2 * t)
+        w.c[INV ? inv_ci(t, b0) : fwd_ci<S>(t, b0)] = tw[tw_mul * (n / (2 * t)) + j * cnt + b0 / (2 * t)];
+    } else if (cnt == 1) {
+      w.c[inv_ci(t, 0)] = tw[tw_mul * (n / (2 * t)) - 1 - j];
+    } else {
+      // group j cnt + k is entry tw_mul h - 1 - j cnt - k: element cnt - 1 - k of the
+      // ascending block from tw_mul h - (j + 1) cnt, two entries per 16-byte load (h and
+      // cnt are even, so the block starts on a 16-byte boundary)
+      const uint4* blk = reinterpret_cast<const uint4*>(tw + tw_mul * (n / (2 * t)) - (j + 1) * cnt);
+#pragma unroll
+      for (int e = 0; e < cnt; e += 2) {
+        const uint4 v = blk[e / 2];
+        w.c[inv_ci(t, 2 * t * (cnt - 1 - e))] = make_uint2(v.x, v.y);
+        w.c[inv_ci(t, 2 * t * (cnt - 2 - e))] = make_uint2(v.z, v.w);
+      }
+    }
+  }
 }
 
 // The inverse direction's twiddles, issued at once (before the products that precede
-// their first use).
-template <int S>
+// their first use).  MIR: from the forward table at the mirrored multiplier.
+template <int S, bool MIR = false>
 __device__ __forceinline__ void load_inv_tw(RowTw<S>& w, const uint2* itw, int tw_mul, int j) {
-  load_contig_tw<S, true>(w, itw, tw_mul, j);
-  load_strided_tw<S, true>(w, itw, tw_mul);
+  load_contig_tw<S, true, MIR>(w, itw, tw_mul, j);
+  load_strided_tw<S, true, MIR>(w, itw, tw_mul);
   __builtin_amdgcn_sched_barrier(0);
 }
 
@@ -544,8 +589,9 @@ __device__ __forceinline__ void fwd_rows(uint32_t (&x)[NP][16], uint32_t* const 
 
 // First inverse n-point row stages of NP rows at once, values at e = 16 j + u in
 // [0, 2q); leaves values in [0, 2q) at e = u T + j for the caller to store.  HOIST: the
-// caller has loaded the twiddles into pre (load_inv_tw, before the products).
-template <int S, int NP, int NB, bool HOIST = false>
+// caller has loaded the twiddles into pre (load_inv_tw, before the products).  MIR: tw
+// is the forward table and tw_mul the mirrored multiplier (mirror_tw).
+template <int S, int NP, int NB, bool HOIST = false, bool MIR = false>
 __device__ __forceinline__ void inv_rows(uint32_t (&x)[NP][16], uint32_t* const (&l)[NB], int j, const uint2* tw,
                                          int tw_mul, uint32_t q, uint32_t two_q, RowTw<S>& pre) {
   constexpr int n = 1 << S, T = n / 16;
@@ -554,11 +600,16 @@ __device__ __forceinline__ void inv_rows(uint32_t (&x)[NP][16], uint32_t* const 
     const int h = n / (2 * t);
 #pragma unroll
     for (int b0 = 0; b0 < 16; b0 += 2 * t) {
-      const uint2 wg = HOIST ? pre.c[inv_ci(t, b0)] : tw[tw_mul * h + j * (8 / t) + b0 / (2 * t)];
+      const int g = j * (8 / t) + b0 / (2 * t);
+      const uint2 wf = HOIST ? pre.c[inv_ci(t, b0)] : tw[MIR ? tw_mul * h - 1 - g : tw_mul * h + g];
+      const uint2 wg = MIR ? mirror_tw(wf) : wf;
 #pragma unroll
       for (int r = 0; r < NP; ++r)
 #pragma unroll
-        for (int u = b0; u < b0 + t; ++u) gs_bfly(x[r][u], x[r][u + t], wg, q, two_q);
+        for (int u = b0; u < b0 + t; ++u) {
+          if (MIR) gs_bfly_neg(x[r][u], x[r][u + t], wg, q, two_q);
+          else gs_bfly(x[r][u], x[r][u + t], wg, q, two_q);
+        }
     }
   }
 #pragma unroll
@@ -585,11 +636,15 @@ __device__ __forceinline__ void inv_rows(uint32_t (&x)[NP][16], uint32_t* const 
     const int hd = 1 << st, h = 8 >> st;
 #pragma unroll
     for (int g = 0; g < h; ++g) {
-      const uint2 wg = HOIST ? pre.s[h - 1 + g] : tw[tw_mul * h + g];
+      const uint2 wf = HOIST ? pre.s[h - 1 + g] : tw[MIR ? tw_mul * h - 1 - g : tw_mul * h + g];
+      const uint2 wg = MIR ? mirror_tw(wf) : wf;
 #pragma unroll
       for (int r = 0; r < NP; ++r)
 #pragma unroll
-        for (int u = 2 * hd * g; u < 2 * hd * g + hd; ++u) gs_bfly(x[r][u], x[r][u + hd], wg, q, two_q);
+        for (int u = 2 * hd * g; u < 2 * hd * g + hd; ++u) {
+          if (MIR) gs_bfly_neg(x[r][u], x[r][u + hd], wg, q, two_q);
+          else gs_bfly(x[r][u], x[r][u + hd], wg, q, two_q);
+        }
     }
   }
 }
@@ -718,8 +773,12 @@ __device__ __forceinline__ void rows_fused_kernel_body(const RowsArgs& a, const 
     for (int u = 0; u < 16; ++u) x[0][u] = __builtin_amdgcn_raw_buffer_load_b32(ri, (int)(lane + 4u * u * T), 0, 0);
     uint32_t* const lf[1] = {lb[0]};
     fwd_rows<S, 1, 1, HOIST>(x, lf, j, tw, tw_mul, q, two_q);
+    // the inverse twiddles from the forward table (the tensor form, VALU-bound, keeps
+    // the inverse table and saves the conversion; this one saves the table's traffic)
+    const int mi = 2 * nsub_total - min(sg, nsub_total - 1);  // sg inside the transform
+    const int tw_mi = CG > 1 ? __builtin_amdgcn_readfirstlane(mi) : mi;
     RowTw<S> wi;
-    if (HOIST) load_inv_tw<S>(wi, itw, tw_mul, j);
+    if (HOIST) load_inv_tw<S, true>(wi, tw, tw_mi, j);
     // the key rows are stored transposed (launch_row_transpose): thread j's element
     // 16 j + u sits at u T + j, so that these loads are coalesced
     // all 32 key words issued together (left to the scheduler, they may be issued two
@@ -738,7 +797,7 @@ __device__ __forceinline__ void rows_fused_kernel_body(const RowsArgs& a, const 
     }
     slot_sync();  // every lane has read the forward exchange before it is overwritten
     uint32_t* const li[1] = {lb[0]};
-    inv_rows<S, 2, 1, HOIST>(k, li, j, itw, tw_mul, q, two_q, wi);
+    inv_rows<S, 2, 1, HOIST, true>(k, li, j, tw, tw_mi, q, two_q, wi);
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
