@@ -373,18 +373,26 @@ const std::vector<uint32_t>& crt_c(fhe_ctx* c, int K) {
   return c->crt_c[K] = std::move(v);
 }
 
+// The inverse transform's last-stage twiddle of prime k (inverse table entry 1):
+// psi_k^-bitrev(1) over the table's 16 bits, i.e. psi_k^-(2^15).
+uint64_t last_inv_twiddle(const fhe_ctx* c, int k) {
+  return powmod(invmod(c->psi[k], c->q[k]), 1ull << (kLogNMax - 1), c->q[k]);
+}
+
 // Final inverse-NTT factors [N^-1 2^32 c_k]_(q_k) (Shoup pairs) for transforms whose
 // output goes to a K-prime CRT reconstruction: 2^32 undoes the 2^-32 of the
-// Montgomery pointwise products, c_k is the CRT factor.
+// Montgomery pointwise products, c_k is the CRT factor.  Entries Kpad + k hold the
+// factor times the last stage's twiddle (NttArgs::scale_w).
 const uint2* crt_scale(fhe_ctx* c, int logN, int K, hipError_t* err) {
   auto it = c->cscale.find(std::make_pair(logN, K));
   if (it != c->cscale.end()) return it->second;
   const std::vector<uint32_t>& ck = crt_c(c, K);
-  std::vector<uint2> h(c->Kpad, make_uint2(0, 0));
+  std::vector<uint2> h(2 * (size_t)c->Kpad, make_uint2(0, 0));
   for (int k = 0; k < K; ++k) {
     const uint32_t q = c->q[k];
     const uint64_t f = mulmod64(mulmod64(invmod(1ull << logN, q), (1ull << 32) % q, q), ck[k], q);
     h[k] = shoup_pair((uint32_t)f, q);
+    h[c->Kpad + k] = shoup_pair((uint32_t)mulmod64(f, last_inv_twiddle(c, k), q), q);
   }
   uint2* d = nullptr;
   *err = upload(&d, h);
@@ -557,6 +565,7 @@ NttArgs ntt_args(fhe_ctx* c, uint32_t* data, int logN, int K, int per_group, lon
   a.tw = inverse ? c->itw : c->tw;
   a.pc = c->pc;
   a.scale = scale;
+  a.scale_w = scale ? scale + c->Kpad : nullptr;  // the tables hold both halves
   return a;
 }
 
@@ -1645,11 +1654,16 @@ int fhe_ctx_create(int device, int logQ_max, int logP_max, fhe_ctx** out) {
       }
     }
   }
-  // final inverse factors N^-1 per logN (standalone transforms)
+  // final inverse factors N^-1 per logN (standalone transforms), then the same times
+  // the last stage's twiddle (NttArgs::scale_w)
   std::vector<std::vector<uint2>> ns(kLogNMax + 1);
   for (int lg = FHE_LOGN_MIN; lg <= kLogNMax; ++lg) {
-    ns[lg].assign(Kpad, make_uint2(0, 0));
-    for (int p = 0; p < K; ++p) ns[lg][p] = shoup_pair((uint32_t)invmod(1ull << lg, c->q[p]), c->q[p]);
+    ns[lg].assign(2 * (size_t)Kpad, make_uint2(0, 0));
+    for (int p = 0; p < K; ++p) {
+      const uint64_t f = invmod(1ull << lg, c->q[p]);
+      ns[lg][p] = shoup_pair((uint32_t)f, c->q[p]);
+      ns[lg][Kpad + p] = shoup_pair((uint32_t)mulmod64(f, last_inv_twiddle(c, p), c->q[p]), c->q[p]);
+    }
   }
   // upload
   if ((e = upload(&c->pc, pc)) == hipSuccess && (e = upload(&c->tw, tw)) == hipSuccess &&

@@ -31,6 +31,8 @@ struct NttArgs {
   const PrimeC* pc = nullptr;
   const uint2* scale = nullptr; // inverse only: per-prime final factor (w, w'); null: the
                                 // inputs already carry it (only the canonical reduction)
+  const uint2* scale_w = nullptr; // with scale: the factor times the last stage's twiddle
+                                  // (table entry 1), folded into that stage
   int ntr = 0;         // number of transforms (set by launch_ntt; a multiple of K)
 };
 

@@ -392,10 +392,13 @@ __device__ __forceinline__ void ntt_pass_kernel_body(const NttArgs& a, const Blk
       const int e = u * T + j;
       x[u] = lrow[e + (e >> 4)];
     }
-    // strided stages: register distance hd = 1, 2, 4, 8; h = 8 / hd groups
+    // strided stages: register distance hd = 1, 2, 4, 8; h = 8 / hd groups.  The last
+    // inverse pass with a final factor takes its last stage below.
+    const bool fold = !ROWS && a.scale != nullptr;
 #pragma unroll
     for (int st = 0; st < 4; ++st) {
       const int hd = 1 << st, h = 8 >> st;
+      if (st == 3 && fold) break;
 #pragma unroll
       for (int g = 0; g < h; ++g) {
         const uint2 w = tw[tw_mul * h + g];
@@ -404,10 +407,16 @@ __device__ __forceinline__ void ntt_pass_kernel_body(const NttArgs& a, const Blk
       }
     }
     if (!ROWS) {  // last inverse pass: final factor (unless the inputs carry it), canonical output
-      if (a.scale) {
-        const uint2 sc = a.scale[p];
+      if (fold) {
+        // the last stage (one group, twiddle w = entry 1) with the factor c folded in:
+        // X + Y times c and (X - Y) times w c (scale_w), both below 4q, then canonical
+        const uint2 sc = a.scale[p], sw = a.scale_w[p];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) x[u] = csub(shoup_lazy(x[u], sc.x, sc.y, q), q);
+        for (int u = 0; u < 8; ++u) {
+          const uint32_t xs = x[u], ys = x[u + 8];
+          x[u] = csub(shoup_lazy(xs + ys, sc.x, sc.y, q), q);
+          x[u + 8] = csub(shoup_lazy(xs - ys + two_q, sw.x, sw.y, q), q);
+        }
       } else {
 #pragma unroll
         for (int u = 0; u < 16; ++u) x[u] = csub(x[u], q);
