@@ -179,6 +179,27 @@ __device__ __forceinline__ int cell_of(const CellSeg* seg, int ncells, Blk& bk) 
   return lo;
 }
 
+// A pointer read from memory (a stage-batched launch's table of cell arguments) is
+// generic to the compiler, and its loads become flat loads into vector registers even
+// where the address is wave-uniform.  Held as a global-memory pointer, its loads are
+// global ones, or scalar ones where uniform, as in a single launch.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+
+// One prime's twiddle table (Shoup pairs) through such a pointer.
+struct TwTab {
+  gptr<uint64_t> p;
+  __device__ __forceinline__ uint2 operator[](int i) const {
+    const uint64_t v = p[i];
+    return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+  }
+  // entries i and i + 1 in one 16-byte load (i even)
+  __device__ __forceinline__ v4i_t pair(int i) const { return *(gptr<v4i_t>)(p + i); }
+};
+__device__ __forceinline__ TwTab tw_table(const uint2* t, int p) {
+  return TwTab{(gptr<uint64_t>)t + (long long)p * kNMax};
+}
+
 // Low 32 bits of a b + c in one v_mad_u64_u32 (the compiler would otherwise narrow
 // the expression to a 32-bit multiply and an add).
 __device__ __forceinline__ uint32_t mad_lo(uint32_t a, uint32_t b, uint32_t c) {
@@ -480,7 +501,7 @@ struct RowTw {
 
 // MIR (inverse only): tw is the forward table and tw_mul the mirrored multiplier.
 template <int S, bool INV, bool MIR = false>
-__device__ __forceinline__ void load_strided_tw(RowTw<S>& w, const uint2* tw, int tw_mul) {
+__device__ __forceinline__ void load_strided_tw(RowTw<S>& w, TwTab tw, int tw_mul) {
 #pragma unroll
   for (int st = 0; st < 4; ++st) {
     const int m = INV ? (8 >> st) : (1 << st);
@@ -496,7 +517,7 @@ __device__ constexpr int fwd_ci(int t, int b0) { return 8 / t - 256 / (1 << S) +
 __device__ constexpr int inv_ci(int t, int b0) { return 16 - 16 / t + b0 / (2 * t); }
 
 template <int S, bool INV, bool MIR = false>
-__device__ __forceinline__ void load_contig_tw(RowTw<S>& w, const uint2* tw, int tw_mul, int j) {
+__device__ __forceinline__ void load_contig_tw(RowTw<S>& w, TwTab tw, int tw_mul, int j) {
   constexpr int n = 1 << S, T = n / 16;
 #pragma unroll
   for (int t = 1; t < T; t <<= 1) {
@@ -511,12 +532,12 @@ __device__ __forceinline__ void load_contig_tw(RowTw<S>& w, const uint2* tw, int
       // group j cnt + k is entry tw_mul h - 1 - j cnt - k: element cnt - 1 - k of the
       // ascending block from tw_mul h - (j + 1) cnt, two entries per 16-byte load (h and
       // cnt are even, so the block starts on a 16-byte boundary)
-      const uint4* blk = reinterpret_cast<const uint4*>(tw + tw_mul * (n / (2 * t)) - (j + 1) * cnt);
+      const int b = tw_mul * (n / (2 * t)) - (j + 1) * cnt;
 #pragma unroll
       for (int e = 0; e < cnt; e += 2) {
-        const uint4 v = blk[e / 2];
-        w.c[inv_ci(t, 2 * t * (cnt - 1 - e))] = make_uint2(v.x, v.y);
-        w.c[inv_ci(t, 2 * t * (cnt - 2 - e))] = make_uint2(v.z, v.w);
+        const v4i_t v = tw.pair(b + e);
+        w.c[inv_ci(t, 2 * t * (cnt - 1 - e))] = make_uint2((uint32_t)v[0], (uint32_t)v[1]);
+        w.c[inv_ci(t, 2 * t * (cnt - 2 - e))] = make_uint2((uint32_t)v[2], (uint32_t)v[3]);
       }
     }
   }
@@ -525,7 +546,7 @@ __device__ __forceinline__ void load_contig_tw(RowTw<S>& w, const uint2* tw, int
 // The inverse direction's twiddles, issued at once (before the products that precede
 // their first use).  MIR: from the forward table at the mirrored multiplier.
 template <int S, bool MIR = false>
-__device__ __forceinline__ void load_inv_tw(RowTw<S>& w, const uint2* itw, int tw_mul, int j) {
+__device__ __forceinline__ void load_inv_tw(RowTw<S>& w, TwTab itw, int tw_mul, int j) {
   load_contig_tw<S, true, MIR>(w, itw, tw_mul, j);
   load_strided_tw<S, true, MIR>(w, itw, tw_mul);
   __builtin_amdgcn_sched_barrier(0);
@@ -536,7 +557,7 @@ __device__ __forceinline__ void load_inv_tw(RowTw<S>& w, const uint2* itw, int t
 // the NP exchanges share one ordering point.  Leaves values in [0, 2q) at e = 16 j + u.
 // HOIST: twiddles loaded ahead of their stages (RowTw).
 template <int S, int NP, int NB, bool HOIST = false>
-__device__ __forceinline__ void fwd_rows(uint32_t (&x)[NP][16], uint32_t* const (&l)[NB], int j, const uint2* tw,
+__device__ __forceinline__ void fwd_rows(uint32_t (&x)[NP][16], uint32_t* const (&l)[NB], int j, TwTab tw,
                                          int tw_mul, uint32_t q, uint32_t two_q) {
   constexpr int n = 1 << S, T = n / 16;
   RowTw<S> w;
@@ -601,7 +622,7 @@ __device__ __forceinline__ void fwd_rows(uint32_t (&x)[NP][16], uint32_t* const 
 // caller has loaded the twiddles into pre (load_inv_tw, before the products).  MIR: tw
 // is the forward table and tw_mul the mirrored multiplier (mirror_tw).
 template <int S, int NP, int NB, bool HOIST = false, bool MIR = false>
-__device__ __forceinline__ void inv_rows(uint32_t (&x)[NP][16], uint32_t* const (&l)[NB], int j, const uint2* tw,
+__device__ __forceinline__ void inv_rows(uint32_t (&x)[NP][16], uint32_t* const (&l)[NB], int j, TwTab tw,
                                          int tw_mul, uint32_t q, uint32_t two_q, RowTw<S>& pre) {
   constexpr int n = 1 << S, T = n / 16;
 #pragma unroll
@@ -714,8 +735,7 @@ __device__ __forceinline__ void rows_fused_kernel_body(const RowsArgs& a, const 
   const bool valid = sg < nsub_total && c + cs < a.cnum;
   const PrimeC pc = a.pc[p];
   const uint32_t q = pc.q, two_q = pc.two_q, qneg = pc.qneg;
-  const uint2* tw = a.tw + (long long)p * kNMax;
-  const uint2* itw = a.itw + (long long)p * kNMax;
+  const TwTab tw = tw_table(a.tw, p), itw = tw_table(a.itw, p);
   // one sub-row per wave when CG = 4: the strided stages' twiddle index is then uniform
   const int tw_mul = CG > 1 ? __builtin_amdgcn_readfirstlane(nsub_total + sg) : nsub_total + sg;
   const long long KN = (long long)a.K * N;
