@@ -246,6 +246,12 @@ __device__ __forceinline__ uint2 mirror_tw(uint2 f) {
   opaque(v);
   return make_uint2(v, f.y);
 }
+// The same for a wave-uniform twiddle: the negation stays in scalar registers.
+__device__ __forceinline__ uint2 mirror_tw_s(uint2 f) {
+  uint32_t v = 0u - f.x;
+  asm volatile("" : "+s"(v));
+  return make_uint2(v, f.y);
+}
 
 // gs_bfly with the twiddle given as -v (the Shoup pair of v): (X - Y)(-v) = (Y - X) v,
 // the Shoup product of d = Y - X + 2q.
@@ -620,8 +626,9 @@ __device__ __forceinline__ void fwd_rows(uint32_t (&x)[NP][16], uint32_t* const 
 // First inverse n-point row stages of NP rows at once, values at e = 16 j + u in
 // [0, 2q); leaves values in [0, 2q) at e = u T + j for the caller to store.  HOIST: the
 // caller has loaded the twiddles into pre (load_inv_tw, before the products).  MIR: tw
-// is the forward table and tw_mul the mirrored multiplier (mirror_tw).
-template <int S, int NP, int NB, bool HOIST = false, bool MIR = false>
+// is the forward table and tw_mul the mirrored multiplier (mirror_tw).  SU: the strided
+// stages' twiddles are wave-uniform (mirror_tw_s).
+template <int S, int NP, int NB, bool HOIST = false, bool MIR = false, bool SU = false>
 __device__ __forceinline__ void inv_rows(uint32_t (&x)[NP][16], uint32_t* const (&l)[NB], int j, TwTab tw,
                                          int tw_mul, uint32_t q, uint32_t two_q, RowTw<S>& pre) {
   constexpr int n = 1 << S, T = n / 16;
@@ -667,7 +674,7 @@ __device__ __forceinline__ void inv_rows(uint32_t (&x)[NP][16], uint32_t* const 
 #pragma unroll
     for (int g = 0; g < h; ++g) {
       const uint2 wf = HOIST ? pre.s[h - 1 + g] : tw[MIR ? tw_mul * h - 1 - g : tw_mul * h + g];
-      const uint2 wg = MIR ? mirror_tw(wf) : wf;
+      const uint2 wg = MIR ? (SU ? mirror_tw_s(wf) : mirror_tw(wf)) : wf;
 #pragma unroll
       for (int r = 0; r < NP; ++r)
 #pragma unroll
@@ -738,6 +745,12 @@ __device__ __forceinline__ void rows_fused_kernel_body(const RowsArgs& a, const 
   const TwTab tw = tw_table(a.tw, p), itw = tw_table(a.itw, p);
   // one sub-row per wave when CG = 4: the strided stages' twiddle index is then uniform
   const int tw_mul = CG > 1 ? __builtin_amdgcn_readfirstlane(nsub_total + sg) : nsub_total + sg;
+  // The tensor and relinearization forms take their inverse twiddles from the forward
+  // table at the mirrored multiplier (mirror_tw; sg taken inside the transform on lanes
+  // past the last sub-row), so that a prime's inverse table is not read; the ring form
+  // reads the inverse table.
+  const int mi = 2 * nsub_total - min(sg, nsub_total - 1);
+  const int tw_mi = CG > 1 ? __builtin_amdgcn_readfirstlane(mi) : mi;
   const long long KN = (long long)a.K * N;
   // Rows are addressed through buffer resources from the workgroup's first row of
   // prime p (and its first ciphertext): a lane's 32-bit offset selects its sub-row and
@@ -765,7 +778,7 @@ __device__ __forceinline__ void rows_fused_kernel_body(const RowsArgs& a, const 
         x[r][u] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(lane + 4u * u * T), (int)(4 * r * KN), 0);
     fwd_rows<S, 4, NB, HOIST>(x, lb, j, tw, tw_mul, q, two_q);
     RowTw<S> wi;
-    if (HOIST) load_inv_tw<S>(wi, itw, tw_mul, j);  // in flight during the products
+    if (HOIST) load_inv_tw<S, true>(wi, tw, tw_mi, j);  // in flight during the products
     // Montgomery products (Eq. ntt_mul) carry a factor 2^-32, compensated in the inverse
     // transform's final factor.  d1 is formed directly (the Karatsuba identity of
     // Section 5.4 gives the same value; with full-rate multiplies the direct form issues
@@ -781,7 +794,7 @@ __device__ __forceinline__ void rows_fused_kernel_body(const RowsArgs& a, const 
       d[2][u] = redc_lazy(mad64(x[1][u], x[3][u], 0), q, qneg);
     }
     slot_sync();  // every lane has read the forward exchange before it is overwritten
-    inv_rows<S, 3, NB, HOIST>(d, lb, j, itw, tw_mul, q, two_q, wi);
+    inv_rows<S, 3, NB, HOIST, true, (CG > 1)>(d, lb, j, tw, tw_mi, q, two_q, wi);
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -802,10 +815,6 @@ __device__ __forceinline__ void rows_fused_kernel_body(const RowsArgs& a, const 
     for (int u = 0; u < 16; ++u) x[0][u] = __builtin_amdgcn_raw_buffer_load_b32(ri, (int)(lane + 4u * u * T), 0, 0);
     uint32_t* const lf[1] = {lb[0]};
     fwd_rows<S, 1, 1, HOIST>(x, lf, j, tw, tw_mul, q, two_q);
-    // the inverse twiddles from the forward table (the tensor form, VALU-bound, keeps
-    // the inverse table and saves the conversion; this one saves the table's traffic)
-    const int mi = 2 * nsub_total - min(sg, nsub_total - 1);  // sg inside the transform
-    const int tw_mi = CG > 1 ? __builtin_amdgcn_readfirstlane(mi) : mi;
     RowTw<S> wi;
     if (HOIST) load_inv_tw<S, true>(wi, tw, tw_mi, j);
     // the key rows are stored transposed (launch_row_transpose): thread j's element
@@ -826,7 +835,7 @@ __device__ __forceinline__ void rows_fused_kernel_body(const RowsArgs& a, const 
     }
     slot_sync();  // every lane has read the forward exchange before it is overwritten
     uint32_t* const li[1] = {lb[0]};
-    inv_rows<S, 2, 1, HOIST, true>(k, li, j, tw, tw_mi, q, two_q, wi);
+    inv_rows<S, 2, 1, HOIST, true, (CG > 1)>(k, li, j, tw, tw_mi, q, two_q, wi);
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
