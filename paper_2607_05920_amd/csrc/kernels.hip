@@ -246,7 +246,8 @@ __device__ __forceinline__ uint2 mirror_tw(uint2 f) {
   opaque(v);
   return make_uint2(v, f.y);
 }
-// The same for a wave-uniform twiddle: the negation stays in scalar registers.
+// The same for a wave-uniform twiddle: the negation stays in scalar registers (the
+// compiler rejects the constraint for a value it cannot keep there).
 __device__ __forceinline__ uint2 mirror_tw_s(uint2 f) {
   uint32_t v = 0u - f.x;
   asm volatile("" : "+s"(v));
@@ -550,11 +551,12 @@ __device__ __forceinline__ void load_contig_tw(RowTw<S>& w, TwTab tw, int tw_mul
 }
 
 // The inverse direction's twiddles, issued at once (before the products that precede
-// their first use).  MIR: from the forward table at the mirrored multiplier.
+// their first use): from the inverse table, or with MIR from the forward table at the
+// mirrored multiplier.
 template <int S, bool MIR = false>
-__device__ __forceinline__ void load_inv_tw(RowTw<S>& w, TwTab itw, int tw_mul, int j) {
-  load_contig_tw<S, true, MIR>(w, itw, tw_mul, j);
-  load_strided_tw<S, true, MIR>(w, itw, tw_mul);
+__device__ __forceinline__ void load_inv_tw(RowTw<S>& w, TwTab tab, int tw_mul, int j) {
+  load_contig_tw<S, true, MIR>(w, tab, tw_mul, j);
+  load_strided_tw<S, true, MIR>(w, tab, tw_mul);
   __builtin_amdgcn_sched_barrier(0);
 }
 
