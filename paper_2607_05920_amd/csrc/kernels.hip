@@ -272,12 +272,17 @@ template <int S, bool ROWS>
 constexpr int ntt_pass_threads() { return ROWS ? 256 : (S >= 8 ? 1024 : (S == 7 ? 512 : 256)); }
 
 // BLK: threads per workgroup (the autotuner may take fewer columns per workgroup than
-// ntt_pass_threads gives).
-template <int S, bool INV, bool ROWS, int BLK>
+// ntt_pass_threads gives).  CG (row passes of 256 points over transforms one group
+// apart): the four 16-lane slots of a wave take one block of four consecutive
+// transforms of a prime, so that its twiddles are wave-uniform (scalar loads) and
+// read once for four transforms.
+template <int S, bool INV, bool ROWS, int BLK, int CG = 1>
 __device__ __forceinline__ void ntt_pass_kernel_body(const NttArgs& a, const Blk bk) {
   constexpr int n = 1 << S;
   constexpr int T = n / 16;
-  constexpr int NSUB = BLK / T;
+  constexpr int NSUB = BLK / T;  // slots (LDS rows) per workgroup
+  static_assert(CG == 1 || (ROWS && CG * T == 64), "four transforms fill one wave");
+  constexpr int RPW = NSUB / CG;  // blocks or columns per workgroup
   // Row stride in LDS, chosen so that both access patterns are free of bank
   // conflicts (element e sits at s * SS + e + e / 16).
   constexpr int SS = ((n + n / 16 + 1 + 31) / 32) * 32 + (ROWS ? T : (NSUB >= 32 ? 1 : 2));
@@ -286,6 +291,8 @@ __device__ __forceinline__ void ntt_pass_kernel_body(const NttArgs& a, const Blk
   const int tid = threadIdx.x;
   const int s = ROWS ? tid / T : tid % NSUB;
   const int j = ROWS ? tid % T : tid / NSUB;
+  const int cs = CG > 1 ? s % CG : 0;  // transform within the block of CG
+  const int sl = CG > 1 ? s / CG : s;  // block or column within the workgroup
 
   const int N = 1 << a.logN;
   const int nsub_total = N / n;  // blocks (ROWS) or columns (COLS)
@@ -295,20 +302,23 @@ __device__ __forceinline__ void ntt_pass_kernel_body(const NttArgs& a, const Blk
   // pass reads only the first n entries of each table; the forward one goes through
   // the transforms in descending order instead, all its primes for each, so that it
   // starts on the residues the lift wrote last (the last-level cache still holds them).
-  const int nwg = (nsub_total + NSUB - 1) / NSUB;  // workgroups per transform
-  const int npp = a.ntr / a.K;                     // transforms per prime
-  const int kx = (a.K + 7) >> 3;                   // primes per XCD (the largest share)
+  const int nwg = (nsub_total + RPW - 1) / RPW;  // workgroups per transform (block)
+  const int npp = a.ntr / a.K;                    // transforms per prime
+  const int ncg = (npp + CG - 1) / CG;            // blocks of CG transforms per prime
+  const int kx = (a.K + 7) >> 3;                  // primes per XCD (the largest share)
   const int w = bk.x, xcd = w & 7, l = w >> 3;
   constexpr bool BY_TRANSFORM = !INV && !ROWS;
-  const int p = (BY_TRANSFORM ? (l / nwg) % kx : l / (npp * nwg)) * 8 + xcd;
+  const int p = (BY_TRANSFORM ? (l / nwg) % kx : l / (ncg * nwg)) * 8 + xcd;
   if (p >= a.K) return;  // whole workgroup exits (primes not a multiple of 8)
-  // transform index among those of prime p
-  const int jp = BY_TRANSFORM ? npp - 1 - l / (kx * nwg) : (l / nwg) % npp;
-  const int sg = (l % nwg) * NSUB + s;
-  const bool valid = sg < nsub_total;
-  // transform jp of prime p: polynomial i of group grp, row r = i K + p
+  // transform (block) index among those of prime p
+  const int jg = BY_TRANSFORM ? ncg - 1 - l / (kx * nwg) : (l / nwg) % ncg;
+  const int sg = (l % nwg) * RPW + sl;
+  const bool valid = sg < nsub_total && (CG == 1 || jg * CG + cs < npp);
+  // transform jg CG of prime p (the first of the block): polynomial i of group grp,
+  // row r = i K + p; with CG > 1 the block's transforms are one group apart
   const int pk = a.per_group / a.K;  // polynomials per group
-  const int grp = jp / pk, r = (jp % pk) * a.K + p;
+  const int jb = jg * CG;
+  const int grp = jb / pk, r = (jb % pk) * a.K + p;
   uint32_t* base = a.data + (long long)grp * a.group_stride + (long long)r * N;
   const PrimeC pc = a.pc[p];
   const uint32_t q = pc.q, two_q = pc.two_q;
@@ -321,13 +331,14 @@ __device__ __forceinline__ void ntt_pass_kernel_body(const NttArgs& a, const Blk
   // scalar offset, and lanes past the last block or column take an offset beyond the
   // buffer (their loads return zero and their stores are dropped).
   const uint32_t es = ROWS ? 4u : 4u * (uint32_t)nsub_total;  // bytes from element e to e + 1
-  const __amdgpu_buffer_rsrc_t rb = row_buffer(wave_uniform(base), 4u * (uint32_t)N);
-  const uint32_t sub = 4u * (uint32_t)(ROWS ? sg * n : sg);
+  const __amdgpu_buffer_rsrc_t rb =
+      row_buffer(wave_uniform(base), 4u * (uint32_t)((CG - 1) * a.group_stride + N));
+  const uint32_t sub = 4u * (uint32_t)(ROWS ? sg * n + cs * a.group_stride : sg);
   const uint32_t o_str = valid ? sub + (uint32_t)j * es : 0x7FFFFF00u;        // e = u T + j
   const uint32_t o_con = valid ? sub + 16u * (uint32_t)j * es : 0x7FFFFF00u;  // e = 16 j + u
   // Twiddle index of local stage m (groups) and local group i:
   // COLS -> m + i; ROWS -> (N / n + sg) m + i.
-  const int tw_mul = ROWS ? (nsub_total + sg) : 1;
+  const int tw_mul = CG > 1 ? __builtin_amdgcn_readfirstlane(nsub_total + sg) : (ROWS ? (nsub_total + sg) : 1);
   // a column pass of 64 columns or more per workgroup has one j per wave: its contiguous
   // stages' twiddles are then wave-uniform (scalar loads)
   const int jt = (!ROWS && NSUB % 64 == 0) ? __builtin_amdgcn_readfirstlane(j) : j;
@@ -455,20 +466,20 @@ __device__ __forceinline__ void ntt_pass_kernel_body(const NttArgs& a, const Blk
   }
 }
 
-template <int S, bool INV, bool ROWS, int BLK = ntt_pass_threads<S, ROWS>()>
+template <int S, bool INV, bool ROWS, int BLK = ntt_pass_threads<S, ROWS>(), int CG = 1>
 __global__ __launch_bounds__(BLK) void ntt_pass_kernel(NttArgs a) {
-  ntt_pass_kernel_body<S, INV, ROWS, BLK>(a, own_blk());
+  ntt_pass_kernel_body<S, INV, ROWS, BLK, CG>(a, own_blk());
 }
 
 // The same over the cells of a stage-batched plan: one launch, each workgroup in its
 // cell's segment (cell_of) with that cell's arguments.
-template <int S, bool INV, bool ROWS, int BLK>
+template <int S, bool INV, bool ROWS, int BLK, int CG = 1>
 __global__ __launch_bounds__(BLK) void ntt_pass_kernel_multi(
     const NttArgs* __restrict__ cells, const CellSeg* __restrict__ seg, int ncells) {
   Blk bk;
   const int c = cell_of(seg, ncells, bk);
   if (c < 0) return;
-  ntt_pass_kernel_body<S, INV, ROWS, BLK>(cells[c], bk);
+  ntt_pass_kernel_body<S, INV, ROWS, BLK, CG>(cells[c], bk);
 }
 
 // ---------------------------------------------------------------------------- fused row pass
@@ -931,20 +942,21 @@ static hipError_t rows_fused_s(int S, const RowsArgs& a, hipStream_t st) {
   }
 }
 
-template <int S, bool INV, bool ROWS, int BLK = ntt_pass_threads<S, ROWS>()>
+template <int S, bool INV, bool ROWS, int BLK = ntt_pass_threads<S, ROWS>(), int CG = 1>
 static hipError_t ntt_pass(const NttArgs& a, int ntr, hipStream_t st) {
   constexpr int n = 1 << S;
-  constexpr int NSUB = BLK / (n / 16);
+  constexpr int RPW = BLK / (n / 16) / CG;
   const int nsub_total = (1 << a.logN) / n;
-  const int nwg = (nsub_total + NSUB - 1) / NSUB;
+  const int nwg = (nsub_total + RPW - 1) / RPW;
   const int kx = (a.K + 7) / 8;  // primes per XCD (the largest share)
-  dim3 grid(8 * kx * (ntr / a.K) * nwg);
+  const int ncg = (ntr / a.K + CG - 1) / CG;
+  dim3 grid(8 * kx * ncg * nwg);
   // algorithmic work: (N / 2) S butterflies per transform, one constant product each
   // algorithmic HBM bytes: every element of every transform read and written once
   Bracket br(INV ? (ROWS ? KID_NTT_INV_ROWS : KID_NTT_INV_COLS) : (ROWS ? KID_NTT_FWD_ROWS : KID_NTT_FWD_COLS), st,
              8.0 * ntr * (double)(1 << a.logN));
-  const hipError_t e = emit((const void*)ntt_pass_kernel<S, INV, ROWS, BLK>,
-                             (const void*)ntt_pass_kernel_multi<S, INV, ROWS, BLK>, grid, dim3(BLK), 0, st, a);
+  const hipError_t e = emit((const void*)ntt_pass_kernel<S, INV, ROWS, BLK, CG>,
+                             (const void*)ntt_pass_kernel_multi<S, INV, ROWS, BLK, CG>, grid, dim3(BLK), 0, st, a);
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }
@@ -953,6 +965,13 @@ static hipError_t ntt_pass(const NttArgs& a, int ntr, hipStream_t st) {
 // (16 or 32 columns of 2^8 points, 32 of 2^7) where it is smaller than the default.
 template <bool INV, bool ROWS>
 static hipError_t ntt_pass_s(int S, const NttArgs& a, int ntr, hipStream_t st, int cols_threads = 0) {
+  // row passes of 256 points over blocks of four transforms one group apart (one
+  // polynomial per group), where at most one slot in eight idles and the block's span
+  // stays below the buffer's out-of-range offset
+  const int npp = ntr / a.K, ncg4 = (npp + 3) / 4;
+  if (ROWS && S == 8 && a.per_group == a.K && npp >= 4 && 8 * (4 * ncg4 - npp) <= 4 * ncg4 &&
+      (3 * a.group_stride + (1LL << a.logN)) * 4 < 0x70000000LL)
+    return ntt_pass<8, INV, true, 256, 4>(a, ntr, st);
   if (!ROWS && S == 8 && cols_threads == 256) return ntt_pass<8, INV, false, 256>(a, ntr, st);
   if (!ROWS && S == 8 && cols_threads == 512) return ntt_pass<8, INV, false, 512>(a, ntr, st);
   if (!ROWS && S == 7 && cols_threads == 256) return ntt_pass<7, INV, false, 256>(a, ntr, st);

@@ -96,6 +96,37 @@ def test_ntt_forward_inverse(ctx, logN):
     assert np.array_equal(host(t, (nprimes, N)), data)
 
 
+@pytest.mark.parametrize("count,natural", [(4, False), (7, False), (8, True)])
+def test_ntt_several_per_prime_logn16(ctx, count, natural):
+    """Transforms of `count` polynomials per prime at N = 2^16 (the row pass then takes
+    four transforms of a prime per wave; 7 leaves one slot of the last block idle):
+    every coefficient against the same transforms one at a time, two against the
+    oracle's transform, and the inverse back to the input."""
+    say(f"ntt logN=16 count={count} natural={natural}")
+    logN, nprimes, prime0 = 16, 2, 5
+    N = 1 << logN
+    rng = np.random.default_rng(1600 + count)
+    data = np.zeros((count, nprimes, N), dtype=np.uint32)
+    for c in range(count):
+        for p in range(nprimes):
+            data[c, p] = rng.integers(0, ctx.prime_info(prime0 + p)[0], N, dtype=np.uint64)
+    t = dev(data)
+    ctx.ntt(logN, nprimes, t, count=count, bitrev=not natural, prime0=prime0)
+    fwd = host(t, (count, nprimes, N)).copy()
+    for c in range(count):
+        one = dev(data[c])
+        ctx.ntt(logN, nprimes, one, count=1, bitrev=not natural, prime0=prime0)
+        assert np.array_equal(host(one, (nprimes, N)), fwd[c]), f"transform {c}"
+    perm = [_bitrev(i, logN) for i in range(N)]
+    for c, p in [(0, 0), (count - 1, 1)]:
+        q, psi_max = ctx.prime_info(prime0 + p)
+        want = ontt.ntt_fast([int(v) for v in data[c, p]], q, psi_max)
+        got = [int(fwd[c, p, i if natural else perm[i]]) for i in range(N)]
+        check(got, want, f"ntt transform {c} prime {prime0 + p}")
+    ctx.ntt(logN, nprimes, t, count=count, inverse=True, bitrev=not natural, prime0=prime0)
+    assert np.array_equal(host(t, (count, nprimes, N)), data)
+
+
 def test_ring_mul_cfg1_bit_exact(ctx):
     """Bare ring multiply, N = 2^10, Q = 2^120, inputs uniform in [0, Q) from seed 1000."""
     say("ring_mul cfg1")
